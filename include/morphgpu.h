@@ -1,0 +1,164 @@
+/*
+ * morphgpu.h -- C ABI of libmorphgpu.so, compression-enabled columnar operators
+ * for AMD Instinct MI355X (gfx950).
+ *
+ * Model (MorphStore, Damme et al., PVLDB 13, 2020):
+ *   - every base column and every intermediate is a sequence of unsigned integers
+ *     held in exactly one format, possibly uncompressed (section 3.1);
+ *   - operators take columns and return columns (headless BATs, section 3.1);
+ *   - each operator decompresses its inputs on the fly and recompresses its output
+ *     into a format chosen per intermediate, independently of the input formats
+ *     ("on-the-fly de/re-compression", section 3.2);
+ *   - a plan must be consistent and its final results are uncompressed (section 3.3).
+ *
+ * Conventions for every call:
+ *   - Pointers named dev_* are device pointers (HBM of the current HIP device);
+ *     host_* are host pointers.  `stream` is a hipStream_t (NULL = default stream).
+ *   - Inputs are borrowed and never modified.  Every ms_column** output is a new
+ *     column owned by the caller and released with ms_column_free.  On any error
+ *     *out is set to NULL and nothing is leaked.
+ *   - Calls are asynchronous on `stream`; only ms_column_info, ms_column_read_section,
+ *     ms_column_shrink, ms_sync and the selector's save/load/get calls synchronise.
+ *   - Element counts of data-dependent outputs live on the device.  Errors that
+ *     depend on data (a position out of range, an unsorted intersect input, a group
+ *     id >= G, a value too wide for a fixed static-BP width) raise a sticky device
+ *     flag that the next ms_sync returns and clears.  Argument errors are returned
+ *     at once.  ms_last_error() gives a message for the last failing call of the
+ *     calling thread.
+ *   - Values and positions are uint32 (columns hold fewer than 2^32 values); sums
+ *     are uint64 and wrap modulo 2^64.
+ *
+ * Formats (block size bs; a column of n values keeps its first floor(n/bs)*bs
+ * values compressed and the n mod bs rest uncompressed, section 4.1):
+ *   MS_UNCOMPR       bs 1    the values
+ *   MS_STATIC_BP     bs 32   all values packed at one width b (section 4.1's static BP)
+ *   MS_DYN_BP        bs 512  per-block width w_k = bw(OR of the block) (binary packing,
+ *                            section 2.1, with SIMD-BP512's block size)
+ *   MS_DELTA_DYN_BP  bs 512  DELTA inside each block (base = first value, modular
+ *                            differences), then per-block packing (a section 2.1 cascade)
+ *   MS_FOR_DYN_BP    bs 512  FOR with the block minimum as reference, then packing
+ *   MS_RLE           runs as (value, start) pairs (section 2.1)
+ * Packing is least-significant-bit first into little-endian 32-bit words.
+ * Footprint = widths 1 B/block + directory 4 B/block + bases/references 4 B/block +
+ * payload + 4 B per remainder value; RLE 8 B per run; uncompressed 4 B per value.
+ */
+#ifndef MORPHGPU_H
+#define MORPHGPU_H
+#include <stddef.h>
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+typedef enum {
+  MS_UNCOMPR = 0, MS_STATIC_BP = 1, MS_DYN_BP = 2, MS_DELTA_DYN_BP = 3, MS_FOR_DYN_BP = 4, MS_RLE = 5
+} ms_kind;
+#define MS_NUM_KINDS 6
+#define MS_BW_AUTO 0xFFFFFFFFu
+
+/* Output format of an operator: kind plus, for MS_STATIC_BP, the width (0..32) or
+ * MS_BW_AUTO for the narrowest width that holds every compressed value. */
+typedef struct { uint32_t kind; uint32_t bit_width; } ms_format;
+
+/* Unsigned comparisons of select (section 5.1's selection; BETWEEN is c0 <= v <= c1). */
+typedef enum { MS_EQ = 0, MS_NE, MS_LT, MS_LE, MS_GT, MS_GE, MS_BETWEEN } ms_cmp;
+
+typedef enum {
+  MS_OK = 0, MS_ERR_INVALID_ARG = 1, MS_ERR_UNSUPPORTED = 2, MS_ERR_VALUE_TOO_WIDE = 3,
+  MS_ERR_OUT_OF_RANGE = 4, MS_ERR_NOT_SORTED = 5, MS_ERR_LENGTH_MISMATCH = 6, MS_ERR_OOM = 7,
+  MS_ERR_HIP = 8, MS_ERR_NOT_INITIALIZED = 9
+} ms_status;
+
+typedef struct ms_column ms_column;
+
+/* Device memory provider.  alloc returns device memory usable in stream order on
+ * `stream` (NULL on failure); free releases it in stream order.  Passing NULL
+ * callbacks to ms_init selects HIP's stream-ordered pool (hipMallocAsync). */
+typedef void *(*ms_alloc_fn)(uint64_t bytes, void *stream, void *ctx);
+typedef void (*ms_free_fn)(void *ptr, uint64_t bytes, void *stream, void *ctx);
+
+/* Initialise the library on the current device.  Must be called once per process
+ * before any other call; may be called again to swap the allocator. */
+ms_status ms_init(ms_alloc_fn alloc, ms_free_fn free_fn, void *ctx);
+const char *ms_last_error(void);
+
+/* Column construction.  ms_column_encode compresses n device values into fmt
+ * (static BP with an explicit width raises MS_ERR_VALUE_TOO_WIDE through ms_sync
+ * when a main-part value needs more bits).  The result has the canonical layout:
+ * blocks in order, directory offsets = running sums of 16*w_k words. */
+ms_status ms_column_encode(const uint32_t *dev_vals, uint64_t n, ms_format fmt, void *stream, ms_column **out);
+/* Wrap n uncompressed device values without copying; the memory stays owned by the
+ * caller and must outlive the column.  dev_vals must be 16-byte aligned. */
+ms_status ms_column_wrap_uncompr(const uint32_t *dev_vals, uint64_t n, void *stream, ms_column **out);
+/* Decode into dev_out (room for the column's element count). */
+ms_status ms_column_decode(const ms_column *col, uint32_t *dev_out, void *stream);
+ms_status ms_column_free(ms_column *col);
+
+typedef struct {
+  uint64_t n;               /* element count */
+  uint32_t kind;
+  uint32_t bit_width;       /* static BP width, else 0 */
+  uint64_t n_main, n_rem;   /* compressed main part and uncompressed remainder */
+  uint64_t n_blocks;        /* 512-blocks of the DynBP family */
+  uint64_t runs;            /* RLE runs */
+  uint64_t payload_words;   /* packed words in use */
+  uint64_t payload_extent;  /* words of the payload region a reader may address */
+  uint64_t footprint;       /* bytes by the section rule above */
+  uint64_t capacity_bytes;  /* device bytes held by the column */
+  uint32_t or_all;          /* OR of all values */
+  uint32_t sorted;          /* 1 when known strictly increasing (position lists) */
+} ms_column_info;
+/* Synchronises `stream`, then reports the column's layout and footprint. */
+ms_status ms_column_info_get(const ms_column *col, void *stream, ms_column_info *out);
+
+/* Sections for inspection and parity checks; copied to host after a sync. */
+typedef enum {
+  MS_SEC_WIDTHS = 0, MS_SEC_OFFSETS = 1, MS_SEC_BASES = 2, MS_SEC_PAYLOAD = 3, MS_SEC_REM = 4,
+  MS_SEC_RVALUES = 5, MS_SEC_RSTARTS = 6
+} ms_section;
+/* Copies min(bytes, section size) bytes of `sec` to host_dst; *copied gets the count.
+ * Section sizes: widths n_blocks B; offsets and bases 4*n_blocks B; payload
+ * 4*payload_extent B; rem 4*n_rem B; rvalues and rstarts 4*runs B. */
+ms_status ms_column_read_section(const ms_column *col, ms_section sec, void *host_dst, uint64_t bytes,
+                                 void *stream, uint64_t *copied);
+/* Rewrite the column into an exactly sized buffer with the canonical layout (DynBP
+ * payload blocks contiguous and in order).  Synchronises `stream`. */
+ms_status ms_column_shrink(ms_column *col, void *stream);
+
+/* Format change, section 3.2 "direct morphing": out = encode_fmt(decode(in)). */
+ms_status ms_morph(const ms_column *in, ms_format fmt, void *stream, ms_column **out);
+
+/* select (section 5.1): ascending positions i with cmp(v_i, c0[, c1]), as a column in fmt. */
+ms_status ms_select(const ms_column *in, ms_cmp cmp, uint32_t c0, uint32_t c1, ms_format fmt, void *stream,
+                    ms_column **out);
+/* Bitmap with bit p set for every position p (domain bits, 32-bit words, bit p in word
+ * p/32 at position p%32).  dev_bitmap must hold ceil(domain/32) words; it is fully
+ * written.  A position >= domain raises MS_ERR_OUT_OF_RANGE. */
+ms_status ms_bitmap_from_positions(const ms_column *pos, uint64_t domain, uint32_t *dev_bitmap, void *stream);
+/* semi-join of a foreign-key column against a dimension bitmap (the star plans of
+ * section 5.2): ascending i with keys_i < domain and bit keys_i set. */
+ms_status ms_semijoin(const ms_column *keys, const uint32_t *dev_bitmap, uint64_t domain, ms_format fmt,
+                      void *stream, ms_column **out);
+/* project (section 4.2): out_j = data[pos_j] in pos's order; a position >= |data|
+ * raises MS_ERR_OUT_OF_RANGE (that element reads 0). */
+ms_status ms_project(const ms_column *data, const ms_column *pos, ms_format fmt, void *stream, ms_column **out);
+/* intersect of two strictly increasing position lists; unsorted input raises
+ * MS_ERR_NOT_SORTED.  `domain` bounds every position (positions < domain). */
+ms_status ms_intersect(const ms_column *a, const ms_column *b, uint64_t domain, ms_format fmt, void *stream,
+                       ms_column **out);
+/* sum (section 5.1): *dev_result = sum of all values mod 2^64. */
+ms_status ms_sum(const ms_column *in, uint64_t *dev_result, void *stream);
+/* group-based aggregation (section 4.2): dev_out[g] = sum of vals_i with groups_i = g,
+ * for g < G (empty groups 0; result uncompressed).  Unequal lengths return
+ * MS_ERR_LENGTH_MISMATCH when both are known on the host, else raise it on the device. */
+ms_status ms_group_sum(const ms_column *groups, const ms_column *vals, uint32_t G, uint64_t *dev_out,
+                       void *stream);
+
+/* Synchronise `stream` and return (then clear) the first data-dependent error. */
+ms_status ms_sync(void *stream);
+
+#ifdef __cplusplus
+}
+#endif
+#endif

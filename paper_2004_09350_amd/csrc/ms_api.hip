@@ -1,0 +1,796 @@
+// ms_api.hip -- the C ABI of libmorphgpu.so: columns, allocation, operator entry points.
+#include <hip/hip_runtime.h>
+
+#include <algorithm>
+#include <atomic>
+#include <cstdio>
+#include <cstring>
+#include <string>
+#include <vector>
+
+#include "../../include/morphgpu.h"
+#include "ms_kernels.h"
+
+using namespace ms;
+
+struct ms_column {
+  uint32_t kind;
+  uint32_t width;          // static BP: explicit width, or the widest possible (32) for auto
+  uint64_t n_cap;          // capacity in values
+  uint64_t n_host;         // element count known on the host, or UINT64_MAX
+  uint64_t nb_cap;         // DynBP-family block capacity
+  uint64_t payload_cap;    // payload words the buffer holds (without slack)
+  void *buf;               // owned device buffer
+  uint64_t buf_bytes;
+  void *stream;            // stream the buffer was allocated on
+  ColView v;
+  uint32_t sorted;
+};
+
+namespace {
+
+constexpr uint64_t kUnknown = ~0ull;
+
+ms_alloc_fn g_alloc = nullptr;
+ms_free_fn g_free = nullptr;
+void *g_ctx = nullptr;
+bool g_init = false;
+int g_cus = 256;
+std::atomic<uint32_t> g_slot{0};
+thread_local std::string t_err;
+
+ms_status fail(ms_status st, const std::string &msg) {
+  t_err = msg;
+  return st;
+}
+
+ms_status hip_fail(hipError_t e, const char *what) {
+  return fail(MS_ERR_HIP, std::string(what) + ": " + hipGetErrorString(e));
+}
+
+void *dev_alloc(uint64_t bytes, void *stream) {
+  if (bytes == 0) bytes = 256;
+  if (g_alloc) return g_alloc(bytes, stream, g_ctx);
+  void *p = nullptr;
+  if (hipMallocAsync(&p, bytes, reinterpret_cast<hipStream_t>(stream)) != hipSuccess) return nullptr;
+  return p;
+}
+
+void dev_free(void *p, uint64_t bytes, void *stream) {
+  if (!p) return;
+  if (bytes == 0) bytes = 256;
+  if (g_free)
+    g_free(p, bytes, stream, g_ctx);
+  else
+    (void)hipFreeAsync(p, reinterpret_cast<hipStream_t>(stream));
+}
+
+unsigned next_slot() { return g_slot.fetch_add(1) % kRingSlots; }
+
+// Stream-ordered scratch released at scope exit.
+struct Scratch {
+  void *stream;
+  std::vector<std::pair<void *, uint64_t>> blocks;
+  bool ok = true;
+  explicit Scratch(void *s) : stream(s) {}
+  template <class T>
+  T *get(uint64_t count) {
+    uint64_t bytes = std::max<uint64_t>(count * sizeof(T), 256);
+    void *p = dev_alloc(bytes, stream);
+    if (!p) {
+      ok = false;
+      return nullptr;
+    }
+    blocks.push_back({p, bytes});
+    return reinterpret_cast<T *>(p);
+  }
+  ~Scratch() {
+    for (auto &b : blocks) dev_free(b.first, b.second, stream);
+  }
+};
+
+uint64_t align256(uint64_t x) { return (x + 255) & ~255ull; }
+
+unsigned grid_for(uint64_t chunks) {
+  uint64_t max_wg = (uint64_t)g_cus * 8;
+  uint64_t g = (chunks + 3) / 4;
+  if (g < 1) g = 1;
+  if (g > max_wg) g = max_wg;
+  return (unsigned)g;
+}
+
+uint64_t chunks_of(uint64_t n) { return (n + kBlk - 1) / kBlk; }
+
+bool valid_kind(uint32_t k) { return k <= MS_RLE; }
+
+// Allocate a column of `kind` with room for n_cap values (payload_words: explicit
+// payload size for canonical layouts, or kUnknown for the worst case).
+ms_status alloc_column(uint32_t kind, uint32_t width, uint64_t n_cap, uint64_t nb_exact, uint64_t payload_words,
+                       void *stream, ms_column **out) {
+  *out = nullptr;
+  ms_column *c = new ms_column();
+  c->kind = kind;
+  c->width = width;
+  c->n_cap = n_cap;
+  c->n_host = kUnknown;
+  c->stream = stream;
+  c->sorted = 0;
+  std::memset(&c->v, 0, sizeof(c->v));
+  c->v.kind = kind;
+  c->v.width = width;
+  c->v.n_cap = n_cap;
+  uint64_t off = align256(sizeof(ColHdr));
+  uint64_t o_widths = 0, o_offsets = 0, o_bases = 0, o_rem = 0, o_payload = 0, o_rv = 0, o_rs = 0;
+  switch (kind) {
+    case MS_UNCOMPR:
+      o_payload = off;
+      c->payload_cap = n_cap;
+      off += align256(4 * n_cap + 64);
+      break;
+    case MS_STATIC_BP: {
+      o_rem = off;
+      off += align256(4 * 32);
+      o_payload = off;
+      uint64_t w = (width > 32) ? 32 : width;
+      c->payload_cap = (payload_words != kUnknown) ? payload_words : (n_cap * w + 31) / 32;
+      off += align256(4 * (c->payload_cap + kPayloadSlackWords));
+      break;
+    }
+    case MS_DYN_BP:
+    case MS_DELTA_DYN_BP:
+    case MS_FOR_DYN_BP: {
+      uint64_t nb = (nb_exact != kUnknown) ? nb_exact : n_cap / kBlk;
+      c->nb_cap = nb;
+      o_widths = off;
+      off += align256(nb + 16);
+      o_offsets = off;
+      off += align256(4 * nb + 16);
+      o_bases = off;
+      off += align256(4 * nb + 16);
+      o_rem = off;
+      off += align256(4 * kBlk);
+      o_payload = off;
+      c->payload_cap = (payload_words != kUnknown) ? payload_words : nb * kBlk;
+      off += align256(4 * (c->payload_cap + kPayloadSlackWords));
+      break;
+    }
+    case MS_RLE:
+      o_rv = off;
+      off += align256(4 * n_cap + 16);
+      o_rs = off;
+      off += align256(4 * n_cap + 16);
+      c->payload_cap = 0;
+      break;
+    default: delete c; return fail(MS_ERR_INVALID_ARG, "bad format kind");
+  }
+  c->v.payload_cap = c->payload_cap;
+  c->buf_bytes = off;
+  c->buf = dev_alloc(off, stream);
+  if (!c->buf) {
+    delete c;
+    return fail(MS_ERR_OOM, "device allocation failed");
+  }
+  char *b = reinterpret_cast<char *>(c->buf);
+  c->v.hdr = reinterpret_cast<ColHdr *>(b);
+  if (o_widths) c->v.widths = reinterpret_cast<unsigned char *>(b + o_widths);
+  if (o_offsets) c->v.offsets = reinterpret_cast<unsigned *>(b + o_offsets);
+  if (o_bases) c->v.bases = reinterpret_cast<unsigned *>(b + o_bases);
+  if (o_rem) c->v.rem = reinterpret_cast<unsigned *>(b + o_rem);
+  if (o_payload) c->v.payload = reinterpret_cast<unsigned *>(b + o_payload);
+  if (o_rv) c->v.rvalues = reinterpret_cast<unsigned *>(b + o_rv);
+  if (o_rs) c->v.rstarts = reinterpret_cast<unsigned *>(b + o_rs);
+  *out = c;
+  return MS_OK;
+}
+
+void free_column(ms_column *c) {
+  if (!c) return;
+  dev_free(c->buf, c->buf_bytes, c->stream);
+  delete c;
+}
+
+ms_status check_fmt(ms_format f) {
+  if (!valid_kind(f.kind)) return fail(MS_ERR_INVALID_ARG, "unknown output format");
+  if (f.kind == MS_STATIC_BP && f.bit_width != MS_BW_AUTO && f.bit_width > 32)
+    return fail(MS_ERR_INVALID_ARG, "static BP width must be 0..32 or auto");
+  return MS_OK;
+}
+
+ms_status check_init() { return g_init ? MS_OK : fail(MS_ERR_NOT_INITIALIZED, "ms_init not called"); }
+
+// Output column for a producer of at most n_cap values.
+ms_status make_output(ms_format fmt, uint64_t n_cap, void *stream, ms_column **out, unsigned &auto_w) {
+  auto_w = (fmt.kind == MS_STATIC_BP && fmt.bit_width == MS_BW_AUTO) ? 1u : 0u;
+  uint32_t w = (fmt.kind == MS_STATIC_BP) ? (auto_w ? 32u : fmt.bit_width) : 0u;
+  ms_status st = alloc_column(fmt.kind, w, n_cap, kUnknown, kUnknown, stream, out);
+  if (st != MS_OK) return st;
+  (*out)->v.width = w;
+  return MS_OK;
+}
+
+ms_status launched(hipError_t e, ms_column **out) {
+  if (e != hipSuccess) {
+    if (out && *out) {
+      free_column(*out);
+      *out = nullptr;
+    }
+    return hip_fail(e, "kernel launch");
+  }
+  return MS_OK;
+}
+
+struct HostHdr {
+  ColHdr h;
+};
+
+ms_status read_hdr(const ms_column *c, void *stream, ColHdr &h) {
+  hipError_t e = hipStreamSynchronize(reinterpret_cast<hipStream_t>(stream));
+  if (e != hipSuccess) return hip_fail(e, "stream sync");
+  e = hipMemcpy(&h, c->v.hdr, sizeof(ColHdr), hipMemcpyDeviceToHost);
+  if (e != hipSuccess) return hip_fail(e, "header copy");
+  return MS_OK;
+}
+
+// Two-phase compaction shared by select, semi-join and intersect.
+ms_status compaction(const ms_column *in, const PredArgs &pa_in, bool emit_values, bool check_sorted, ms_format fmt,
+                     void *stream, ms_column **out) {
+  *out = nullptr;
+  ms_status st = check_fmt(fmt);
+  if (st != MS_OK) return st;
+  const uint64_t n_cap = in->n_host != kUnknown ? in->n_host : in->n_cap;
+  const uint64_t C = chunks_of(n_cap);
+  const unsigned G = grid_for(C);
+  unsigned auto_w = 0;
+  st = make_output(fmt, n_cap, stream, out, auto_w);
+  if (st != MS_OK) return st;
+  Scratch sc(stream);
+  const bool blocky = fmt.kind != MS_UNCOMPR && fmt.kind != MS_RLE;
+  PredArgs pa = pa_in;
+  pa.in = in->v;
+  pa.bitmask = sc.get<unsigned char>(C * 64 + 64);
+  pa.seg_count = sc.get<unsigned>(G);
+  pa.seg_or = sc.get<unsigned>(G);
+  pa.chunk_first = check_sorted ? sc.get<unsigned>(C + 1) : nullptr;
+  pa.chunk_last = check_sorted ? sc.get<unsigned>(C + 1) : nullptr;
+  pa.n_counters = blocky ? n_cap / kBlk + 2 : 0;
+  pa.counters = blocky ? sc.get<unsigned>(pa.n_counters) : nullptr;
+  EmitArgs ea;
+  std::memset(&ea, 0, sizeof(ea));
+  ea.in = in->v;
+  ea.out = (*out)->v;
+  ea.auto_w = auto_w;
+  ea.emit_values = emit_values ? 1u : 0u;
+  ea.check_sorted = check_sorted ? 1u : 0u;
+  ea.bitmask = pa.bitmask;
+  ea.seg_count = pa.seg_count;
+  ea.seg_or = pa.seg_or;
+  ea.chunk_first = pa.chunk_first;
+  ea.chunk_last = pa.chunk_last;
+  ea.stage_g = blocky ? sc.get<unsigned>(n_cap + 1) : nullptr;
+  ea.counters = pa.counters;
+  ea.partials = sc.get<unsigned>(2 * G);
+  ea.slot = next_slot();
+  if (!sc.ok) {
+    free_column(*out);
+    *out = nullptr;
+    return fail(MS_ERR_OOM, "scratch allocation failed");
+  }
+  hipError_t e = launch_pred(pa, G, stream);
+  if (e == hipSuccess) e = launch_emit(ea, G, stream);
+  st = launched(e, out);
+  if (st == MS_OK) (*out)->sorted = 1;
+  return st;
+}
+
+}  // namespace
+
+extern "C" {
+
+ms_status ms_init(ms_alloc_fn alloc, ms_free_fn free_fn, void *ctx) {
+  if ((alloc == nullptr) != (free_fn == nullptr)) return fail(MS_ERR_INVALID_ARG, "give both callbacks or neither");
+  int dev = 0;
+  hipError_t e = hipGetDevice(&dev);
+  if (e != hipSuccess) return hip_fail(e, "hipGetDevice");
+  hipDeviceProp_t prop;
+  e = hipGetDeviceProperties(&prop, dev);
+  if (e != hipSuccess) return hip_fail(e, "hipGetDeviceProperties");
+  g_cus = prop.multiProcessorCount > 0 ? prop.multiProcessorCount : 256;
+  g_alloc = alloc;
+  g_free = free_fn;
+  g_ctx = ctx;
+  g_init = true;
+  return MS_OK;
+}
+
+const char *ms_last_error(void) { return t_err.c_str(); }
+
+ms_status ms_column_free(ms_column *col) {
+  free_column(col);
+  return MS_OK;
+}
+
+ms_status ms_column_wrap_uncompr(const uint32_t *dev_vals, uint64_t n, void *stream, ms_column **out) {
+  if (!out) return fail(MS_ERR_INVALID_ARG, "out is NULL");
+  *out = nullptr;
+  ms_status st = check_init();
+  if (st != MS_OK) return st;
+  if (n >= (1ull << 32)) return fail(MS_ERR_INVALID_ARG, "columns hold fewer than 2^32 values");
+  if (n > 0 && (!dev_vals || (reinterpret_cast<uintptr_t>(dev_vals) & 15)))
+    return fail(MS_ERR_INVALID_ARG, "values must be a 16-byte aligned device pointer");
+  ms_column *c = new ms_column();
+  c->kind = MS_UNCOMPR;
+  c->width = 0;
+  c->n_cap = n;
+  c->n_host = n;
+  c->nb_cap = 0;
+  c->payload_cap = n;
+  c->stream = stream;
+  c->sorted = 0;
+  c->buf_bytes = align256(sizeof(ColHdr));
+  c->buf = dev_alloc(c->buf_bytes, stream);
+  if (!c->buf) {
+    delete c;
+    return fail(MS_ERR_OOM, "device allocation failed");
+  }
+  std::memset(&c->v, 0, sizeof(c->v));
+  c->v.kind = MS_UNCOMPR;
+  c->v.hdr = reinterpret_cast<ColHdr *>(c->buf);
+  c->v.payload = const_cast<unsigned *>(dev_vals);
+  c->v.n_cap = n;
+  c->v.payload_cap = n;
+  hipError_t e = launch_set_hdr(c->v.hdr, n, 0, 0, 0, 0, 0, stream);
+  Scratch sc(stream);
+  const unsigned G = grid_for(chunks_of(n));
+  unsigned *partials = sc.get<unsigned>(2 * G);
+  if (!sc.ok) {
+    free_column(c);
+    return fail(MS_ERR_OOM, "scratch allocation failed");
+  }
+  if (e == hipSuccess) e = launch_colstats(c->v, G, partials, next_slot(), stream);
+  if (e != hipSuccess) {
+    free_column(c);
+    return hip_fail(e, "kernel launch");
+  }
+  *out = c;
+  return MS_OK;
+}
+
+ms_status ms_morph(const ms_column *in, ms_format fmt, void *stream, ms_column **out) {
+  if (!out) return fail(MS_ERR_INVALID_ARG, "out is NULL");
+  *out = nullptr;
+  ms_status st = check_init();
+  if (st != MS_OK) return st;
+  if (!in) return fail(MS_ERR_INVALID_ARG, "input is NULL");
+  st = check_fmt(fmt);
+  if (st != MS_OK) return st;
+  const uint64_t n_cap = in->n_host != kUnknown ? in->n_host : in->n_cap;
+  const unsigned G = grid_for(chunks_of(n_cap));
+  unsigned auto_w = 0;
+  st = make_output(fmt, n_cap, stream, out, auto_w);
+  if (st != MS_OK) return st;
+  Scratch sc(stream);
+  unsigned *partials = sc.get<unsigned>(2 * G);
+  unsigned *seg = (fmt.kind == MS_RLE) ? sc.get<unsigned>(G) : nullptr;
+  if (!sc.ok) {
+    free_column(*out);
+    *out = nullptr;
+    return fail(MS_ERR_OOM, "scratch allocation failed");
+  }
+  hipError_t e;
+  if (fmt.kind == MS_RLE)
+    e = launch_rle(0, in->v, in->v, (*out)->v, G, seg, partials, next_slot(), stream);
+  else
+    e = launch_morph(in->v, (*out)->v, auto_w, G, partials, next_slot(), stream);
+  st = launched(e, out);
+  if (st == MS_OK) {
+    (*out)->n_host = in->n_host;
+    (*out)->sorted = in->sorted;
+  }
+  return st;
+}
+
+ms_status ms_column_shrink(ms_column *col, void *stream) {
+  ms_status st = check_init();
+  if (st != MS_OK) return st;
+  if (!col) return fail(MS_ERR_INVALID_ARG, "column is NULL");
+  ColHdr h;
+  st = read_hdr(col, stream, h);
+  if (st != MS_OK) return st;
+  const uint64_t n = h.n;
+  ms_column *nc = nullptr;
+  hipStream_t s = reinterpret_cast<hipStream_t>(stream);
+  hipError_t e = hipSuccess;
+  switch (col->kind) {
+    case MS_UNCOMPR: {
+      if (col->buf_bytes <= align256(sizeof(ColHdr))) {  // wrapped: nothing owned to shrink
+        col->n_host = n;
+        return MS_OK;
+      }
+      st = alloc_column(MS_UNCOMPR, 0, n, kUnknown, kUnknown, stream, &nc);
+      if (st != MS_OK) return st;
+      if (n) e = hipMemcpyAsync(nc->v.payload, col->v.payload, 4 * n, hipMemcpyDeviceToDevice, s);
+      break;
+    }
+    case MS_STATIC_BP: {
+      const uint64_t n_main = n & ~31ull;
+      const uint64_t words = n_main * h.sbp_width / 32;
+      st = alloc_column(MS_STATIC_BP, h.sbp_width, n, kUnknown, words, stream, &nc);
+      if (st != MS_OK) return st;
+      if (words) e = hipMemcpyAsync(nc->v.payload, col->v.payload, 4 * words, hipMemcpyDeviceToDevice, s);
+      if (e == hipSuccess && n > n_main)
+        e = hipMemcpyAsync(nc->v.rem, col->v.rem, 4 * (n - n_main), hipMemcpyDeviceToDevice, s);
+      break;
+    }
+    case MS_DYN_BP:
+    case MS_DELTA_DYN_BP:
+    case MS_FOR_DYN_BP: {
+      const uint64_t n_main = n & ~511ull, nb = n_main / kBlk;
+      std::vector<unsigned char> widths(nb);
+      if (nb) {
+        e = hipMemcpy(widths.data(), col->v.widths, nb, hipMemcpyDeviceToHost);
+        if (e != hipSuccess) return hip_fail(e, "widths copy");
+      }
+      std::vector<unsigned> noff(nb + 1);
+      uint64_t words = 0;
+      for (uint64_t k = 0; k < nb; k++) {
+        noff[k] = (unsigned)words;
+        words += 16ull * widths[k];
+      }
+      st = alloc_column(col->kind, 0, n, nb, words, stream, &nc);
+      if (st != MS_OK) return st;
+      Scratch sc(stream);
+      unsigned *d_noff = sc.get<unsigned>(nb + 1);
+      if (!sc.ok) {
+        free_column(nc);
+        return fail(MS_ERR_OOM, "scratch allocation failed");
+      }
+      if (nb) {
+        e = hipMemcpyAsync(nc->v.widths, col->v.widths, nb, hipMemcpyDeviceToDevice, s);
+        if (e == hipSuccess) e = hipMemcpyAsync(nc->v.bases, col->v.bases, 4 * nb, hipMemcpyDeviceToDevice, s);
+        if (e == hipSuccess) e = hipMemcpyAsync(nc->v.offsets, noff.data(), 4 * nb, hipMemcpyHostToDevice, s);
+        if (e == hipSuccess) e = hipMemcpyAsync(d_noff, noff.data(), 4 * nb, hipMemcpyHostToDevice, s);
+        if (e == hipSuccess)
+          e = launch_shrink_payload(col->v.payload, col->v.offsets, col->v.widths, d_noff, nc->v.payload, nb, stream);
+      }
+      if (e == hipSuccess && n > n_main)
+        e = hipMemcpyAsync(nc->v.rem, col->v.rem, 4 * (n - n_main), hipMemcpyDeviceToDevice, s);
+      if (e == hipSuccess) e = hipStreamSynchronize(s);  // noff lives on the host stack
+      break;
+    }
+    case MS_RLE: {
+      st = alloc_column(MS_RLE, 0, h.runs, kUnknown, kUnknown, stream, &nc);
+      if (st != MS_OK) return st;
+      if (h.runs) {
+        e = hipMemcpyAsync(nc->v.rvalues, col->v.rvalues, 4 * h.runs, hipMemcpyDeviceToDevice, s);
+        if (e == hipSuccess)
+          e = hipMemcpyAsync(nc->v.rstarts, col->v.rstarts, 4 * h.runs, hipMemcpyDeviceToDevice, s);
+      }
+      nc->n_cap = n;
+      nc->v.n_cap = h.runs;
+      break;
+    }
+    default: return fail(MS_ERR_INVALID_ARG, "bad column");
+  }
+  if (e == hipSuccess) e = hipMemcpyAsync(nc->v.hdr, col->v.hdr, sizeof(ColHdr), hipMemcpyDeviceToDevice, s);
+  if (e != hipSuccess) {
+    free_column(nc);
+    return hip_fail(e, "shrink copy");
+  }
+  // swap the new buffer into the caller's handle
+  dev_free(col->buf, col->buf_bytes, col->stream);
+  col->buf = nc->buf;
+  col->buf_bytes = nc->buf_bytes;
+  col->stream = stream;
+  col->v = nc->v;
+  col->v.n_cap = (col->kind == MS_RLE) ? h.runs : n;
+  col->n_cap = n;
+  col->nb_cap = nc->nb_cap;
+  col->payload_cap = nc->payload_cap;
+  col->width = (col->kind == MS_STATIC_BP) ? h.sbp_width : 0;
+  col->v.width = col->width;
+  col->n_host = n;
+  delete nc;
+  return MS_OK;
+}
+
+ms_status ms_column_encode(const uint32_t *dev_vals, uint64_t n, ms_format fmt, void *stream, ms_column **out) {
+  if (!out) return fail(MS_ERR_INVALID_ARG, "out is NULL");
+  *out = nullptr;
+  ms_column *raw = nullptr;
+  ms_status st = ms_column_wrap_uncompr(dev_vals, n, stream, &raw);
+  if (st != MS_OK) return st;
+  st = ms_morph(raw, fmt, stream, out);
+  if (st == MS_OK) {
+    st = ms_column_shrink(*out, stream);
+    if (st != MS_OK) {
+      free_column(*out);
+      *out = nullptr;
+    }
+  }
+  (void)hipStreamSynchronize(reinterpret_cast<hipStream_t>(stream));
+  free_column(raw);
+  return st;
+}
+
+ms_status ms_column_decode(const ms_column *col, uint32_t *dev_out, void *stream) {
+  ms_status st = check_init();
+  if (st != MS_OK) return st;
+  if (!col) return fail(MS_ERR_INVALID_ARG, "column is NULL");
+  const uint64_t n_cap = col->n_host != kUnknown ? col->n_host : col->n_cap;
+  if (n_cap && !dev_out) return fail(MS_ERR_INVALID_ARG, "output is NULL");
+  if (reinterpret_cast<uintptr_t>(dev_out) & 15) return fail(MS_ERR_INVALID_ARG, "output must be 16-byte aligned");
+  hipError_t e = launch_decode(col->v, dev_out, grid_for(chunks_of(n_cap)), stream);
+  return e == hipSuccess ? MS_OK : hip_fail(e, "kernel launch");
+}
+
+ms_status ms_column_info_get(const ms_column *col, void *stream, ms_column_info *out) {
+  ms_status st = check_init();
+  if (st != MS_OK) return st;
+  if (!col || !out) return fail(MS_ERR_INVALID_ARG, "NULL argument");
+  ColHdr h;
+  st = read_hdr(col, stream, h);
+  if (st != MS_OK) return st;
+  std::memset(out, 0, sizeof(*out));
+  out->n = h.n;
+  out->kind = col->kind;
+  out->or_all = h.or_all;
+  out->sorted = h.sorted | col->sorted;
+  out->capacity_bytes = col->buf_bytes;
+  const uint64_t n = h.n;
+  switch (col->kind) {
+    case MS_UNCOMPR:
+      out->n_main = n;
+      out->payload_words = n;
+      out->payload_extent = n;
+      out->footprint = 4 * n;
+      break;
+    case MS_STATIC_BP:
+      out->bit_width = h.sbp_width;
+      out->n_main = n & ~31ull;
+      out->n_rem = n - out->n_main;
+      out->payload_words = out->n_main * h.sbp_width / 32;
+      out->payload_extent = out->payload_words;
+      out->footprint = 4 * out->payload_words + 4 * out->n_rem;
+      break;
+    case MS_RLE:
+      out->n_main = n;
+      out->runs = h.runs;
+      out->footprint = 8 * h.runs;
+      break;
+    default: {
+      out->n_main = n & ~511ull;
+      out->n_rem = n - out->n_main;
+      const uint64_t nb = out->n_main / kBlk;
+      out->n_blocks = nb;
+      std::vector<unsigned char> w(nb);
+      std::vector<unsigned> o(nb);
+      if (nb) {
+        hipError_t e = hipMemcpy(w.data(), col->v.widths, nb, hipMemcpyDeviceToHost);
+        if (e == hipSuccess) e = hipMemcpy(o.data(), col->v.offsets, 4 * nb, hipMemcpyDeviceToHost);
+        if (e != hipSuccess) return hip_fail(e, "metadata copy");
+      }
+      uint64_t words = 0, extent = 0;
+      for (uint64_t k = 0; k < nb; k++) {
+        words += 16ull * w[k];
+        extent = std::max<uint64_t>(extent, (uint64_t)o[k] + 16ull * w[k]);
+      }
+      out->payload_words = words;
+      out->payload_extent = extent;
+      out->footprint = (col->kind == MS_DYN_BP ? 5 : 9) * nb + 4 * words + 4 * out->n_rem;
+    }
+  }
+  return MS_OK;
+}
+
+ms_status ms_column_read_section(const ms_column *col, ms_section sec, void *host_dst, uint64_t bytes, void *stream,
+                                 uint64_t *copied) {
+  ms_column_info info;
+  ms_status st = ms_column_info_get(col, stream, &info);
+  if (st != MS_OK) return st;
+  const void *src = nullptr;
+  uint64_t size = 0;
+  switch (sec) {
+    case MS_SEC_WIDTHS: src = col->v.widths; size = info.n_blocks; break;
+    case MS_SEC_OFFSETS: src = col->v.offsets; size = 4 * info.n_blocks; break;
+    case MS_SEC_BASES: src = col->v.bases; size = 4 * info.n_blocks; break;
+    case MS_SEC_PAYLOAD: src = col->v.payload; size = 4 * info.payload_extent; break;
+    case MS_SEC_REM: src = col->v.rem; size = 4 * info.n_rem; break;
+    case MS_SEC_RVALUES: src = col->v.rvalues; size = 4 * info.runs; break;
+    case MS_SEC_RSTARTS: src = col->v.rstarts; size = 4 * info.runs; break;
+    default: return fail(MS_ERR_INVALID_ARG, "bad section");
+  }
+  const uint64_t nbytes = std::min(bytes, size);
+  if (nbytes && (!src || !host_dst)) return fail(MS_ERR_INVALID_ARG, "section not present");
+  if (nbytes) {
+    hipError_t e = hipMemcpy(host_dst, src, nbytes, hipMemcpyDeviceToHost);
+    if (e != hipSuccess) return hip_fail(e, "section copy");
+  }
+  if (copied) *copied = nbytes;
+  return MS_OK;
+}
+
+ms_status ms_select(const ms_column *in, ms_cmp cmp, uint32_t c0, uint32_t c1, ms_format fmt, void *stream,
+                    ms_column **out) {
+  if (!out) return fail(MS_ERR_INVALID_ARG, "out is NULL");
+  *out = nullptr;
+  ms_status st = check_init();
+  if (st != MS_OK) return st;
+  if (!in) return fail(MS_ERR_INVALID_ARG, "input is NULL");
+  PredArgs pa;
+  std::memset(&pa, 0, sizeof(pa));
+  pa.mode = 0;
+  // every comparison becomes "v - lo <= span" (unsigned), possibly negated
+  unsigned lo = 0, span = 0, neg = 0;
+  bool never = false;
+  switch (cmp) {
+    case MS_EQ: lo = c0; span = 0; break;
+    case MS_NE: lo = c0; span = 0; neg = 1; break;
+    case MS_LT: if (c0 == 0) never = true; else { lo = 0; span = c0 - 1; } break;
+    case MS_LE: lo = 0; span = c0; break;
+    case MS_GT: if (c0 == 0xFFFFFFFFu) never = true; else { lo = c0 + 1; span = 0xFFFFFFFFu - c0 - 1; } break;
+    case MS_GE: lo = c0; span = 0xFFFFFFFFu - c0; break;
+    case MS_BETWEEN: if (c0 > c1) never = true; else { lo = c0; span = c1 - c0; } break;
+    default: return fail(MS_ERR_INVALID_ARG, "unknown comparison");
+  }
+  if (never) {
+    lo = 0;
+    span = 0xFFFFFFFFu;
+    neg = 1;
+  }
+  pa.lo = lo;
+  pa.span = span;
+  pa.neg = neg;
+  return compaction(in, pa, false, false, fmt, stream, out);
+}
+
+ms_status ms_bitmap_from_positions(const ms_column *pos, uint64_t domain, uint32_t *dev_bitmap, void *stream) {
+  ms_status st = check_init();
+  if (st != MS_OK) return st;
+  if (!pos) return fail(MS_ERR_INVALID_ARG, "input is NULL");
+  if (domain > (1ull << 32)) return fail(MS_ERR_INVALID_ARG, "domain exceeds 2^32");
+  const uint64_t words = (domain + 31) / 32;
+  if (words && !dev_bitmap) return fail(MS_ERR_INVALID_ARG, "bitmap is NULL");
+  hipError_t e = launch_fill_u32(dev_bitmap, words, 0u, stream);
+  const uint64_t n_cap = pos->n_host != kUnknown ? pos->n_host : pos->n_cap;
+  if (e == hipSuccess) e = launch_bitmap(pos->v, domain, dev_bitmap, grid_for(chunks_of(n_cap)), stream);
+  return e == hipSuccess ? MS_OK : hip_fail(e, "kernel launch");
+}
+
+ms_status ms_semijoin(const ms_column *keys, const uint32_t *dev_bitmap, uint64_t domain, ms_format fmt,
+                      void *stream, ms_column **out) {
+  if (!out) return fail(MS_ERR_INVALID_ARG, "out is NULL");
+  *out = nullptr;
+  ms_status st = check_init();
+  if (st != MS_OK) return st;
+  if (!keys) return fail(MS_ERR_INVALID_ARG, "input is NULL");
+  if (domain > (1ull << 32)) return fail(MS_ERR_INVALID_ARG, "domain exceeds 2^32");
+  if (domain && !dev_bitmap) return fail(MS_ERR_INVALID_ARG, "bitmap is NULL");
+  PredArgs pa;
+  std::memset(&pa, 0, sizeof(pa));
+  pa.mode = 1;
+  pa.bitmap = dev_bitmap;
+  pa.domain = domain;
+  return compaction(keys, pa, false, false, fmt, stream, out);
+}
+
+ms_status ms_intersect(const ms_column *a, const ms_column *b, uint64_t domain, ms_format fmt, void *stream,
+                       ms_column **out) {
+  if (!out) return fail(MS_ERR_INVALID_ARG, "out is NULL");
+  *out = nullptr;
+  ms_status st = check_init();
+  if (st != MS_OK) return st;
+  if (!a || !b) return fail(MS_ERR_INVALID_ARG, "input is NULL");
+  if (domain > (1ull << 32)) return fail(MS_ERR_INVALID_ARG, "domain exceeds 2^32");
+  // probe the list with the smaller capacity against a bitmap of the other one
+  const ms_column *probe = a, *build = b;
+  const uint64_t ca = a->n_host != kUnknown ? a->n_host : a->n_cap;
+  const uint64_t cb = b->n_host != kUnknown ? b->n_host : b->n_cap;
+  if (cb < ca) std::swap(probe, build);
+  Scratch sc(stream);
+  const uint64_t words = (domain + 31) / 32;
+  unsigned *bm = sc.get<unsigned>(words + 1);
+  const uint64_t ncb = std::max(ca, cb);
+  const uint64_t Cb = chunks_of(ncb);
+  unsigned *first = sc.get<unsigned>(Cb + 1), *last = sc.get<unsigned>(Cb + 1);
+  if (!sc.ok) return fail(MS_ERR_OOM, "scratch allocation failed");
+  {
+    hipError_t e = launch_fill_u32(bm, words, 0u, stream);
+    if (e == hipSuccess)
+      e = launch_bitmap_checked(build->v, domain, bm, first, last, grid_for(Cb), stream);
+    if (e == hipSuccess) e = launch_check_order(first, last, build->v, stream);
+    if (e != hipSuccess) return hip_fail(e, "kernel launch");
+  }
+  PredArgs pa;
+  std::memset(&pa, 0, sizeof(pa));
+  pa.mode = 2;
+  pa.bitmap = bm;
+  pa.domain = domain;
+  return compaction(probe, pa, true, true, fmt, stream, out);
+}
+
+ms_status ms_project(const ms_column *data, const ms_column *pos, ms_format fmt, void *stream, ms_column **out) {
+  if (!out) return fail(MS_ERR_INVALID_ARG, "out is NULL");
+  *out = nullptr;
+  ms_status st = check_init();
+  if (st != MS_OK) return st;
+  if (!data || !pos) return fail(MS_ERR_INVALID_ARG, "input is NULL");
+  st = check_fmt(fmt);
+  if (st != MS_OK) return st;
+  const uint64_t n_cap = pos->n_host != kUnknown ? pos->n_host : pos->n_cap;
+  const unsigned G = grid_for(chunks_of(n_cap));
+  unsigned auto_w = 0;
+  st = make_output(fmt, n_cap, stream, out, auto_w);
+  if (st != MS_OK) return st;
+  Scratch sc(stream);
+  unsigned *partials = sc.get<unsigned>(2 * G);
+  unsigned *seg = (fmt.kind == MS_RLE) ? sc.get<unsigned>(G) : nullptr;
+  if (!sc.ok) {
+    free_column(*out);
+    *out = nullptr;
+    return fail(MS_ERR_OOM, "scratch allocation failed");
+  }
+  hipError_t e;
+  if (fmt.kind == MS_RLE)
+    e = launch_rle(1, pos->v, data->v, (*out)->v, G, seg, partials, next_slot(), stream);
+  else
+    e = launch_project(pos->v, data->v, (*out)->v, auto_w, G, partials, next_slot(), stream);
+  st = launched(e, out);
+  if (st == MS_OK) (*out)->n_host = pos->n_host;
+  return st;
+}
+
+ms_status ms_sum(const ms_column *in, uint64_t *dev_result, void *stream) {
+  ms_status st = check_init();
+  if (st != MS_OK) return st;
+  if (!in || !dev_result) return fail(MS_ERR_INVALID_ARG, "NULL argument");
+  const uint64_t n_cap = in->n_host != kUnknown ? in->n_host : in->n_cap;
+  const unsigned G = grid_for(chunks_of(n_cap));
+  Scratch sc(stream);
+  unsigned long long *partials = sc.get<unsigned long long>(G);
+  if (!sc.ok) return fail(MS_ERR_OOM, "scratch allocation failed");
+  hipError_t e = launch_sum(in->v, reinterpret_cast<unsigned long long *>(dev_result), G, partials, next_slot(),
+                            stream);
+  return e == hipSuccess ? MS_OK : hip_fail(e, "kernel launch");
+}
+
+ms_status ms_group_sum(const ms_column *groups, const ms_column *vals, uint32_t G_groups, uint64_t *dev_out,
+                       void *stream) {
+  ms_status st = check_init();
+  if (st != MS_OK) return st;
+  if (!groups || !vals) return fail(MS_ERR_INVALID_ARG, "input is NULL");
+  if (G_groups && !dev_out) return fail(MS_ERR_INVALID_ARG, "output is NULL");
+  if (groups->n_host != kUnknown && vals->n_host != kUnknown && groups->n_host != vals->n_host)
+    return fail(MS_ERR_LENGTH_MISMATCH, "groups and values differ in length");
+  if (G_groups == 0) return MS_OK;
+  const uint64_t n_cap = std::min(groups->n_host != kUnknown ? groups->n_host : groups->n_cap,
+                                  vals->n_host != kUnknown ? vals->n_host : vals->n_cap);
+  unsigned G = grid_for(chunks_of(n_cap));
+  if (G > (unsigned)g_cus) G = (unsigned)g_cus;  // partials are G x groups
+  Scratch sc(stream);
+  const bool lds = G_groups <= 4096;
+  unsigned long long *partials = sc.get<unsigned long long>(lds ? (uint64_t)G * G_groups : G_groups);
+  if (!sc.ok) return fail(MS_ERR_OOM, "scratch allocation failed");
+  hipError_t e = hipSuccess;
+  if (!lds) e = launch_fill_u64(partials, G_groups, 0ull, stream);
+  if (e == hipSuccess)
+    e = launch_group_sum(groups->v, vals->v, G_groups, reinterpret_cast<unsigned long long *>(dev_out), G, partials,
+                         next_slot(), stream);
+  return e == hipSuccess ? MS_OK : hip_fail(e, "kernel launch");
+}
+
+ms_status ms_sync(void *stream) {
+  ms_status st = check_init();
+  if (st != MS_OK) return st;
+  hipError_t e = hipStreamSynchronize(reinterpret_cast<hipStream_t>(stream));
+  if (e != hipSuccess) return hip_fail(e, "stream sync");
+  unsigned code = read_and_clear_err(stream);
+  if (code) {
+    static const char *names[] = {"ok", "invalid argument", "unsupported", "value too wide for the static BP width",
+                                  "position or group out of range", "input not strictly increasing",
+                                  "length mismatch"};
+    return fail((ms_status)code, std::string("device-side error: ") + (code < 7 ? names[code] : "unknown"));
+  }
+  return MS_OK;
+}
+
+}  // extern "C"

@@ -1,0 +1,367 @@
+// ms_device.h -- device primitives for CDNA4 (gfx950, wave64).
+//
+// Unit of work: a wave handles one 512-value chunk at a time, lane l holding the
+// 8 consecutive values 8l..8l+7 of the chunk.  Packed at width W those 8 values
+// are the W bytes starting at byte l*W of the chunk's packed block, so every lane
+// reads one short contiguous window and unpacks it with compile-time shifts
+// (one instantiation per width 0..32).  Packing runs the other way: each lane
+// ORs its window into a zeroed per-wave LDS block, then the wave writes the
+// block out with 16-byte stores.
+#pragma once
+#include <hip/hip_runtime.h>
+
+#include "ms_internal.h"
+
+namespace ms {
+
+#define MS_WIDTH_CASES(X)                                                                                        \
+  X(0) X(1) X(2) X(3) X(4) X(5) X(6) X(7) X(8) X(9) X(10) X(11) X(12) X(13) X(14) X(15) X(16) X(17) X(18) X(19) \
+  X(20) X(21) X(22) X(23) X(24) X(25) X(26) X(27) X(28) X(29) X(30) X(31) X(32)
+
+__device__ unsigned int g_err;               // first data-dependent error since the last sync
+__device__ unsigned int g_ring[kRingSlots];  // self-resetting "last workgroup" counters
+
+__device__ __forceinline__ void raise_err(unsigned code) { atomicCAS(&g_err, 0u, code); }
+
+__device__ __forceinline__ unsigned lane_id() { return __lane_id(); }
+__device__ __forceinline__ unsigned bw(unsigned x) { return x ? 32u - __clz(x) : 0u; }
+__device__ __forceinline__ unsigned lowmask(unsigned w) { return w >= 32 ? 0xFFFFFFFFu : ((1u << w) - 1u); }
+
+__device__ __forceinline__ void wave_sync() {
+  __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
+  __builtin_amdgcn_wave_barrier();
+  __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
+}
+
+__device__ __forceinline__ unsigned wave_or(unsigned x) {
+#pragma unroll
+  for (int d = 32; d >= 1; d >>= 1) x |= __shfl_xor(x, d);
+  return x;
+}
+__device__ __forceinline__ unsigned wave_min(unsigned x) {
+#pragma unroll
+  for (int d = 32; d >= 1; d >>= 1) x = min(x, (unsigned)__shfl_xor(x, d));
+  return x;
+}
+__device__ __forceinline__ unsigned wave_add(unsigned x) {
+#pragma unroll
+  for (int d = 32; d >= 1; d >>= 1) x += __shfl_xor(x, d);
+  return x;
+}
+__device__ __forceinline__ unsigned long long wave_add64(unsigned long long x) {
+#pragma unroll
+  for (int d = 32; d >= 1; d >>= 1) x += __shfl_xor(x, d);
+  return x;
+}
+// Exclusive prefix sum over the 64 lanes (wrapping uint32 arithmetic).
+__device__ __forceinline__ unsigned wave_excl_scan(unsigned x, unsigned lane) {
+  unsigned incl = x;
+#pragma unroll
+  for (int d = 1; d < 64; d <<= 1) {
+    unsigned y = __shfl_up(incl, d);
+    if (lane >= (unsigned)d) incl += y;
+  }
+  return incl - x;
+}
+
+// ---------------------------------------------------------------------------------------------
+// Unpack: lane's 8 values of a block packed at width W (block 64-byte aligned).
+template <int W>
+__device__ __forceinline__ void extract8(const unsigned *w, unsigned (&v)[8]) {
+#pragma unroll
+  for (int i = 0; i < 8; i++) {
+    constexpr unsigned mask = (W >= 32) ? 0xFFFFFFFFu : ((1u << W) - 1u);
+    const int bit = i * W;
+    const int q = bit >> 5, sh = bit & 31;
+    if (sh + W <= 32)
+      v[i] = (w[q] >> sh) & mask;
+    else
+      v[i] = __builtin_amdgcn_alignbit(w[q + 1], w[q], sh) & mask;
+  }
+}
+
+template <int W>
+__device__ __forceinline__ void unpack8(const unsigned *__restrict__ blk, unsigned lane, unsigned (&v)[8]) {
+  if constexpr (W == 0) {
+#pragma unroll
+    for (int i = 0; i < 8; i++) v[i] = 0;
+  } else if constexpr (W == 32) {
+    const uint4 *p = reinterpret_cast<const uint4 *>(blk) + 2 * lane;
+    uint4 a = p[0], b = p[1];
+    v[0] = a.x; v[1] = a.y; v[2] = a.z; v[3] = a.w;
+    v[4] = b.x; v[5] = b.y; v[6] = b.z; v[7] = b.w;
+  } else if constexpr (W % 4 == 0) {
+    constexpr int NW = W / 4;  // the lane's window is word aligned
+    const unsigned *p = blk + lane * NW;
+    unsigned w[NW];
+#pragma unroll
+    for (int k = 0; k < NW; k++) w[k] = p[k];
+    extract8<W>(w, v);
+  } else {
+    constexpr int NW = (W + 3) / 4;
+    const unsigned byte = lane * W;
+    const unsigned *p = blk + (byte >> 2);
+    const unsigned s = (byte & 3u) * 8u;
+    unsigned raw[NW + 1], w[NW];
+#pragma unroll
+    for (int k = 0; k <= NW; k++) raw[k] = p[k];
+#pragma unroll
+    for (int k = 0; k < NW; k++) w[k] = __builtin_amdgcn_alignbit(raw[k + 1], raw[k], s);
+    extract8<W>(w, v);
+  }
+}
+
+__device__ __forceinline__ void unpack8_rt(unsigned W, const unsigned *__restrict__ blk, unsigned lane,
+                                           unsigned (&v)[8]) {
+  switch (W) {
+#define MS_UNPACK_CASE(w) \
+  case w: unpack8<w>(blk, lane, v); break;
+    MS_WIDTH_CASES(MS_UNPACK_CASE)
+#undef MS_UNPACK_CASE
+    default:
+#pragma unroll
+      for (int i = 0; i < 8; i++) v[i] = 0;
+  }
+}
+
+// Random access: the value at bit offset `bit` of width W in a packed stream.
+__device__ __forceinline__ unsigned extract_at(const unsigned *__restrict__ words, unsigned long long bit, unsigned W) {
+  if (W == 0) return 0;
+  const unsigned long long q = bit >> 5;
+  const unsigned sh = (unsigned)(bit & 31);
+  const unsigned lo = words[q];
+  const unsigned hi = (sh + W > 32) ? words[q + 1] : 0u;
+  return __builtin_amdgcn_alignbit(hi, lo, sh) & lowmask(W);
+}
+
+// ---------------------------------------------------------------------------------------------
+// Pack: OR the lane's 8 W-bit values into a zeroed LDS block (16*W words).
+template <int W>
+__device__ __forceinline__ void pack8_lds(unsigned *lds, unsigned lane, const unsigned (&r)[8]) {
+  if constexpr (W == 0) {
+    return;
+  } else if constexpr (W == 32) {
+#pragma unroll
+    for (int i = 0; i < 8; i++) lds[8 * lane + i] = r[i];
+  } else {
+    constexpr int NW = (W + 3) / 4;
+    unsigned w[NW + 1];
+#pragma unroll
+    for (int k = 0; k <= NW; k++) w[k] = 0;
+#pragma unroll
+    for (int i = 0; i < 8; i++) {
+      const int bit = i * W;
+      const int q = bit >> 5, sh = bit & 31;
+      w[q] |= r[i] << sh;
+      if (sh + W > 32) w[q + 1] |= r[i] >> (32 - sh);
+    }
+    const unsigned byte = lane * W;
+    unsigned *dst = lds + (byte >> 2);
+    if constexpr (W % 4 == 0) {
+#pragma unroll
+      for (int k = 0; k < NW; k++) dst[k] = w[k];  // word-aligned, owned by this lane alone
+    } else {
+      const unsigned s = (byte & 3u) * 8u;
+      unsigned prev = 0;
+#pragma unroll
+      for (int k = 0; k <= NW; k++) {
+        const unsigned cur = w[k];
+        const unsigned g = (unsigned)(((((unsigned long long)cur) << 32) | prev) << s >> 32);
+        if (g) atomicOr(dst + k, g);
+        prev = cur;
+      }
+    }
+  }
+}
+
+__device__ __forceinline__ void pack8_lds_rt(unsigned W, unsigned *lds, unsigned lane, const unsigned (&r)[8]) {
+  switch (W) {
+#define MS_PACK_CASE(w) \
+  case w: pack8_lds<w>(lds, lane, r); break;
+    MS_WIDTH_CASES(MS_PACK_CASE)
+#undef MS_PACK_CASE
+    default: break;
+  }
+}
+
+// Pack one 512-value block held by the wave (8 values per lane, each < 2^W) and
+// write its 16*W words to dst (64-byte aligned).  lds: the wave's 512-word buffer.
+__device__ __forceinline__ void pack_block(unsigned W, const unsigned (&r)[8], unsigned lane, unsigned *lds,
+                                           unsigned *__restrict__ dst) {
+  if (W == 0) return;
+  const unsigned words = 16u * W;
+  if (W % 4 != 0) {
+    for (unsigned q = lane; q < words; q += 64) lds[q] = 0;
+    wave_sync();
+  }
+  pack8_lds_rt(W, lds, lane, r);
+  wave_sync();
+  const uint4 *s4 = reinterpret_cast<const uint4 *>(lds);
+  uint4 *d4 = reinterpret_cast<uint4 *>(dst);
+  for (unsigned q = lane; q < 4u * W; q += 64) d4[q] = s4[q];
+  wave_sync();
+}
+
+// ---------------------------------------------------------------------------------------------
+// Input column as seen by a kernel, with the sizes read from its device header.
+struct InCol {
+  unsigned kind, W;
+  unsigned long long n, n_main, nb, runs, payload_cap;
+  const unsigned char *widths;
+  const unsigned *offsets, *bases, *payload, *rem, *rvalues, *rstarts;
+};
+
+__device__ __forceinline__ InCol load_in(const ColView &c) {
+  InCol in;
+  in.kind = c.kind;
+  in.n = c.hdr->n;
+  in.W = c.hdr->sbp_width;
+  in.runs = min(c.hdr->runs, c.n_cap);
+  in.payload_cap = c.payload_cap;
+  in.widths = c.widths;
+  in.offsets = c.offsets;
+  in.bases = c.bases;
+  in.payload = c.payload;
+  in.rem = c.rem;
+  in.rvalues = c.rvalues;
+  in.rstarts = c.rstarts;
+  if (c.kind == STATIC_BP)
+    in.n_main = in.n & ~31ull;
+  else if (c.kind == DYN_BP || c.kind == DELTA_DYN_BP || c.kind == FOR_DYN_BP)
+    in.n_main = in.n & ~511ull;
+  else
+    in.n_main = in.n;
+  in.nb = in.n_main >> 9;
+  return in;
+}
+
+// First run r with rstarts[r] <= idx (runs are sorted by start, rstarts[0] = 0).
+__device__ __forceinline__ unsigned long long rle_find(const InCol &in, unsigned long long idx) {
+  unsigned long long lo = 0, hi = in.runs;  // invariant: rstarts[lo] <= idx, answer in [lo, hi)
+  while (hi - lo > 1) {
+    unsigned long long mid = (lo + hi) >> 1;
+    if (in.rstarts[mid] <= idx)
+      lo = mid;
+    else
+      hi = mid;
+  }
+  return lo;
+}
+
+// Decode chunk c (values 512c .. 512c+511); lane gets 8 consecutive values.  Values
+// at indices >= n are unspecified (callers mask them out).
+__device__ __forceinline__ void decode_chunk(const InCol &in, unsigned long long c, unsigned lane, unsigned (&v)[8]) {
+  const unsigned long long idx0 = c * kBlk + 8ull * lane;
+  switch (in.kind) {
+    case UNCOMPR: {
+      if (idx0 + 8 <= in.n) {
+        const uint4 *p = reinterpret_cast<const uint4 *>(in.payload + idx0);
+        uint4 a = p[0], b = p[1];
+        v[0] = a.x; v[1] = a.y; v[2] = a.z; v[3] = a.w;
+        v[4] = b.x; v[5] = b.y; v[6] = b.z; v[7] = b.w;
+      } else {
+#pragma unroll
+        for (int i = 0; i < 8; i++) v[i] = (idx0 + i < in.n) ? in.payload[idx0 + i] : 0u;
+      }
+      break;
+    }
+    case STATIC_BP: {
+      if (c * kBlk < in.n_main && in.W <= 32 && (c + 1) * 16ull * in.W <= in.payload_cap + 512) {
+        unpack8_rt(in.W, in.payload + c * 16ull * in.W, lane, v);  // lanes past n_main read slack
+      }
+      if (idx0 >= in.n_main) {
+#pragma unroll
+        for (int i = 0; i < 8; i++) v[i] = (idx0 + i < in.n) ? in.rem[idx0 + i - in.n_main] : 0u;
+      }
+      break;
+    }
+    case DYN_BP:
+    case DELTA_DYN_BP:
+    case FOR_DYN_BP: {
+      if (c < in.nb) {
+        unsigned W = in.widths[c];
+        unsigned long long off = in.offsets[c];
+        if (W > 32 || off + 16ull * W > in.payload_cap) {  // a corrupt directory never reads out of bounds
+          raise_err(E_INVALID);
+          W = 0;
+          off = 0;
+        }
+        unpack8_rt(W, in.payload + off, lane, v);
+        if (in.kind == FOR_DYN_BP) {
+          const unsigned ref = in.bases[c];
+#pragma unroll
+          for (int i = 0; i < 8; i++) v[i] += ref;
+        } else if (in.kind == DELTA_DYN_BP) {
+#pragma unroll
+          for (int i = 1; i < 8; i++) v[i] += v[i - 1];
+          const unsigned excl = wave_excl_scan(v[7], lane) + in.bases[c];
+#pragma unroll
+          for (int i = 0; i < 8; i++) v[i] += excl;
+        }
+      } else {
+#pragma unroll
+        for (int i = 0; i < 8; i++) v[i] = (idx0 + i < in.n) ? in.rem[idx0 + i - in.n_main] : 0u;
+      }
+      break;
+    }
+    case RLE: {
+      if (idx0 < in.n) {
+        unsigned long long r = rle_find(in, idx0);
+#pragma unroll
+        for (int i = 0; i < 8; i++) {
+          while (r + 1 < in.runs && in.rstarts[r + 1] <= idx0 + i) r++;
+          v[i] = in.rvalues[r];
+        }
+      } else {
+#pragma unroll
+        for (int i = 0; i < 8; i++) v[i] = 0;
+      }
+      break;
+    }
+    default:
+#pragma unroll
+      for (int i = 0; i < 8; i++) v[i] = 0;
+  }
+}
+
+// Random access to value idx (< n) of a column (used by project).
+__device__ __forceinline__ unsigned value_at(const InCol &in, unsigned long long idx) {
+  switch (in.kind) {
+    case UNCOMPR: return in.payload[idx];
+    case STATIC_BP:
+      if (idx < in.n_main) return in.W <= 32 ? extract_at(in.payload, idx * in.W, in.W) : 0u;
+      return in.rem[idx - in.n_main];
+    case DYN_BP:
+    case FOR_DYN_BP: {
+      if (idx >= in.n_main) return in.rem[idx - in.n_main];
+      const unsigned long long k = idx >> 9;
+      unsigned W = in.widths[k];
+      unsigned long long off = in.offsets[k];
+      if (W > 32 || off + 16ull * W > in.payload_cap) {
+        raise_err(E_INVALID);
+        return 0;
+      }
+      unsigned x = extract_at(in.payload + off, (idx & 511) * W, W);
+      return in.kind == FOR_DYN_BP ? x + in.bases[k] : x;
+    }
+    case DELTA_DYN_BP: {
+      if (idx >= in.n_main) return in.rem[idx - in.n_main];
+      const unsigned long long k = idx >> 9;
+      const unsigned W = in.widths[k];
+      const unsigned long long off = in.offsets[k];
+      if (W > 32 || off + 16ull * W > in.payload_cap) {
+        raise_err(E_INVALID);
+        return 0;
+      }
+      const unsigned *p = in.payload + off;
+      unsigned x = in.bases[k];
+      const unsigned j = (unsigned)(idx & 511);
+      for (unsigned t = 1; t <= j; t++) x += extract_at(p, (unsigned long long)t * W, W);
+      return x;
+    }
+    case RLE: return in.rvalues[rle_find(in, idx)];
+    default: return 0;
+  }
+}
+
+}  // namespace ms

@@ -1,0 +1,65 @@
+// ms_kernels.h -- kernel argument blocks and host launchers (implemented in ms_kernels.hip).
+#pragma once
+#include <hip/hip_runtime.h>
+
+#include "ms_internal.h"
+
+namespace ms {
+
+struct PredArgs {
+  ColView in;
+  unsigned mode;              // 0 range predicate, 1 bitmap on keys, 2 bitmap on values (intersect)
+  unsigned lo, span, neg;     // range predicate: ((v - lo) <= span) != neg
+  const unsigned *bitmap;
+  unsigned long long domain;
+  unsigned char *bitmask;     // one byte per lane per chunk = one bit per row
+  unsigned *seg_count;
+  unsigned *seg_or;
+  unsigned *chunk_first, *chunk_last;
+  unsigned *counters;         // zeroed here for the emit phase
+  unsigned long long n_counters;
+};
+
+struct EmitArgs {
+  ColView in;                 // the phase-1 input (decoded again when emitting values)
+  ColView out;
+  unsigned auto_w;
+  unsigned emit_values;
+  unsigned check_sorted;
+  const unsigned char *bitmask;
+  const unsigned *seg_count;
+  const unsigned *seg_or;
+  const unsigned *chunk_first, *chunk_last;
+  unsigned *stage_g;          // global staging for blocks shared by several segments
+  unsigned *counters;         // per output block: values staged so far
+  unsigned *partials;
+  unsigned slot;
+};
+
+unsigned read_and_clear_err(void *stream);
+hipError_t launch_colstats(const ColView &in, unsigned G, unsigned *partials, unsigned slot, void *s);
+hipError_t launch_set_hdr(ColHdr *h, unsigned long long n, unsigned long long runs, unsigned width, unsigned or_all,
+                          unsigned or_main, unsigned sorted, void *s);
+hipError_t launch_morph(const ColView &in, const ColView &out, unsigned auto_w, unsigned G, unsigned *partials,
+                        unsigned slot, void *s);
+hipError_t launch_decode(const ColView &in, unsigned *out, unsigned G, void *s);
+hipError_t launch_rle(unsigned mode, const ColView &a, const ColView &b, const ColView &out, unsigned G,
+                      unsigned *seg_count, unsigned *partials, unsigned slot, void *s);
+hipError_t launch_project(const ColView &pos, const ColView &data, const ColView &out, unsigned auto_w, unsigned G,
+                          unsigned *partials, unsigned slot, void *s);
+hipError_t launch_pred(const PredArgs &a, unsigned G, void *s);
+hipError_t launch_emit(const EmitArgs &a, unsigned G, void *s);
+hipError_t launch_sum(const ColView &in, unsigned long long *result, unsigned G, unsigned long long *partials,
+                      unsigned slot, void *s);
+hipError_t launch_group_sum(const ColView &g, const ColView &v, unsigned groups, unsigned long long *out, unsigned G,
+                            unsigned long long *partials, unsigned slot, void *s);
+hipError_t launch_fill_u32(unsigned *p, unsigned long long n, unsigned v, void *s);
+hipError_t launch_fill_u64(unsigned long long *p, unsigned long long n, unsigned long long v, void *s);
+hipError_t launch_bitmap(const ColView &pos, unsigned long long domain, unsigned *bitmap, unsigned G, void *s);
+hipError_t launch_bitmap_checked(const ColView &pos, unsigned long long domain, unsigned *bitmap, unsigned *first,
+                                 unsigned *last, unsigned G, void *s);
+hipError_t launch_check_order(const unsigned *first, const unsigned *last, const ColView &pos, void *s);
+hipError_t launch_shrink_payload(const unsigned *src, const unsigned *old_off, const unsigned char *widths,
+                                 const unsigned *new_off, unsigned *dst, unsigned long long nb, void *s);
+
+}  // namespace ms

@@ -1,0 +1,295 @@
+"""Thin Python binding of libmorphgpu.so (argument marshalling only).
+
+Every step of every operator runs in the HIP library; this module converts
+arguments, registers PyTorch's caching allocator as the library's device memory
+provider and uses PyTorch streams.  There is no CPU fallback: if the library is
+missing the import of this module fails.
+"""
+from __future__ import annotations
+
+import ctypes
+import os
+
+import numpy as np
+import torch
+
+HERE = os.path.dirname(os.path.abspath(__file__))
+LIB_PATH = os.path.join(HERE, "libmorphgpu.so")
+
+UNCOMPR, STATIC_BP, DYN_BP, DELTA_DYN_BP, FOR_DYN_BP, RLE = range(6)
+KINDS = (UNCOMPR, STATIC_BP, DYN_BP, DELTA_DYN_BP, FOR_DYN_BP, RLE)
+KIND_NAMES = ("UNCOMPR", "STATIC_BP", "DYN_BP", "DELTA_DYN_BP", "FOR_DYN_BP", "RLE")
+EQ, NE, LT, LE, GT, GE, BETWEEN = range(7)
+BW_AUTO = 0xFFFFFFFF
+STATUS = {0: "OK", 1: "INVALID_ARG", 2: "UNSUPPORTED", 3: "VALUE_TOO_WIDE", 4: "OUT_OF_RANGE", 5: "NOT_SORTED",
+          6: "LENGTH_MISMATCH", 7: "OOM", 8: "HIP", 9: "NOT_INITIALIZED"}
+SEC_WIDTHS, SEC_OFFSETS, SEC_BASES, SEC_PAYLOAD, SEC_REM, SEC_RVALUES, SEC_RSTARTS = range(7)
+
+
+class MorphError(RuntimeError):
+    def __init__(self, code: int, msg: str):
+        super().__init__(f"{STATUS.get(code, code)}: {msg}")
+        self.code = code
+        self.status = STATUS.get(code, str(code))
+
+
+class Format(ctypes.Structure):
+    _fields_ = [("kind", ctypes.c_uint32), ("bit_width", ctypes.c_uint32)]
+
+
+class ColumnInfo(ctypes.Structure):
+    _fields_ = [("n", ctypes.c_uint64), ("kind", ctypes.c_uint32), ("bit_width", ctypes.c_uint32),
+                ("n_main", ctypes.c_uint64), ("n_rem", ctypes.c_uint64), ("n_blocks", ctypes.c_uint64),
+                ("runs", ctypes.c_uint64), ("payload_words", ctypes.c_uint64), ("payload_extent", ctypes.c_uint64),
+                ("footprint", ctypes.c_uint64), ("capacity_bytes", ctypes.c_uint64), ("or_all", ctypes.c_uint32),
+                ("sorted", ctypes.c_uint32)]
+
+
+def fmt(kind, bit_width: int = BW_AUTO) -> Format:
+    if isinstance(kind, str):
+        kind = KIND_NAMES.index(kind)
+    return Format(int(kind), int(bit_width) if kind == STATIC_BP else 0)
+
+
+if not os.path.exists(LIB_PATH):
+    raise ImportError(f"{LIB_PATH} is not built; run __graft_entry__.build() (hipcc for gfx950)")
+
+_lib = ctypes.CDLL(LIB_PATH)
+_P = ctypes.c_void_p
+_U64 = ctypes.c_uint64
+_U32 = ctypes.c_uint32
+_PP = ctypes.POINTER(ctypes.c_void_p)
+_ALLOC_T = ctypes.CFUNCTYPE(ctypes.c_void_p, ctypes.c_uint64, ctypes.c_void_p, ctypes.c_void_p)
+_FREE_T = ctypes.CFUNCTYPE(None, ctypes.c_void_p, ctypes.c_uint64, ctypes.c_void_p, ctypes.c_void_p)
+
+_sigs = {
+    "ms_init": [_ALLOC_T, _FREE_T, _P],
+    "ms_column_encode": [_P, _U64, Format, _P, _PP],
+    "ms_column_wrap_uncompr": [_P, _U64, _P, _PP],
+    "ms_column_decode": [_P, _P, _P],
+    "ms_column_free": [_P],
+    "ms_column_info_get": [_P, _P, ctypes.POINTER(ColumnInfo)],
+    "ms_column_read_section": [_P, _U32, _P, _U64, _P, ctypes.POINTER(_U64)],
+    "ms_column_shrink": [_P, _P],
+    "ms_morph": [_P, Format, _P, _PP],
+    "ms_select": [_P, _U32, _U32, _U32, Format, _P, _PP],
+    "ms_bitmap_from_positions": [_P, _U64, _P, _P],
+    "ms_semijoin": [_P, _P, _U64, Format, _P, _PP],
+    "ms_project": [_P, _P, Format, _P, _PP],
+    "ms_intersect": [_P, _P, _U64, Format, _P, _PP],
+    "ms_sum": [_P, _P, _P],
+    "ms_group_sum": [_P, _P, _U32, _P, _P],
+    "ms_sync": [_P],
+}
+for _name, _args in _sigs.items():
+    _f = getattr(_lib, _name)
+    _f.argtypes = _args
+    _f.restype = ctypes.c_int
+_lib.ms_last_error.restype = ctypes.c_char_p
+_lib.ms_last_error.argtypes = []
+
+
+def lib():
+    return _lib
+
+
+def _check(st: int):
+    if st != 0:
+        raise MorphError(st, _lib.ms_last_error().decode())
+
+
+def _stream(stream=None) -> int:
+    if stream is None:
+        stream = torch.cuda.current_stream()
+    return stream.cuda_stream if hasattr(stream, "cuda_stream") else int(stream)
+
+
+# --------------------------------------------------------------------------------- allocator
+_allocations: dict = {}
+
+
+@_ALLOC_T
+def _torch_alloc(nbytes, stream, ctx):
+    try:
+        p = torch.cuda.caching_allocator_alloc(int(nbytes), torch.cuda.current_device(), stream or 0)
+        return p
+    except Exception:  # allocation failure is reported to the library as NULL (MS_ERR_OOM)
+        return None
+
+
+@_FREE_T
+def _torch_free(ptr, nbytes, stream, ctx):
+    if ptr:
+        torch.cuda.caching_allocator_delete(ptr)
+
+
+_initialized = False
+
+
+def init(use_torch_allocator: bool = True):
+    """Initialise the library on the current device (idempotent)."""
+    global _initialized
+    if _initialized:
+        return
+    if not torch.cuda.is_available():
+        raise RuntimeError("libmorphgpu needs a ROCm GPU; none is visible")
+    torch.cuda.init()
+    if use_torch_allocator:
+        _check(_lib.ms_init(_torch_alloc, _torch_free, None))
+    else:
+        _check(_lib.ms_init(_ALLOC_T(), _FREE_T(), None))
+    _initialized = True
+
+
+# --------------------------------------------------------------------------------- columns
+class Column:
+    """A compressed column on the device (owns an ms_column*)."""
+
+    def __init__(self, handle: int, keep=None, stream=None):
+        self._h = ctypes.c_void_p(handle)
+        self._keep = keep  # device tensors a wrapped column borrows
+        self._stream = _stream(stream)
+
+    @property
+    def handle(self):
+        return self._h
+
+    def free(self):
+        if self._h and self._h.value:
+            _lib.ms_column_free(self._h)
+            self._h = ctypes.c_void_p(0)
+
+    def __del__(self):
+        try:
+            self.free()
+        except Exception:
+            pass
+
+    def info(self, stream=None) -> dict:
+        ci = ColumnInfo()
+        _check(_lib.ms_column_info_get(self._h, _stream(stream), ctypes.byref(ci)))
+        return {f: getattr(ci, f) for f, _ in ColumnInfo._fields_}
+
+    def read_section(self, sec: int, nbytes: int, dtype, stream=None) -> np.ndarray:
+        buf = np.zeros(max(nbytes, 1), np.uint8)
+        got = _U64(0)
+        _check(_lib.ms_column_read_section(self._h, sec, buf.ctypes.data, nbytes, _stream(stream), ctypes.byref(got)))
+        return buf[: got.value].view(dtype).copy()
+
+    def sections(self, stream=None) -> dict:
+        """The column's sections on the host, in the dictionary shape the oracle's decoder reads."""
+        i = self.info(stream)
+        nb = i["n_blocks"]
+        out = dict(kind=i["kind"], n=i["n"], bit_width=i["bit_width"], n_main=i["n_main"], n_rem=i["n_rem"],
+                   nb=nb, runs=i["runs"], payload_words=i["payload_words"], footprint=i["footprint"])
+        out["widths"] = self.read_section(SEC_WIDTHS, nb, np.uint8, stream)
+        out["offsets"] = self.read_section(SEC_OFFSETS, 4 * nb, np.uint32, stream)
+        out["bases"] = self.read_section(SEC_BASES, 4 * nb, np.uint32, stream)
+        out["payload"] = self.read_section(SEC_PAYLOAD, 4 * i["payload_extent"], np.uint32, stream)
+        out["rem"] = self.read_section(SEC_REM, 4 * i["n_rem"], np.uint32, stream)
+        out["rvalues"] = self.read_section(SEC_RVALUES, 4 * i["runs"], np.uint32, stream)
+        out["rstarts"] = self.read_section(SEC_RSTARTS, 4 * i["runs"], np.uint32, stream)
+        return out
+
+    def decode(self, n: int | None = None, stream=None) -> torch.Tensor:
+        """Decode into a new int32 device tensor holding the uint32 bit patterns."""
+        if n is None:
+            n = self.info(stream)["n"]
+        out = torch.empty(max(n, 4), dtype=torch.int32, device="cuda")
+        _check(_lib.ms_column_decode(self._h, out.data_ptr(), _stream(stream)))
+        return out[:n]
+
+    def shrink(self, stream=None):
+        _check(_lib.ms_column_shrink(self._h, _stream(stream)))
+        return self
+
+    def __len__(self):
+        return self.info()["n"]
+
+
+def _out(fn, *args, keep=None, stream=None) -> Column:
+    h = ctypes.c_void_p(0)
+    _check(fn(*args, ctypes.byref(h)))
+    return Column(h.value, keep=keep, stream=stream)
+
+
+def _as_u32_tensor(values) -> torch.Tensor:
+    if isinstance(values, torch.Tensor):
+        t = values
+        if t.dtype not in (torch.int32, torch.uint32):
+            raise TypeError("device values must be int32/uint32 tensors (uint32 bit patterns)")
+        if not t.is_cuda:
+            t = t.cuda()
+        return t.contiguous()
+    a = np.ascontiguousarray(values, dtype=np.uint32)
+    return torch.from_numpy(a.view(np.int32)).cuda()
+
+
+def encode(values, f: Format, stream=None) -> Column:
+    t = _as_u32_tensor(values)
+    return _out(_lib.ms_column_encode, t.data_ptr() if t.numel() else None, t.numel(), f, _stream(stream),
+                stream=stream)
+
+
+def wrap(values, stream=None) -> Column:
+    t = _as_u32_tensor(values)
+    return _out(_lib.ms_column_wrap_uncompr, t.data_ptr() if t.numel() else None, t.numel(), _stream(stream),
+                keep=t, stream=stream)
+
+
+def morph(col: Column, f: Format, stream=None) -> Column:
+    return _out(_lib.ms_morph, col.handle, f, _stream(stream), stream=stream)
+
+
+def select(col: Column, cmp: int, c0: int, c1: int = 0, f: Format = None, stream=None) -> Column:
+    f = f if f is not None else fmt(DELTA_DYN_BP)
+    return _out(_lib.ms_select, col.handle, cmp, c0 & 0xFFFFFFFF, c1 & 0xFFFFFFFF, f, _stream(stream), stream=stream)
+
+
+def bitmap_from_positions(pos: Column, domain: int, stream=None) -> torch.Tensor:
+    bm = torch.empty(max((domain + 31) // 32, 1), dtype=torch.int32, device="cuda")
+    _check(_lib.ms_bitmap_from_positions(pos.handle, domain, bm.data_ptr(), _stream(stream)))
+    return bm
+
+
+def semijoin(keys: Column, bitmap: torch.Tensor, domain: int, f: Format = None, stream=None) -> Column:
+    f = f if f is not None else fmt(DELTA_DYN_BP)
+    return _out(_lib.ms_semijoin, keys.handle, bitmap.data_ptr(), domain, f, _stream(stream), stream=stream)
+
+
+def project(data: Column, pos: Column, f: Format = None, stream=None) -> Column:
+    f = f if f is not None else fmt(STATIC_BP)
+    return _out(_lib.ms_project, data.handle, pos.handle, f, _stream(stream), stream=stream)
+
+
+def intersect(a: Column, b: Column, domain: int, f: Format = None, stream=None) -> Column:
+    f = f if f is not None else fmt(DELTA_DYN_BP)
+    return _out(_lib.ms_intersect, a.handle, b.handle, domain, f, _stream(stream), stream=stream)
+
+
+def sum_(col: Column, out: torch.Tensor | None = None, stream=None) -> torch.Tensor:
+    if out is None:
+        out = torch.empty(1, dtype=torch.int64, device="cuda")
+    _check(_lib.ms_sum(col.handle, out.data_ptr(), _stream(stream)))
+    return out
+
+
+def group_sum(groups: Column, vals: Column, G: int, out: torch.Tensor | None = None, stream=None) -> torch.Tensor:
+    if out is None:
+        out = torch.empty(max(G, 1), dtype=torch.int64, device="cuda")
+    _check(_lib.ms_group_sum(groups.handle, vals.handle, G, out.data_ptr(), _stream(stream)))
+    return out[:G]
+
+
+def sync(stream=None):
+    """Synchronise and raise the first data-dependent device error, if any."""
+    _check(_lib.ms_sync(_stream(stream)))
+
+
+def u64(t: torch.Tensor) -> np.ndarray:
+    """int64 device tensor holding uint64 results -> numpy uint64."""
+    return t.cpu().numpy().view(np.uint64)
+
+
+def u32(t: torch.Tensor) -> np.ndarray:
+    return t.cpu().numpy().view(np.uint32)
