@@ -155,6 +155,15 @@ ms_status ms_sum(const ms_column *in, uint64_t *dev_result, void *stream);
 ms_status ms_group_sum(const ms_column *groups, const ms_column *vals, uint32_t G, uint64_t *dev_out,
                        void *stream);
 
+/* Launch timing.  While enabled, every kernel launch is bracketed by two HIP events
+ * recorded on its own stream.  Records are kept in launch order until ms_prof_reset.
+ * ms_prof_get needs the launches to have finished (call ms_sync first); *name points
+ * to a static string (the kernel's name). */
+void ms_prof_enable(int on);
+uint64_t ms_prof_count(void);
+ms_status ms_prof_get(uint64_t i, const char **name, float *ms);
+void ms_prof_reset(void);
+
 /* Synchronise `stream` and return (then clear) the first data-dependent error. */
 ms_status ms_sync(void *stream);
 

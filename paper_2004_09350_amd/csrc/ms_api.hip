@@ -36,7 +36,6 @@ ms_free_fn g_free = nullptr;
 void *g_ctx = nullptr;
 bool g_init = false;
 int g_cus = 256;
-std::atomic<uint32_t> g_slot{0};
 thread_local std::string t_err;
 
 ms_status fail(ms_status st, const std::string &msg) {
@@ -65,7 +64,6 @@ void dev_free(void *p, uint64_t bytes, void *stream) {
     (void)hipFreeAsync(p, reinterpret_cast<hipStream_t>(stream));
 }
 
-unsigned next_slot() { return g_slot.fetch_add(1) % kRingSlots; }
 
 // Stream-ordered scratch released at scope exit.
 struct Scratch {
@@ -219,9 +217,21 @@ ms_status launched(hipError_t e, ms_column **out) {
   return MS_OK;
 }
 
-struct HostHdr {
-  ColHdr h;
-};
+// Header of a count-known producer's output: count from `n_src`, ORs from the partials,
+// auto-width static BP narrowed to its main part.
+hipError_t finish_produced(const ColView &out, const ColHdr *n_src, const unsigned *partials, unsigned G,
+                           unsigned auto_w, unsigned sorted, void *stream) {
+  FinishArgs f{};
+  f.out = out;
+  f.n_src = n_src;
+  f.partials = partials;
+  f.G = G;
+  f.Wp = out.width;
+  f.auto_w = auto_w;
+  f.sorted = sorted;
+  f.mode = auto_w ? 2u : 0u;
+  return launch_finish(f, stream);
+}
 
 ms_status read_hdr(const ms_column *c, void *stream, ColHdr &h) {
   hipError_t e = hipStreamSynchronize(reinterpret_cast<hipStream_t>(stream));
@@ -252,8 +262,6 @@ ms_status compaction(const ms_column *in, const PredArgs &pa_in, bool emit_value
   pa.seg_or = sc.get<unsigned>(G);
   pa.chunk_first = check_sorted ? sc.get<unsigned>(C + 1) : nullptr;
   pa.chunk_last = check_sorted ? sc.get<unsigned>(C + 1) : nullptr;
-  pa.n_counters = blocky ? n_cap / kBlk + 2 : 0;
-  pa.counters = blocky ? sc.get<unsigned>(pa.n_counters) : nullptr;
   EmitArgs ea;
   std::memset(&ea, 0, sizeof(ea));
   ea.in = in->v;
@@ -267,9 +275,7 @@ ms_status compaction(const ms_column *in, const PredArgs &pa_in, bool emit_value
   ea.chunk_first = pa.chunk_first;
   ea.chunk_last = pa.chunk_last;
   ea.stage_g = blocky ? sc.get<unsigned>(n_cap + 1) : nullptr;
-  ea.counters = pa.counters;
   ea.partials = sc.get<unsigned>(2 * G);
-  ea.slot = next_slot();
   if (!sc.ok) {
     free_column(*out);
     *out = nullptr;
@@ -277,6 +283,18 @@ ms_status compaction(const ms_column *in, const PredArgs &pa_in, bool emit_value
   }
   hipError_t e = launch_pred(pa, G, stream);
   if (e == hipSuccess) e = launch_emit(ea, G, stream);
+  if (e == hipSuccess && fmt.kind == MS_STATIC_BP && auto_w) {
+    FinishArgs f{};
+    f.out = (*out)->v;
+    f.n_src = nullptr;
+    f.partials = ea.partials;
+    f.G = G;
+    f.Wp = 32;
+    f.auto_w = 1;
+    f.sorted = 1;
+    f.mode = 2;  // provisional width is in the header
+    e = launch_finish(f, stream);
+  }
   st = launched(e, out);
   if (st == MS_OK) (*out)->sorted = 1;
   return st;
@@ -346,7 +364,7 @@ ms_status ms_column_wrap_uncompr(const uint32_t *dev_vals, uint64_t n, void *str
     free_column(c);
     return fail(MS_ERR_OOM, "scratch allocation failed");
   }
-  if (e == hipSuccess) e = launch_colstats(c->v, G, partials, next_slot(), stream);
+  if (e == hipSuccess) e = launch_colstats(c->v, G, partials, stream);
   if (e != hipSuccess) {
     free_column(c);
     return hip_fail(e, "kernel launch");
@@ -378,9 +396,10 @@ ms_status ms_morph(const ms_column *in, ms_format fmt, void *stream, ms_column *
   }
   hipError_t e;
   if (fmt.kind == MS_RLE)
-    e = launch_rle(0, in->v, in->v, (*out)->v, G, seg, partials, next_slot(), stream);
+    e = launch_rle(0, in->v, in->v, (*out)->v, G, seg, partials, stream);
   else
-    e = launch_morph(in->v, (*out)->v, auto_w, G, partials, next_slot(), stream);
+    e = launch_morph(in->v, (*out)->v, auto_w, G, partials, stream);
+  if (e == hipSuccess) e = finish_produced((*out)->v, in->v.hdr, partials, G, auto_w, in->sorted, stream);
   st = launched(e, out);
   if (st == MS_OK) {
     (*out)->n_host = in->n_host;
@@ -731,9 +750,10 @@ ms_status ms_project(const ms_column *data, const ms_column *pos, ms_format fmt,
   }
   hipError_t e;
   if (fmt.kind == MS_RLE)
-    e = launch_rle(1, pos->v, data->v, (*out)->v, G, seg, partials, next_slot(), stream);
+    e = launch_rle(1, pos->v, data->v, (*out)->v, G, seg, partials, stream);
   else
-    e = launch_project(pos->v, data->v, (*out)->v, auto_w, G, partials, next_slot(), stream);
+    e = launch_project(pos->v, data->v, (*out)->v, auto_w, G, partials, stream);
+  if (e == hipSuccess) e = finish_produced((*out)->v, pos->v.hdr, partials, G, auto_w, 0, stream);
   st = launched(e, out);
   if (st == MS_OK) (*out)->n_host = pos->n_host;
   return st;
@@ -748,8 +768,7 @@ ms_status ms_sum(const ms_column *in, uint64_t *dev_result, void *stream) {
   Scratch sc(stream);
   unsigned long long *partials = sc.get<unsigned long long>(G);
   if (!sc.ok) return fail(MS_ERR_OOM, "scratch allocation failed");
-  hipError_t e = launch_sum(in->v, reinterpret_cast<unsigned long long *>(dev_result), G, partials, next_slot(),
-                            stream);
+  hipError_t e = launch_sum(in->v, reinterpret_cast<unsigned long long *>(dev_result), G, partials, stream);
   return e == hipSuccess ? MS_OK : hip_fail(e, "kernel launch");
 }
 
@@ -774,9 +793,17 @@ ms_status ms_group_sum(const ms_column *groups, const ms_column *vals, uint32_t 
   if (!lds) e = launch_fill_u64(partials, G_groups, 0ull, stream);
   if (e == hipSuccess)
     e = launch_group_sum(groups->v, vals->v, G_groups, reinterpret_cast<unsigned long long *>(dev_out), G, partials,
-                         next_slot(), stream);
+                         stream);
   return e == hipSuccess ? MS_OK : hip_fail(e, "kernel launch");
 }
+
+void ms_prof_enable(int on) { prof_enable(on != 0); }
+uint64_t ms_prof_count(void) { return prof_count(); }
+ms_status ms_prof_get(uint64_t i, const char **name, float *ms) {
+  if (!name || !ms) return fail(MS_ERR_INVALID_ARG, "NULL argument");
+  return prof_get(i, name, ms) ? MS_OK : fail(MS_ERR_INVALID_ARG, "no such record");
+}
+void ms_prof_reset(void) { prof_reset(); }
 
 ms_status ms_sync(void *stream) {
   ms_status st = check_init();

@@ -80,28 +80,37 @@ __device__ __forceinline__ void extract8(const unsigned *w, unsigned (&v)[8]) {
   }
 }
 
+// The lane's window: byte offset lane*W of the block, i.e. word (lane*W)/4 at bit
+// shift 8*((lane*W) mod 4).  Computed once at run time so that nothing per width is
+// hoisted out of the callers' loops.
+struct Window {
+  unsigned word;  // first word of the lane's window
+  unsigned s;     // bit shift of the first value inside that word (0, 8, 16 or 24)
+};
+__device__ __forceinline__ Window lane_window(unsigned W, unsigned lane) {
+  unsigned byte = lane * W;
+  asm volatile("" : "+v"(byte));  // keep the window per iteration, not per width
+  return Window{byte >> 2, (byte & 3u) * 8u};
+}
+
 template <int W>
-__device__ __forceinline__ void unpack8(const unsigned *__restrict__ blk, unsigned lane, unsigned (&v)[8]) {
+__device__ __forceinline__ void unpack8(const unsigned *__restrict__ p, unsigned s, unsigned lane, unsigned (&v)[8]) {
   if constexpr (W == 0) {
 #pragma unroll
     for (int i = 0; i < 8; i++) v[i] = 0;
   } else if constexpr (W == 32) {
-    const uint4 *p = reinterpret_cast<const uint4 *>(blk) + 2 * lane;
-    uint4 a = p[0], b = p[1];
+    const uint4 *q = reinterpret_cast<const uint4 *>(p);
+    uint4 a = q[0], b = q[1];
     v[0] = a.x; v[1] = a.y; v[2] = a.z; v[3] = a.w;
     v[4] = b.x; v[5] = b.y; v[6] = b.z; v[7] = b.w;
   } else if constexpr (W % 4 == 0) {
-    constexpr int NW = W / 4;  // the lane's window is word aligned
-    const unsigned *p = blk + lane * NW;
+    constexpr int NW = W / 4;  // the lane's window is word aligned (s == 0)
     unsigned w[NW];
 #pragma unroll
     for (int k = 0; k < NW; k++) w[k] = p[k];
     extract8<W>(w, v);
   } else {
     constexpr int NW = (W + 3) / 4;
-    const unsigned byte = lane * W;
-    const unsigned *p = blk + (byte >> 2);
-    const unsigned s = (byte & 3u) * 8u;
     unsigned raw[NW + 1], w[NW];
 #pragma unroll
     for (int k = 0; k <= NW; k++) raw[k] = p[k];
@@ -113,9 +122,11 @@ __device__ __forceinline__ void unpack8(const unsigned *__restrict__ blk, unsign
 
 __device__ __forceinline__ void unpack8_rt(unsigned W, const unsigned *__restrict__ blk, unsigned lane,
                                            unsigned (&v)[8]) {
+  const Window win = lane_window(W, lane);
+  const unsigned *p = blk + win.word;
   switch (W) {
 #define MS_UNPACK_CASE(w) \
-  case w: unpack8<w>(blk, lane, v); break;
+  case w: unpack8<w>(p, win.s, lane, v); break;
     MS_WIDTH_CASES(MS_UNPACK_CASE)
 #undef MS_UNPACK_CASE
     default:
@@ -137,12 +148,12 @@ __device__ __forceinline__ unsigned extract_at(const unsigned *__restrict__ word
 // ---------------------------------------------------------------------------------------------
 // Pack: OR the lane's 8 W-bit values into a zeroed LDS block (16*W words).
 template <int W>
-__device__ __forceinline__ void pack8_lds(unsigned *lds, unsigned lane, const unsigned (&r)[8]) {
+__device__ __forceinline__ void pack8_lds(unsigned *dst, unsigned s, const unsigned (&r)[8]) {
   if constexpr (W == 0) {
     return;
   } else if constexpr (W == 32) {
 #pragma unroll
-    for (int i = 0; i < 8; i++) lds[8 * lane + i] = r[i];
+    for (int i = 0; i < 8; i++) dst[i] = r[i];
   } else {
     constexpr int NW = (W + 3) / 4;
     unsigned w[NW + 1];
@@ -155,13 +166,10 @@ __device__ __forceinline__ void pack8_lds(unsigned *lds, unsigned lane, const un
       w[q] |= r[i] << sh;
       if (sh + W > 32) w[q + 1] |= r[i] >> (32 - sh);
     }
-    const unsigned byte = lane * W;
-    unsigned *dst = lds + (byte >> 2);
     if constexpr (W % 4 == 0) {
 #pragma unroll
       for (int k = 0; k < NW; k++) dst[k] = w[k];  // word-aligned, owned by this lane alone
     } else {
-      const unsigned s = (byte & 3u) * 8u;
       unsigned prev = 0;
 #pragma unroll
       for (int k = 0; k <= NW; k++) {
@@ -175,9 +183,11 @@ __device__ __forceinline__ void pack8_lds(unsigned *lds, unsigned lane, const un
 }
 
 __device__ __forceinline__ void pack8_lds_rt(unsigned W, unsigned *lds, unsigned lane, const unsigned (&r)[8]) {
+  const Window win = lane_window(W, lane);
+  unsigned *dst = lds + win.word;
   switch (W) {
 #define MS_PACK_CASE(w) \
-  case w: pack8_lds<w>(lds, lane, r); break;
+  case w: pack8_lds<w>(dst, win.s, r); break;
     MS_WIDTH_CASES(MS_PACK_CASE)
 #undef MS_PACK_CASE
     default: break;
@@ -235,7 +245,20 @@ __device__ __forceinline__ InCol load_in(const ColView &c) {
   return in;
 }
 
-// First run r with rstarts[r] <= idx (runs are sorted by start, rstarts[0] = 0).
+// Last run r with rstarts[r] <= idx (runs are sorted by start, rstarts[0] = 0), searched
+// in [lo, hi) where the caller knows rstarts[lo] <= idx.
+__device__ __forceinline__ unsigned long long rle_find_in(const InCol &in, unsigned long long idx,
+                                                         unsigned long long lo, unsigned long long hi) {
+  while (hi - lo > 1) {
+    unsigned long long mid = (lo + hi) >> 1;
+    if (in.rstarts[mid] <= idx)
+      lo = mid;
+    else
+      hi = mid;
+  }
+  return lo;
+}
+
 __device__ __forceinline__ unsigned long long rle_find(const InCol &in, unsigned long long idx) {
   unsigned long long lo = 0, hi = in.runs;  // invariant: rstarts[lo] <= idx, answer in [lo, hi)
   while (hi - lo > 1) {
@@ -305,8 +328,15 @@ __device__ __forceinline__ void decode_chunk(const InCol &in, unsigned long long
       break;
     }
     case RLE: {
+      // run of the chunk's first value (one search per wave), then each lane searches
+      // the at most 8*lane + 1 runs between it and its own first value
+      const unsigned long long c0 = c * kBlk;
+      unsigned long long r0 = 0;
+      if (lane == 0 && c0 < in.n) r0 = rle_find(in, c0);
+      r0 = __shfl(r0, 0);
       if (idx0 < in.n) {
-        unsigned long long r = rle_find(in, idx0);
+        const unsigned long long hi = min(in.runs, r0 + 8ull * lane + 1);
+        unsigned long long r = rle_find_in(in, idx0, r0, hi);
 #pragma unroll
         for (int i = 0; i < 8; i++) {
           while (r + 1 < in.runs && in.rstarts[r + 1] <= idx0 + i) r++;
@@ -321,6 +351,124 @@ __device__ __forceinline__ void decode_chunk(const InCol &in, unsigned long long
     default:
 #pragma unroll
       for (int i = 0; i < 8; i++) v[i] = 0;
+  }
+}
+
+// ---------------------------------------------------------------------------------------------
+// Pipelined chunk decode.  issue() starts the global loads of one chunk (coalesced
+// 16-byte loads of the packed block, or the lane's own 8 values when uncompressed)
+// without waiting for them; finish() stages a packed block through the wave's LDS
+// buffer, unpacks the lane's window and applies FOR / DELTA.  Callers issue chunk
+// c + kWaves before finishing chunk c, so two chunks per wave are in flight.
+// Partial chunks, remainders and RLE take the direct path (decode_chunk).
+struct Raw {
+  uint4 q0, q1;
+  unsigned W, base;
+  unsigned mode;  // 0 packed block, 1 uncompressed lane data, 2 direct path
+};
+
+__device__ __forceinline__ Raw issue_chunk(const InCol &in, unsigned long long c, unsigned lane) {
+  Raw r;
+  r.q0 = make_uint4(0, 0, 0, 0);
+  r.q1 = r.q0;
+  r.W = 0;
+  r.base = 0;
+  r.mode = 2;
+  const unsigned long long c0 = c * kBlk;
+  const unsigned *blk = nullptr;
+  switch (in.kind) {
+    case UNCOMPR:
+      if (c0 + kBlk <= in.n) {
+        const uint4 *p = reinterpret_cast<const uint4 *>(in.payload + c0) + 2 * lane;
+        r.q0 = p[0];
+        r.q1 = p[1];
+        r.mode = 1;
+      }
+      return r;
+    case STATIC_BP:
+      if (c0 + kBlk <= in.n_main && in.W <= 32) {
+        r.W = in.W;
+        blk = in.payload + c * 16ull * in.W;
+        r.mode = 0;
+      }
+      break;
+    case DYN_BP:
+    case DELTA_DYN_BP:
+    case FOR_DYN_BP:
+      if (c < in.nb) {
+        unsigned W = in.widths[c];
+        unsigned long long off = in.offsets[c];
+        if (W > 32 || off + 16ull * W > in.payload_cap) {  // a corrupt directory never reads out of bounds
+          raise_err(E_INVALID);
+          W = 0;
+          off = 0;
+        }
+        r.W = W;
+        r.base = (in.kind == DYN_BP) ? 0u : in.bases[c];
+        blk = in.payload + off;
+        r.mode = 0;
+      }
+      break;
+    default: return r;
+  }
+  if (r.mode == 0) {
+    const uint4 *b4 = reinterpret_cast<const uint4 *>(blk);
+    const unsigned nq = 4u * r.W;  // 16-byte pieces of the block
+    if (lane < nq) r.q0 = b4[lane];
+    if (lane + 64 < nq) r.q1 = b4[lane + 64];
+  }
+  return r;
+}
+
+__device__ __forceinline__ void finish_chunk(const InCol &in, const Raw &r, unsigned long long c, unsigned lane,
+                                             unsigned *lds, unsigned (&v)[8]) {
+  if (r.mode == 1) {
+    v[0] = r.q0.x; v[1] = r.q0.y; v[2] = r.q0.z; v[3] = r.q0.w;
+    v[4] = r.q1.x; v[5] = r.q1.y; v[6] = r.q1.z; v[7] = r.q1.w;
+    return;
+  }
+  if (r.mode == 2) {
+    decode_chunk(in, c, lane, v);
+    return;
+  }
+  uint4 *l4 = reinterpret_cast<uint4 *>(lds);
+  const unsigned nq = 4u * r.W;
+  if (lane < nq) l4[lane] = r.q0;
+  if (lane + 64 < nq) l4[lane + 64] = r.q1;
+  wave_sync();
+  unpack8_rt(r.W, lds, lane, v);
+  wave_sync();
+  if (in.kind == FOR_DYN_BP) {
+#pragma unroll
+    for (int i = 0; i < 8; i++) v[i] += r.base;
+  } else if (in.kind == DELTA_DYN_BP) {
+#pragma unroll
+    for (int i = 1; i < 8; i++) v[i] += v[i - 1];
+    const unsigned excl = wave_excl_scan(v[7], lane) + r.base;
+#pragma unroll
+    for (int i = 0; i < 8; i++) v[i] += excl;
+  }
+}
+
+// Walk chunks cb + w, cb + w + kWaves, ... < ce with one chunk of look-ahead;
+// body(c, v) gets the decoded values.  lds: the wave's 512-word buffer.
+template <class Body>
+__device__ __forceinline__ void for_chunks(const InCol &in, unsigned long long cb, unsigned long long ce, unsigned w,
+                                           unsigned lane, unsigned *lds, Body &&body) {
+  unsigned long long c = cb + w;
+  if (c >= ce) return;
+  Raw cur = issue_chunk(in, c, lane);
+  while (true) {
+    const unsigned long long cn = c + kWaves;
+    const bool more = cn < ce;
+    Raw nxt;
+    if (more) nxt = issue_chunk(in, cn, lane);
+    unsigned v[8];
+    finish_chunk(in, cur, c, lane, lds, v);
+    body(c, v);
+    if (!more) break;
+    cur = nxt;
+    c = cn;
   }
 }
 
@@ -361,6 +509,38 @@ __device__ __forceinline__ unsigned value_at(const InCol &in, unsigned long long
     }
     case RLE: return in.rvalues[rle_find(in, idx)];
     default: return 0;
+  }
+}
+
+// Gather: v[i] <- data[v[i]] for the lane's 8 positions (bit i of `valid` set), with the
+// format switch outside the per-value loop so each case unrolls.  Positions >= n read 0
+// and set *bad.
+template <int KIND>
+__device__ __forceinline__ void gather8_kind(const InCol &d, unsigned (&v)[8], unsigned valid, bool &bad) {
+  InCol dk = d;
+  dk.kind = KIND;
+#pragma unroll
+  for (int i = 0; i < 8; i++) {
+    unsigned x = 0;
+    if (valid & (1u << i)) {
+      if (v[i] < d.n)
+        x = value_at(dk, v[i]);
+      else
+        bad = true;
+    }
+    v[i] = x;
+  }
+}
+
+__device__ __forceinline__ void gather8(const InCol &d, unsigned (&v)[8], unsigned valid, bool &bad) {
+  switch (d.kind) {
+    case UNCOMPR: gather8_kind<UNCOMPR>(d, v, valid, bad); break;
+    case STATIC_BP: gather8_kind<STATIC_BP>(d, v, valid, bad); break;
+    case DYN_BP: gather8_kind<DYN_BP>(d, v, valid, bad); break;
+    case DELTA_DYN_BP: gather8_kind<DELTA_DYN_BP>(d, v, valid, bad); break;
+    case FOR_DYN_BP: gather8_kind<FOR_DYN_BP>(d, v, valid, bad); break;
+    case RLE: gather8_kind<RLE>(d, v, valid, bad); break;
+    default: break;
   }
 }
 

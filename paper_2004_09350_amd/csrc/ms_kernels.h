@@ -16,8 +16,17 @@ struct PredArgs {
   unsigned *seg_count;
   unsigned *seg_or;
   unsigned *chunk_first, *chunk_last;
-  unsigned *counters;         // zeroed here for the emit phase
-  unsigned long long n_counters;
+};
+
+struct FinishArgs {
+  ColView out;
+  const ColHdr *n_src;        // element count to record (NULL: keep out's header count)
+  const unsigned *partials;   // {OR of all values, OR of the main part} per workgroup
+  unsigned G;
+  unsigned Wp;                // static BP packing width used by the producer
+  unsigned auto_w;            // static BP auto width: narrow to the main part's width
+  unsigned sorted;
+  unsigned mode;              // 0 finish a produced column, 1 record OR statistics only
 };
 
 struct EmitArgs {
@@ -31,28 +40,31 @@ struct EmitArgs {
   const unsigned *seg_or;
   const unsigned *chunk_first, *chunk_last;
   unsigned *stage_g;          // global staging for blocks shared by several segments
-  unsigned *counters;         // per output block: values staged so far
   unsigned *partials;
-  unsigned slot;
 };
 
 unsigned read_and_clear_err(void *stream);
-hipError_t launch_colstats(const ColView &in, unsigned G, unsigned *partials, unsigned slot, void *s);
+void prof_enable(bool on);
+size_t prof_count();
+bool prof_get(size_t i, const char **name, float *ms);
+void prof_reset();
+hipError_t launch_colstats(const ColView &in, unsigned G, unsigned *partials, void *s);
+hipError_t launch_finish(const FinishArgs &a, void *s);
 hipError_t launch_set_hdr(ColHdr *h, unsigned long long n, unsigned long long runs, unsigned width, unsigned or_all,
                           unsigned or_main, unsigned sorted, void *s);
 hipError_t launch_morph(const ColView &in, const ColView &out, unsigned auto_w, unsigned G, unsigned *partials,
-                        unsigned slot, void *s);
+                        void *s);
 hipError_t launch_decode(const ColView &in, unsigned *out, unsigned G, void *s);
 hipError_t launch_rle(unsigned mode, const ColView &a, const ColView &b, const ColView &out, unsigned G,
-                      unsigned *seg_count, unsigned *partials, unsigned slot, void *s);
+                      unsigned *seg_count, unsigned *partials, void *s);
 hipError_t launch_project(const ColView &pos, const ColView &data, const ColView &out, unsigned auto_w, unsigned G,
-                          unsigned *partials, unsigned slot, void *s);
+                          unsigned *partials, void *s);
 hipError_t launch_pred(const PredArgs &a, unsigned G, void *s);
 hipError_t launch_emit(const EmitArgs &a, unsigned G, void *s);
 hipError_t launch_sum(const ColView &in, unsigned long long *result, unsigned G, unsigned long long *partials,
-                      unsigned slot, void *s);
+                      void *s);
 hipError_t launch_group_sum(const ColView &g, const ColView &v, unsigned groups, unsigned long long *out, unsigned G,
-                            unsigned long long *partials, unsigned slot, void *s);
+                            unsigned long long *partials, void *s);
 hipError_t launch_fill_u32(unsigned *p, unsigned long long n, unsigned v, void *s);
 hipError_t launch_fill_u64(unsigned long long *p, unsigned long long n, unsigned long long v, void *s);
 hipError_t launch_bitmap(const ColView &pos, unsigned long long domain, unsigned *bitmap, unsigned G, void *s);

@@ -3,24 +3,26 @@
 // Every operator decodes its inputs in registers and writes its output directly in
 // the requested format (the paper's on-the-fly de/re-compression, section 3.2, with
 // the input side at register granularity and the output side at block granularity,
-// section 4.2).  Kernels use persistent workgroups; workgroup s owns a contiguous
-// segment of 512-value chunks.
+// section 4.2).  Workgroup s of G owns a contiguous segment of 512-value chunks;
+// its four waves walk the segment's chunks with one chunk of look-ahead.
 //
 // Operators with a data-dependent output count (select, semi-join, intersect) run
-// in two phases: the predicate phase writes one bit per input row plus a count per
+// in phases: the predicate phase writes one bit per input row plus a count per
 // segment; the emit phase derives each segment's output offset from the counts,
-// turns set bits back into positions (or values) and packs complete 512-blocks
-// from LDS.  An output block whose values come from several segments is gathered
-// in a global staging array and packed by the segment that completes it.
+// turns set bits back into positions (or values) and packs the output blocks that
+// lie inside the segment from LDS; blocks shared by neighbouring segments are
+// gathered in a staging array and packed by a fix-up kernel.  No kernel waits on
+// another workgroup: every cross-workgroup dependency is a kernel boundary.
 #include <hip/hip_runtime.h>
 
 #include <algorithm>
+#include <mutex>
+#include <vector>
 
 #include "ms_device.h"
 #include "ms_kernels.h"
 
 namespace ms {
-
 
 // Segment s of G over C chunks.
 __device__ __forceinline__ void segment(unsigned long long C, unsigned s, unsigned G, unsigned long long &cb,
@@ -53,20 +55,8 @@ __device__ __forceinline__ unsigned wg_or(unsigned x, unsigned *sh) {
   return t;
 }
 
-// Arrive at the end of a kernel; returns true in every thread of the last workgroup.
-__device__ __forceinline__ bool fin_arrive(unsigned slot, unsigned G) {
-  __shared__ unsigned s_last;
-  __threadfence();
-  __syncthreads();
-  if (threadIdx.x == 0) {
-    unsigned prev = atomicAdd(&g_ring[slot], 1u);
-    s_last = (prev == G - 1) ? 1u : 0u;
-    if (s_last) atomicExch(&g_ring[slot], 0u);
-  }
-  __syncthreads();
-  const bool last = s_last != 0;
-  if (last) __threadfence();
-  return last;
+__device__ __forceinline__ unsigned valid_mask(unsigned long long idx0, unsigned long long n) {
+  return idx0 >= n ? 0u : (idx0 + 8 <= n ? 0xFFu : ((1u << (unsigned)(n - idx0)) - 1u));
 }
 
 // ---------------------------------------------------------------------------------------------
@@ -130,9 +120,8 @@ __device__ __forceinline__ void encode_dyn_block(const OutCol &o, unsigned long 
   pack_block(W, r, lane, lds, o.c.payload + off);
 }
 
-// Encode output chunk c of a static BP column: `valid` values of the chunk are
-// defined (valid = 512 except for the last chunk); values of the main part are
-// packed at o.W, values past n_main go to the remainder.
+// Encode output chunk c of a static BP column; values of the main part are packed at
+// o.W, values past n_main go to the remainder.
 __device__ __forceinline__ void encode_sbp_chunk(const OutCol &o, unsigned long long c, const unsigned (&v)[8],
                                                  unsigned lane, unsigned *lds, unsigned &or_main) {
   const unsigned long long idx0 = c * kBlk + 8ull * lane;
@@ -197,64 +186,76 @@ __device__ __forceinline__ void write_chunk_known(const OutCol &o, unsigned long
   }
 }
 
-// Narrow a static BP payload in place from width Wf to Wt < Wf (one workgroup,
-// chunk by chunk in increasing order: output chunk c only overlaps input chunks <= c).
-__device__ void narrow_sbp(const ColView &c, unsigned long long n_main, unsigned Wf, unsigned Wt, unsigned *lds_all) {
-  const unsigned lane = lane_id(), w = threadIdx.x >> 6;
-  unsigned *lds = lds_all + w * kBlk;
-  const unsigned long long C = (n_main + kBlk - 1) / kBlk;
-  for (unsigned long long c0 = 0; c0 < C; c0 += kWaves) {
-    const unsigned long long cc = c0 + w;
-    unsigned v[8] = {0, 0, 0, 0, 0, 0, 0, 0};
-    if (cc < C) unpack8_rt(Wf, c.payload + cc * 16ull * Wf, lane, v);
-    __syncthreads();
-    if (cc < C) {
-      const unsigned long long idx0 = cc * kBlk + 8ull * lane;
-#pragma unroll
-      for (int i = 0; i < 8; i++) v[i] = (idx0 + i < n_main) ? v[i] : 0u;
-      pack_block(Wt, v, lane, lds, c.payload + cc * 16ull * Wt);
-    }
-    __syncthreads();
-  }
-}
-
-// Last-workgroup epilogue of every column-producing kernel: reduce per-workgroup
-// partials {or_all, or_main}, write the header, narrow an auto-width static BP column.
-__device__ void finish_column(const ColView &oc, unsigned long long n, unsigned Wp, bool auto_w,
-                              const unsigned *partials, unsigned G, unsigned *lds_all) {
-  __shared__ unsigned s_or[2];
-  unsigned a = 0, m = 0;
-  for (unsigned i = threadIdx.x; i < G; i += kWG) {
-    a |= partials[2 * i];
-    m |= partials[2 * i + 1];
-  }
+// ---------------------------------------------------------------------------------------------
+// Finish: one workgroup after a column-producing kernel.  Reduces the per-workgroup
+// {OR of all values, OR of the main part}, writes the header and, for an auto-width
+// static BP column whose main part needs fewer bits than the provisional width,
+// repacks it in place (chunk by chunk in increasing order: output chunk c only
+// overlaps input chunks <= c).
+__global__ __launch_bounds__(kWG) void k_finish(FinishArgs a) {
+  __shared__ unsigned lds_all[kWaves * kBlk];
   __shared__ unsigned red[kWaves];
-  a = wg_or(a, red);
-  m = wg_or(m, red);
-  if (threadIdx.x == 0) {
-    s_or[0] = a;
-    s_or[1] = m;
+  __shared__ unsigned long long s_n;
+  const unsigned lane = lane_id(), w = threadIdx.x >> 6;
+  unsigned ao = 0, mo = 0;
+  for (unsigned i = threadIdx.x; i < a.G; i += kWG) {
+    ao |= a.partials[2 * i];
+    mo |= a.partials[2 * i + 1];
   }
+  ao = wg_or(ao, red);
+  mo = wg_or(mo, red);
+  if (threadIdx.x == 0) s_n = a.n_src ? a.n_src->n : a.out.hdr->n;
   __syncthreads();
-  unsigned W = Wp;
-  if (oc.kind == STATIC_BP && auto_w) {
-    const unsigned Wt = bw(s_or[1]);
+  const unsigned long long n = s_n;
+  if (a.mode == 1) {  // statistics of an existing column
+    if (threadIdx.x == 0) {
+      a.out.hdr->or_all = ao;
+      a.out.hdr->or_main = mo;
+    }
+    return;
+  }
+  __shared__ unsigned s_wp;
+  if (threadIdx.x == 0) s_wp = (a.out.kind == STATIC_BP && a.auto_w) ? a.out.hdr->sbp_width : a.Wp;
+  __syncthreads();
+  const unsigned Wprov = s_wp;  // the width the producer packed at
+  unsigned W = Wprov;
+  if (a.out.kind == STATIC_BP && a.auto_w) {
+    const unsigned Wt = bw(mo);
     const unsigned long long n_main = n & ~31ull;
-    if (Wt < Wp && n_main > 0) narrow_sbp(oc, n_main, Wp, Wt, lds_all);
+    if (Wt < Wprov && Wprov <= 32 && n_main > 0) {
+      unsigned *lds = lds_all + w * kBlk;
+      const unsigned long long C = (n_main + kBlk - 1) / kBlk;
+      for (unsigned long long c0 = 0; c0 < C; c0 += kWaves) {
+        const unsigned long long cc = c0 + w;
+        unsigned v[8] = {0, 0, 0, 0, 0, 0, 0, 0};
+        if (cc < C) unpack8_rt(Wprov, a.out.payload + cc * 16ull * Wprov, lane, v);
+        __syncthreads();
+        if (cc < C) {
+          const unsigned long long idx0 = cc * kBlk + 8ull * lane;
+#pragma unroll
+          for (int i = 0; i < 8; i++) v[i] = (idx0 + i < n_main) ? v[i] : 0u;
+          pack_block(Wt, v, lane, lds, a.out.payload + cc * 16ull * Wt);
+        }
+        __syncthreads();
+      }
+    }
     W = Wt;
   }
   if (threadIdx.x == 0) {
-    oc.hdr->n = n;
-    oc.hdr->or_all = s_or[0];
-    oc.hdr->or_main = s_or[1];
-    oc.hdr->sbp_width = (oc.kind == STATIC_BP) ? W : 0u;
-    if (oc.kind != RLE) oc.hdr->runs = 0;
+    a.out.hdr->n = n;
+    a.out.hdr->or_all = ao;
+    a.out.hdr->or_main = mo;
+    a.out.hdr->sbp_width = (a.out.kind == STATIC_BP) ? W : 0u;
+    if (a.out.kind != RLE) a.out.hdr->runs = 0;
+    a.out.hdr->sorted = a.sorted;
   }
 }
 
 // ---------------------------------------------------------------------------------------------
 // Column statistics needed by later operators: OR of all values (width bound).
-__global__ __launch_bounds__(kWG) void k_colstats(ColView inv, unsigned *partials, unsigned slot) {
+__global__ __launch_bounds__(kWG) void k_colstats(ColView inv, unsigned *partials) {
+  __shared__ unsigned lds_all[kWaves * kBlk];
+  __shared__ unsigned red[kWaves];
   const InCol in = load_in(inv);
   const unsigned lane = lane_id(), w = threadIdx.x >> 6, G = gridDim.x;
   const unsigned long long C = (in.n + kBlk - 1) / kBlk;
@@ -262,79 +263,58 @@ __global__ __launch_bounds__(kWG) void k_colstats(ColView inv, unsigned *partial
   segment(C, blockIdx.x, G, cb, ce);
   unsigned a = 0, m = 0;
   const unsigned long long nm32 = in.n & ~31ull;
-  for (unsigned long long c = cb + w; c < ce; c += kWaves) {
-    unsigned v[8];
-    decode_chunk(in, c, lane, v);
+  for_chunks(in, cb, ce, w, lane, lds_all + w * kBlk, [&](unsigned long long c, const unsigned (&v)[8]) {
     const unsigned long long idx0 = c * kBlk + 8ull * lane;
 #pragma unroll
     for (int i = 0; i < 8; i++) {
       if (idx0 + i < in.n) a |= v[i];
       if (idx0 + i < nm32) m |= v[i];
     }
-  }
-  __shared__ unsigned red[kWaves];
+  });
   a = wg_or(a, red);
   m = wg_or(m, red);
   if (threadIdx.x == 0) {
     partials[2 * blockIdx.x] = a;
     partials[2 * blockIdx.x + 1] = m;
   }
-  if (fin_arrive(slot, G)) {
-    unsigned aa = 0, mm = 0;
-    for (unsigned i = threadIdx.x; i < G; i += kWG) {
-      aa |= partials[2 * i];
-      mm |= partials[2 * i + 1];
-    }
-    aa = wg_or(aa, red);
-    mm = wg_or(mm, red);
-    if (threadIdx.x == 0) {
-      inv.hdr->or_all = aa;
-      inv.hdr->or_main = mm;
-    }
-  }
 }
 
 // ---------------------------------------------------------------------------------------------
-// Morph (and encode / decode): out = encode_fmt(decode(in)), count known.
-// W_src: 0 = explicit width in out.width; 1 = auto from the input's OR of all values.
-__global__ __launch_bounds__(kWG) void k_morph(ColView inv, ColView outv, unsigned auto_w, unsigned *partials,
-                                               unsigned slot) {
+// Morph (and encode): out = encode_fmt(decode(in)), count known.
+__global__ __launch_bounds__(kWG) void k_morph(ColView inv, ColView outv, unsigned auto_w, unsigned *partials) {
   __shared__ unsigned lds_all[kWaves * kBlk];
+  __shared__ unsigned red[kWaves];
   const InCol in = load_in(inv);
   const unsigned lane = lane_id(), w = threadIdx.x >> 6, G = gridDim.x;
   unsigned Wp = outv.width;
   if (outv.kind == STATIC_BP && auto_w) Wp = bw(inv.hdr->or_all);
   const OutCol o = make_out(outv, in.n, Wp);
+  if (blockIdx.x == 0 && threadIdx.x == 0) outv.hdr->sbp_width = Wp;
   const unsigned long long C = (in.n + kBlk - 1) / kBlk;
   unsigned long long cb, ce;
   segment(C, blockIdx.x, G, cb, ce);
   unsigned or_all = 0, or_main = 0;
   unsigned *lds = lds_all + w * kBlk;
-  for (unsigned long long c = cb + w; c < ce; c += kWaves) {
-    unsigned v[8];
-    decode_chunk(in, c, lane, v);
+  for_chunks(in, cb, ce, w, lane, lds, [&](unsigned long long c, const unsigned (&v)[8]) {
     write_chunk_known(o, c, v, lane, lds, or_all, or_main);
-  }
-  __shared__ unsigned red[kWaves];
+  });
   or_all = wg_or(or_all, red);
   or_main = wg_or(or_main, red);
   if (threadIdx.x == 0) {
     partials[2 * blockIdx.x] = or_all;
     partials[2 * blockIdx.x + 1] = or_main;
   }
-  if (fin_arrive(slot, G)) finish_column(outv, in.n, Wp, auto_w != 0, partials, G, lds_all);
 }
 
 // Decode into a plain device array.
 __global__ __launch_bounds__(kWG) void k_decode(ColView inv, unsigned *__restrict__ out) {
+  __shared__ unsigned lds_all[kWaves * kBlk];
   const InCol in = load_in(inv);
   const unsigned lane = lane_id(), w = threadIdx.x >> 6, G = gridDim.x;
   const unsigned long long C = (in.n + kBlk - 1) / kBlk;
   unsigned long long cb, ce;
   segment(C, blockIdx.x, G, cb, ce);
-  for (unsigned long long c = cb + w; c < ce; c += kWaves) {
-    unsigned v[8];
-    decode_chunk(in, c, lane, v);
+  for_chunks(in, cb, ce, w, lane, lds_all + w * kBlk, [&](unsigned long long c, const unsigned (&v)[8]) {
     const unsigned long long idx0 = c * kBlk + 8ull * lane;
     if (idx0 + 8 <= in.n) {
       uint4 *p = reinterpret_cast<uint4 *>(out + idx0);
@@ -345,38 +325,51 @@ __global__ __launch_bounds__(kWG) void k_decode(ColView inv, unsigned *__restric
       for (int i = 0; i < 8; i++)
         if (idx0 + i < in.n) out[idx0 + i] = v[i];
     }
+  });
+}
+
+// ---------------------------------------------------------------------------------------------
+// Project: out_j = data[pos_j].
+__global__ __launch_bounds__(kWG) void k_project(ColView posv, ColView datav, ColView outv, unsigned auto_w,
+                                                 unsigned *partials) {
+  __shared__ unsigned lds_all[kWaves * kBlk];
+  __shared__ unsigned red[kWaves];
+  const InCol ip = load_in(posv);
+  const InCol id = load_in(datav);
+  const unsigned lane = lane_id(), w = threadIdx.x >> 6, G = gridDim.x;
+  unsigned Wp = outv.width;
+  if (outv.kind == STATIC_BP && auto_w) Wp = bw(datav.hdr->or_all);
+  const OutCol o = make_out(outv, ip.n, Wp);
+  if (blockIdx.x == 0 && threadIdx.x == 0) outv.hdr->sbp_width = Wp;
+  const unsigned long long C = (ip.n + kBlk - 1) / kBlk;
+  unsigned long long cb, ce;
+  segment(C, blockIdx.x, G, cb, ce);
+  unsigned or_all = 0, or_main = 0;
+  unsigned *lds = lds_all + w * kBlk;
+  bool bad = false;
+  for_chunks(ip, cb, ce, w, lane, lds, [&](unsigned long long c, const unsigned (&pv)[8]) {
+    unsigned v[8];
+#pragma unroll
+    for (int i = 0; i < 8; i++) v[i] = pv[i];
+    gather8(id, v, valid_mask(c * kBlk + 8ull * lane, ip.n), bad);
+    write_chunk_known(o, c, v, lane, lds, or_all, or_main);
+  });
+  if (bad) raise_err(E_RANGE);
+  or_all = wg_or(or_all, red);
+  or_main = wg_or(or_main, red);
+  if (threadIdx.x == 0) {
+    partials[2 * blockIdx.x] = or_all;
+    partials[2 * blockIdx.x + 1] = or_main;
   }
 }
 
 // ---------------------------------------------------------------------------------------------
 // RLE output for count-known producers (morph, project): phase 1 counts run starts per
-// segment, phase 2 writes (value, start) pairs.  `src` yields chunk values.
+// segment, phase 2 writes (value, start) pairs.
 struct ChunkSrc {
   unsigned mode;   // 0 = decode column `a`; 1 = project: a = positions, b = data
   ColView a, b;
 };
-
-__device__ __forceinline__ unsigned long long src_n(const ChunkSrc &s) { return s.a.hdr->n; }
-
-__device__ __forceinline__ void src_chunk(const ChunkSrc &s, const InCol &ia, const InCol &ib, unsigned long long c,
-                                          unsigned lane, unsigned (&v)[8]) {
-  decode_chunk(ia, c, lane, v);
-  if (s.mode == 1) {
-    const unsigned long long idx0 = c * kBlk + 8ull * lane;
-#pragma unroll
-    for (int i = 0; i < 8; i++) {
-      if (idx0 + i < ia.n) {
-        const unsigned p = v[i];
-        if (p < ib.n) {
-          v[i] = value_at(ib, p);
-        } else {
-          raise_err(E_RANGE);
-          v[i] = 0;
-        }
-      }
-    }
-  }
-}
 
 __device__ __forceinline__ unsigned src_value(const ChunkSrc &s, const InCol &ia, const InCol &ib,
                                               unsigned long long idx) {
@@ -385,38 +378,51 @@ __device__ __forceinline__ unsigned src_value(const ChunkSrc &s, const InCol &ia
   return x;
 }
 
+// Run starts among the lane's 8 values (bit i set when value i starts a run).
+__device__ __forceinline__ unsigned run_flags(const ChunkSrc &s, const InCol &ia, const InCol &ib,
+                                              unsigned long long c, unsigned lane, const unsigned (&v)[8]) {
+  const unsigned long long idx0 = c * kBlk + 8ull * lane;
+  unsigned prev = __shfl_up(v[7], 1);
+  if (lane == 0) prev = (c > 0) ? src_value(s, ia, ib, c * kBlk - 1) : ~v[0];
+  unsigned flags = 0;
+#pragma unroll
+  for (int i = 0; i < 8; i++) {
+    const unsigned pv = i ? v[i - 1] : prev;
+    if (idx0 + i < ia.n && (idx0 + i == 0 || v[i] != pv)) flags |= 1u << i;
+  }
+  return flags;
+}
+
 __global__ __launch_bounds__(kWG) void k_rle_count(ChunkSrc s, unsigned *seg_count) {
+  __shared__ unsigned lds_all[kWaves * kBlk];
+  __shared__ unsigned long long red[kWaves];
   const InCol ia = load_in(s.a);
   InCol ib = ia;
   if (s.mode == 1) ib = load_in(s.b);
   const unsigned lane = lane_id(), w = threadIdx.x >> 6, G = gridDim.x;
-  const unsigned long long n = ia.n;
-  const unsigned long long C = (n + kBlk - 1) / kBlk;
+  const unsigned long long C = (ia.n + kBlk - 1) / kBlk;
   unsigned long long cb, ce;
   segment(C, blockIdx.x, G, cb, ce);
   unsigned cnt = 0;
-  for (unsigned long long c = cb + w; c < ce; c += kWaves) {
+  bool bad = false;
+  unsigned *lds = lds_all + w * kBlk;
+  for_chunks(ia, cb, ce, w, lane, lds, [&](unsigned long long c, const unsigned (&dv)[8]) {
     unsigned v[8];
-    src_chunk(s, ia, ib, c, lane, v);
-    const unsigned long long idx0 = c * kBlk + 8ull * lane;
-    unsigned prev = __shfl_up(v[7], 1);
-    if (lane == 0) prev = (c > 0) ? src_value(s, ia, ib, c * kBlk - 1) : ~v[0];
 #pragma unroll
-    for (int i = 0; i < 8; i++) {
-      const unsigned pv = i ? v[i - 1] : prev;
-      if (idx0 + i < n && (idx0 + i == 0 || v[i] != pv)) cnt++;
-    }
-  }
-  __shared__ unsigned long long red[kWaves];
+    for (int i = 0; i < 8; i++) v[i] = dv[i];
+    if (s.mode == 1) gather8(ib, v, valid_mask(c * kBlk + 8ull * lane, ia.n), bad);
+    cnt += __popc(run_flags(s, ia, ib, c, lane, v));
+  });
   const unsigned long long t = wg_add64(cnt, red);
   if (threadIdx.x == 0) seg_count[blockIdx.x] = (unsigned)t;
 }
 
 __global__ __launch_bounds__(kWG) void k_rle_emit(ChunkSrc s, ColView outv, const unsigned *seg_count,
-                                                  unsigned *partials, unsigned slot) {
+                                                  unsigned *partials) {
   __shared__ unsigned lds_all[kWaves * kBlk];
   __shared__ unsigned long long red[kWaves];
   __shared__ unsigned s_chunk_runs[kWaves];
+  __shared__ unsigned redu[kWaves];
   const InCol ia = load_in(s.a);
   InCol ib = ia;
   if (s.mode == 1) ib = load_in(s.b);
@@ -432,26 +438,31 @@ __global__ __launch_bounds__(kWG) void k_rle_emit(ChunkSrc s, ColView outv, cons
   }
   before = wg_add64(before, red);
   total = wg_add64(total, red);
+  if (blockIdx.x == 0 && threadIdx.x == 0) {
+    outv.hdr->n = n;
+    outv.hdr->runs = total;
+  }
   unsigned or_all = 0;
+  bool bad = false;
+  unsigned *lds = lds_all + w * kBlk;
   // Chunks are taken in order, kWaves at a time, so run indices stay ordered.
   unsigned long long base = before;
+  Raw cur;
+  if (cb + w < ce) cur = issue_chunk(ia, cb + w, lane);
   for (unsigned long long c0 = cb; c0 < ce; c0 += kWaves) {
     const unsigned long long c = c0 + w;
+    Raw nxt;
+    if (c + kWaves < ce) nxt = issue_chunk(ia, c + kWaves, lane);
     unsigned v[8] = {0, 0, 0, 0, 0, 0, 0, 0};
     unsigned flags = 0;
     if (c < ce) {
-      src_chunk(s, ia, ib, c, lane, v);
+      finish_chunk(ia, cur, c, lane, lds, v);
+      if (s.mode == 1) gather8(ib, v, valid_mask(c * kBlk + 8ull * lane, n), bad);
+      flags = run_flags(s, ia, ib, c, lane, v);
       const unsigned long long idx0 = c * kBlk + 8ull * lane;
-      unsigned prev = __shfl_up(v[7], 1);
-      if (lane == 0) prev = (c > 0) ? src_value(s, ia, ib, c * kBlk - 1) : ~v[0];
 #pragma unroll
-      for (int i = 0; i < 8; i++) {
-        const unsigned pv = i ? v[i - 1] : prev;
-        if (idx0 + i < n) {
-          or_all |= v[i];
-          if (idx0 + i == 0 || v[i] != pv) flags |= 1u << i;
-        }
-      }
+      for (int i = 0; i < 8; i++)
+        if (idx0 + i < n) or_all |= v[i];
     }
     const unsigned cnt = __popc(flags);
     const unsigned off = wave_excl_scan(cnt, lane);
@@ -480,60 +491,14 @@ __global__ __launch_bounds__(kWG) void k_rle_emit(ChunkSrc s, ColView outv, cons
       }
     }
     base = all;
+    cur = nxt;
   }
-  __shared__ unsigned redu[kWaves];
+  if (bad) raise_err(E_RANGE);
   or_all = wg_or(or_all, redu);
   if (threadIdx.x == 0) {
     partials[2 * blockIdx.x] = or_all;
     partials[2 * blockIdx.x + 1] = 0;
   }
-  if (fin_arrive(slot, G)) {
-    finish_column(outv, n, 0, false, partials, G, lds_all);
-    if (threadIdx.x == 0) outv.hdr->runs = total;
-  }
-}
-
-// ---------------------------------------------------------------------------------------------
-// Project: out_j = data[pos_j].
-__global__ __launch_bounds__(kWG) void k_project(ColView posv, ColView datav, ColView outv, unsigned auto_w,
-                                                 unsigned *partials, unsigned slot) {
-  __shared__ unsigned lds_all[kWaves * kBlk];
-  const InCol ip = load_in(posv);
-  const InCol id = load_in(datav);
-  const unsigned lane = lane_id(), w = threadIdx.x >> 6, G = gridDim.x;
-  unsigned Wp = outv.width;
-  if (outv.kind == STATIC_BP && auto_w) Wp = bw(datav.hdr->or_all);
-  const OutCol o = make_out(outv, ip.n, Wp);
-  const unsigned long long C = (ip.n + kBlk - 1) / kBlk;
-  unsigned long long cb, ce;
-  segment(C, blockIdx.x, G, cb, ce);
-  unsigned or_all = 0, or_main = 0;
-  unsigned *lds = lds_all + w * kBlk;
-  for (unsigned long long c = cb + w; c < ce; c += kWaves) {
-    unsigned v[8];
-    decode_chunk(ip, c, lane, v);
-    const unsigned long long idx0 = c * kBlk + 8ull * lane;
-#pragma unroll
-    for (int i = 0; i < 8; i++) {
-      unsigned x = 0;
-      if (idx0 + i < ip.n) {
-        if (v[i] < id.n)
-          x = value_at(id, v[i]);
-        else
-          raise_err(E_RANGE);
-      }
-      v[i] = x;
-    }
-    write_chunk_known(o, c, v, lane, lds, or_all, or_main);
-  }
-  __shared__ unsigned red[kWaves];
-  or_all = wg_or(or_all, red);
-  or_main = wg_or(or_main, red);
-  if (threadIdx.x == 0) {
-    partials[2 * blockIdx.x] = or_all;
-    partials[2 * blockIdx.x + 1] = or_main;
-  }
-  if (fin_arrive(slot, G)) finish_column(outv, ip.n, Wp, auto_w != 0, partials, G, lds_all);
 }
 
 // ---------------------------------------------------------------------------------------------
@@ -542,32 +507,32 @@ __global__ __launch_bounds__(kWG) void k_project(ColView posv, ColView datav, Co
 // mode 1: bitmap predicate v < domain && bit(v), emits positions (semi-join)
 // mode 2: bitmap predicate on values, emits values, checks strict increase (intersect)
 __global__ __launch_bounds__(kWG) void k_pred(PredArgs a) {
+  __shared__ unsigned lds_all[kWaves * kBlk];
+  __shared__ unsigned long long red[kWaves];
+  __shared__ unsigned redo[kWaves];
   const InCol in = load_in(a.in);
   const unsigned lane = lane_id(), w = threadIdx.x >> 6, G = gridDim.x;
   const unsigned long long C = (in.n + kBlk - 1) / kBlk;
   unsigned long long cb, ce;
   segment(C, blockIdx.x, G, cb, ce);
-  // zero the staging counters of the emit phase
-  for (unsigned long long i = (unsigned long long)blockIdx.x * kWG + threadIdx.x; i < a.n_counters;
-       i += (unsigned long long)G * kWG)
-    a.counters[i] = 0;
   unsigned cnt = 0, orv = 0;
-  for (unsigned long long c = cb + w; c < ce; c += kWaves) {
-    unsigned v[8];
-    decode_chunk(in, c, lane, v);
+  bool unsorted = false;
+  for_chunks(in, cb, ce, w, lane, lds_all + w * kBlk, [&](unsigned long long c, const unsigned (&v)[8]) {
     const unsigned long long idx0 = c * kBlk + 8ull * lane;
+    const unsigned valid = valid_mask(idx0, in.n);
     unsigned mask = 0;
+    if (a.mode == 0) {
 #pragma unroll
-    for (int i = 0; i < 8; i++) {
-      bool p;
-      if (a.mode == 0) {
-        p = ((v[i] - a.lo) <= a.span) != (a.neg != 0);
-      } else {
+      for (int i = 0; i < 8; i++)
+        if (((v[i] - a.lo) <= a.span) != (a.neg != 0)) mask |= 1u << i;
+    } else {
+#pragma unroll
+      for (int i = 0; i < 8; i++) {
         const unsigned x = v[i];
-        p = (unsigned long long)x < a.domain && ((a.bitmap[x >> 5] >> (x & 31)) & 1u);
+        if ((unsigned long long)x < a.domain && ((a.bitmap[x >> 5] >> (x & 31)) & 1u)) mask |= 1u << i;
       }
-      if (idx0 + i < in.n && p) mask |= 1u << i;
     }
+    mask &= valid;
     a.bitmask[c * 64 + lane] = (unsigned char)mask;
     cnt += __popc(mask);
     if (a.mode == 2) {
@@ -579,21 +544,22 @@ __global__ __launch_bounds__(kWG) void k_pred(PredArgs a) {
 #pragma unroll
       for (int i = 0; i < 8; i++) {
         const unsigned pv = i ? v[i - 1] : prev;
-        if (idx0 + i < in.n && (i > 0 || lane > 0) && v[i] <= pv) raise_err(E_NOT_SORTED);
+        if (((valid >> i) & 1u) && (i > 0 || lane > 0) && v[i] <= pv) unsorted = true;
       }
       const unsigned long long last_idx = min(in.n, (c + 1) * kBlk) - 1;
       if (lane == 0) a.chunk_first[c] = v[0];
-      if (idx0 <= last_idx && last_idx < idx0 + 8) a.chunk_last[c] = v[last_idx - idx0];
-    } else if (mask) {
-      unsigned bits = 0;
+      if (idx0 <= last_idx && last_idx < idx0 + 8) {
+        unsigned lv = v[0];
 #pragma unroll
-      for (int i = 0; i < 8; i++)
-        if (mask & (1u << i)) bits |= (unsigned)i;
-      orv |= (unsigned)idx0 | bits;
+        for (int i = 1; i < 8; i++)
+          if (idx0 + i == last_idx) lv = v[i];
+        a.chunk_last[c] = lv;
+      }
+    } else if (mask) {
+      orv |= (unsigned)idx0 | (31u - __clz(mask));  // positions: bit width of the largest
     }
-  }
-  __shared__ unsigned long long red[kWaves];
-  __shared__ unsigned redo[kWaves];
+  });
+  if (unsorted) raise_err(E_NOT_SORTED);
   const unsigned long long t = wg_add64(cnt, red);
   orv = wg_or(orv, redo);
   if (threadIdx.x == 0) {
@@ -607,20 +573,39 @@ __global__ __launch_bounds__(kWG) void k_pred(PredArgs a) {
 constexpr int kEmitChunks = 8;                 // chunks per emit tile (2 per wave)
 constexpr int kStage = kEmitChunks * kBlk + kBlk;
 
-// Block structure of a compaction output: blocks of 512 over [0, Nb) where Nb = n_main
-// for the DynBP family (the rest is remainder) and N for static BP (last block partial).
+// Output blocks of a compaction: 512-blocks over [0, Nb), Nb = n_main for the DynBP
+// family (the rest is remainder) and N for static BP (the last block may be partial).
 __device__ __forceinline__ unsigned long long blk_end(unsigned long long k, unsigned long long Nb) {
   return min((k + 1) * (unsigned long long)kBlk, Nb);
 }
 
-// Encode block k of a compaction output from v (8 per lane); `len` values valid.
 __device__ __forceinline__ void encode_out_block(const OutCol &o, unsigned long long k, const unsigned (&v)[8],
                                                  unsigned lane, unsigned *lds, unsigned &or_main) {
-  if (o.c.kind == STATIC_BP) {
+  if (o.c.kind == STATIC_BP)
     encode_sbp_chunk(o, k, v, lane, lds, or_main);
-  } else {
+  else
     encode_dyn_block(o, k, v, lane, lds);
+}
+
+// Offsets of segment `seg` from the phase-1 counts: O (outputs before it), N (total),
+// OR of every segment's OR.
+__device__ __forceinline__ void seg_offsets(const unsigned *seg_count, const unsigned *seg_or, unsigned seg,
+                                            unsigned G, unsigned long long &O, unsigned long long &N, unsigned &orv,
+                                            unsigned long long *red, unsigned *redo) {
+  unsigned long long before = 0, total = 0;
+  unsigned o = 0;
+  for (unsigned i = threadIdx.x; i < G; i += kWG) {
+    total += seg_count[i];
+    if (i < seg) before += seg_count[i];
+    o |= seg_or[i];
   }
+  O = wg_add64(before, red);
+  N = wg_add64(total, red);
+  orv = wg_or(o, redo);
+}
+
+__device__ __forceinline__ unsigned emit_width(const EmitArgs &a, unsigned orv) {
+  return (a.out.kind == STATIC_BP && a.auto_w) ? bw(orv) : a.out.width;
 }
 
 __global__ __launch_bounds__(kWG) void k_emit(EmitArgs a) {
@@ -629,60 +614,48 @@ __global__ __launch_bounds__(kWG) void k_emit(EmitArgs a) {
   __shared__ unsigned s_ctot[kEmitChunks];
   __shared__ unsigned long long red[kWaves];
   __shared__ unsigned redo[kWaves];
-  __shared__ unsigned s_flag;
   const InCol in = load_in(a.in);
   const unsigned lane = lane_id(), w = threadIdx.x >> 6, G = gridDim.x, seg = blockIdx.x;
   const unsigned long long C = (in.n + kBlk - 1) / kBlk;
   unsigned long long cb, ce;
   segment(C, seg, G, cb, ce);
-
-  // Offsets from the phase-1 counts.
-  unsigned long long before = 0, total = 0;
-  unsigned orv = 0;
-  for (unsigned i = threadIdx.x; i < G; i += kWG) {
-    total += a.seg_count[i];
-    if (i < seg) before += a.seg_count[i];
-    orv |= a.seg_or[i];
-  }
-  before = wg_add64(before, red);
-  total = wg_add64(total, red);
-  orv = wg_or(orv, redo);
-  const unsigned long long O = before, N = total;
-  unsigned Wp = a.out.width;
-  if (a.out.kind == STATIC_BP && a.auto_w) Wp = bw(orv);
+  unsigned long long O, N;
+  unsigned orv;
+  seg_offsets(a.seg_count, a.seg_or, seg, G, O, N, orv, red, redo);
+  const unsigned Wp = emit_width(a, orv);
   const OutCol o = make_out(a.out, N, Wp);
   const unsigned kind = a.out.kind;
   const bool blocky = (kind == STATIC_BP || kind == DYN_BP || kind == DELTA_DYN_BP || kind == FOR_DYN_BP);
   const unsigned long long Nb = (kind == STATIC_BP) ? N : o.n_main;   // block elements are [0, Nb)
-
-  const unsigned long long mycnt = a.seg_count[seg];
-  const unsigned long long E = O + mycnt;       // end (exclusive) of this segment's outputs
-  // Owned blocks: fully inside [O, E) and below Nb.
+  if (seg == 0 && threadIdx.x == 0) {
+    a.out.hdr->n = N;
+    a.out.hdr->or_all = orv;
+    a.out.hdr->sorted = 1;
+    a.out.hdr->runs = (kind == RLE) ? N : 0ull;
+    a.out.hdr->sbp_width = (kind == STATIC_BP) ? Wp : 0u;
+  }
+  const unsigned long long E = O + a.seg_count[seg];   // this segment's outputs are [O, E)
+  // Owned blocks lie entirely inside [O, E) and below Nb; all other block elements are staged.
   unsigned long long A = 0, B = 0;
   if (blocky) {
     const unsigned long long Eb = min(E, Nb);
     const unsigned long long kA = (O + kBlk - 1) / kBlk;
-    unsigned long long kB1;  // one past the last owned block
-    if (Eb == Nb && Nb > 0)
-      kB1 = (Nb + kBlk - 1) / kBlk;
-    else
-      kB1 = Eb / kBlk;
+    const unsigned long long kB1 = (Eb == Nb && Nb > 0) ? (Nb + kBlk - 1) / kBlk : Eb / kBlk;
     if (O >= Nb || kA >= kB1) {
-      A = B = (O < Nb) ? O : Nb;  // nothing owned
+      A = B = (O < Nb) ? O : Nb;
     } else {
       A = kA * kBlk;
       B = blk_end(kB1 - 1, Nb);
     }
   }
-  // sortedness across chunk ends (intersect inputs)
   if (a.check_sorted) {
     for (unsigned long long c = cb + threadIdx.x; c < ce; c += kWG)
       if (c > 0 && a.chunk_first[c] <= a.chunk_last[c - 1]) raise_err(E_NOT_SORTED);
   }
 
-  unsigned or_all = 0, or_main = 0;
+  unsigned or_main = 0;
   unsigned long long emitted = 0;   // outputs of this segment so far
-  unsigned long long Lbase = A;     // global index of stage[0] (owned elements only)
+  unsigned long long Lbase = A;     // global index of stage[0]
   unsigned *lds = lds_all + w * kBlk;
   const unsigned long long n_main_o = o.n_main;
 
@@ -703,24 +676,27 @@ __global__ __launch_bounds__(kWG) void k_emit(EmitArgs a) {
       if (lane == 63) s_ctot[lc] = off[j] + cntl;
     }
     __syncthreads();
-    unsigned long long tile_base = 0, tile_total = 0, cbase[2] = {0, 0};
+    unsigned long long tile_total = 0, cbase[2] = {0, 0};
     for (unsigned lc = 0; lc < kEmitChunks; lc++) {
       if (lc == 2 * w) cbase[0] = tile_total;
       if (lc == 2 * w + 1) cbase[1] = tile_total;
       tile_total += s_ctot[lc];
     }
-    (void)tile_base;
 #pragma unroll
     for (int j = 0; j < 2; j++) {
       const unsigned long long c = t0 + 2 * w + j;
-      if (c >= ce || !msk[j]) continue;
+      unsigned m = msk[j];
       unsigned long long g = O + emitted + cbase[j] + off[j];
       const unsigned long long idx0 = c * kBlk + 8ull * lane;
+      while (m) {
+        const unsigned i = __ffs(m) - 1;
+        m &= m - 1;
+        unsigned val = (unsigned)(idx0 + i);
+        if (a.emit_values) {
 #pragma unroll
-      for (int i = 0; i < 8; i++) {
-        if (!(msk[j] & (1u << i))) continue;
-        const unsigned val = a.emit_values ? v[j][i] : (unsigned)(idx0 + i);
-        or_all |= val;
+          for (int q = 0; q < 8; q++)
+            if (q == (int)i) val = v[j][q];
+        }
         if (g < n_main_o) or_main |= val;
         if (g >= a.out.n_cap) {
           raise_err(E_INVALID);
@@ -732,7 +708,7 @@ __global__ __launch_bounds__(kWG) void k_emit(EmitArgs a) {
         } else if (g >= Nb) {
           a.out.rem[g - Nb] = val;             // DynBP-family remainder
         } else if (g < A || g >= B) {
-          a.stage_g[g] = val;                  // shared block
+          a.stage_g[g] = val;                  // block shared with a neighbouring segment
         } else {
           const unsigned long long li = g - Lbase;
           if (li < (unsigned long long)kStage)
@@ -749,9 +725,8 @@ __global__ __launch_bounds__(kWG) void k_emit(EmitArgs a) {
       const unsigned long long have_end = min(O + emitted, B);
       if (have_end > Lbase) {
         const unsigned long long have = have_end - Lbase;
-        unsigned long long nfull = have / kBlk;
-        // the final block of the output may be partial and ends at B
-        const bool final_partial = (have_end == B) && (have % kBlk != 0);
+        const unsigned long long nfull = have / kBlk;
+        const bool final_partial = (have_end == B) && (have % kBlk != 0);  // last block of the output
         const unsigned long long nenc = nfull + (final_partial ? 1 : 0);
         for (unsigned long long j = w; j < nenc; j += kWaves) {
           unsigned x[8];
@@ -773,84 +748,54 @@ __global__ __launch_bounds__(kWG) void k_emit(EmitArgs a) {
       }
     }
   }
-  // Shared blocks: contribute counts; the contributor that completes a block packs it.
-  if (blocky) {
-    const unsigned long long Eb = min(E, Nb);
-    unsigned long long ks[2];
-    unsigned long long kc[2];
-    int nk = 0;
-    if (O < Nb) {
-      if (A == B) {  // no owned block: [O, Eb) spans at most two blocks
-        unsigned long long k = O / kBlk;
-        while (k * kBlk < Eb && nk < 2) {
-          const unsigned long long lo = max(O, k * kBlk), hi = min(Eb, blk_end(k, Nb));
-          ks[nk] = k;
-          kc[nk] = hi - lo;
-          nk++;
-          k++;
-        }
-      } else {
-        if (O < A) {
-          ks[nk] = O / kBlk;
-          kc[nk] = A - O;
-          nk++;
-        }
-        if (B < Eb) {
-          ks[nk] = B / kBlk;
-          kc[nk] = Eb - B;
-          nk++;
-        }
-      }
-    }
-    for (int q = 0; q < nk; q++) {
-      const unsigned long long k = ks[q];
-      const unsigned long long target = blk_end(k, Nb) - k * kBlk;
-      __threadfence();
-      __syncthreads();
-      if (threadIdx.x == 0) {
-        const unsigned prev = atomicAdd(&a.counters[k], (unsigned)kc[q]);
-        s_flag = (prev + kc[q] == target) ? 1u : 0u;
-      }
-      __syncthreads();
-      if (s_flag) {
-        __threadfence();
-        if (w == 0) {
-          unsigned x[8];
-#pragma unroll
-          for (int i = 0; i < 8; i++) {
-            const unsigned long long li = 8ull * lane + i;
-            x[i] = (li < target) ? __hip_atomic_load(&a.stage_g[k * kBlk + li], __ATOMIC_RELAXED,
-                                                     __HIP_MEMORY_SCOPE_AGENT)
-                                 : 0u;
-          }
-          encode_out_block(o, k, x, lane, lds, or_main);
-        }
-      }
-      __syncthreads();
-    }
-  }
-  or_all = wg_or(or_all, redo);
   or_main = wg_or(or_main, redo);
   if (threadIdx.x == 0) {
-    a.partials[2 * seg] = or_all;
+    a.partials[2 * seg] = orv;
     a.partials[2 * seg + 1] = or_main;
   }
-  if (fin_arrive(a.slot, G)) {
-    finish_column(a.out, N, Wp, a.auto_w != 0, a.partials, G, lds_all);
-    if (threadIdx.x == 0) {
-      if (kind == RLE) a.out.hdr->runs = N;
-      a.out.hdr->sorted = 1;
+}
+
+// Compaction phase 3 (block formats): a block that started in an earlier segment is
+// packed from the staging array by the segment that holds its last element.
+__global__ __launch_bounds__(kWG) void k_emit_fix(EmitArgs a) {
+  __shared__ unsigned lds_all[kWaves * kBlk];
+  __shared__ unsigned long long red[kWaves];
+  __shared__ unsigned redo[kWaves];
+  const unsigned lane = lane_id(), w = threadIdx.x >> 6, G = gridDim.x, seg = blockIdx.x;
+  unsigned long long O, N;
+  unsigned orv;
+  seg_offsets(a.seg_count, a.seg_or, seg, G, O, N, orv, red, redo);
+  const unsigned long long E = O + a.seg_count[seg];
+  const unsigned Wp = emit_width(a, orv);
+  const OutCol o = make_out(a.out, N, Wp);
+  const unsigned long long Nb = (a.out.kind == STATIC_BP) ? N : o.n_main;
+  const unsigned long long Eb = min(E, Nb);
+  if (Eb <= O) return;  // no block element in this segment
+  // Only the block holding the segment's first output can have started in an earlier
+  // segment; it is packed here when it also ends inside this segment.
+  const unsigned long long k = O / kBlk;
+  const unsigned long long end = blk_end(k, Nb);
+  if (k * kBlk == O || end > Eb) return;
+  if (w == 0) {
+    const unsigned long long len = end - k * kBlk;
+    unsigned x[8];
+#pragma unroll
+    for (int i = 0; i < 8; i++) {
+      const unsigned long long li = 8ull * lane + i;
+      x[i] = (li < len) ? a.stage_g[k * kBlk + li] : 0u;
     }
+    unsigned om = 0;
+    encode_out_block(o, k, x, lane, lds_all, om);
   }
 }
 
 // ---------------------------------------------------------------------------------------------
 // Sum and group-sum.
-__global__ __launch_bounds__(kWG) void k_sum(ColView inv, unsigned long long *result,
-                                             unsigned long long *partials, unsigned slot) {
+__global__ __launch_bounds__(kWG) void k_sum(ColView inv, unsigned long long *partials) {
+  __shared__ unsigned lds_all[kWaves * kBlk];
+  __shared__ unsigned long long red[kWaves];
   const InCol in = load_in(inv);
   const unsigned lane = lane_id(), w = threadIdx.x >> 6, G = gridDim.x;
-  __shared__ unsigned long long red[kWaves];
   unsigned long long s = 0;
   if (in.kind == RLE) {
     // sum over runs: value * run length (section 2.2)
@@ -865,42 +810,37 @@ __global__ __launch_bounds__(kWG) void k_sum(ColView inv, unsigned long long *re
     const unsigned long long C = (in.n + kBlk - 1) / kBlk;
     unsigned long long cb, ce;
     segment(C, blockIdx.x, G, cb, ce);
-    for (unsigned long long c = cb + w; c < ce; c += kWaves) {
-      unsigned v[8];
-      decode_chunk(in, c, lane, v);
-      const unsigned long long idx0 = c * kBlk + 8ull * lane;
-      if (idx0 + 8 <= in.n) {
+    for_chunks(in, cb, ce, w, lane, lds_all + w * kBlk, [&](unsigned long long c, const unsigned (&v)[8]) {
+      const unsigned valid = valid_mask(c * kBlk + 8ull * lane, in.n);
+      unsigned long long t = 0;
 #pragma unroll
-        for (int i = 0; i < 8; i++) s += v[i];
-      } else {
-#pragma unroll
-        for (int i = 0; i < 8; i++)
-          if (idx0 + i < in.n) s += v[i];
-      }
-    }
+      for (int i = 0; i < 8; i++) t += ((valid >> i) & 1u) ? v[i] : 0u;
+      s += t;
+    });
   }
   s = wg_add64(s, red);
   if (threadIdx.x == 0) partials[blockIdx.x] = s;
-  if (fin_arrive(slot, G)) {
-    unsigned long long t = 0;
-    for (unsigned i = threadIdx.x; i < G; i += kWG) t += partials[i];
-    t = wg_add64(t, red);
-    if (threadIdx.x == 0) *result = t;
-  }
+}
+
+__global__ __launch_bounds__(kWG) void k_sum_finish(const unsigned long long *partials, unsigned G,
+                                                    unsigned long long *result) {
+  __shared__ unsigned long long red[kWaves];
+  unsigned long long t = 0;
+  for (unsigned i = threadIdx.x; i < G; i += kWG) t += partials[i];
+  t = wg_add64(t, red);
+  if (threadIdx.x == 0) *result = t;
 }
 
 constexpr unsigned kMaxLdsGroups = 4096;
 
 __global__ __launch_bounds__(kWG) void k_group_sum(ColView gv, ColView vv, unsigned G_groups,
-                                                   unsigned long long *out, unsigned long long *partials,
-                                                   unsigned slot) {
+                                                   unsigned long long *partials) {
   __shared__ unsigned long long hist[kMaxLdsGroups];
+  __shared__ unsigned lds_all[2 * kWaves * kBlk];
   const InCol ig = load_in(gv);
   const InCol iv = load_in(vv);
   const unsigned lane = lane_id(), w = threadIdx.x >> 6, G = gridDim.x;
-  if (ig.n != iv.n) {
-    if (blockIdx.x == 0 && threadIdx.x == 0) raise_err(E_LENGTH);
-  }
+  if (ig.n != iv.n && blockIdx.x == 0 && threadIdx.x == 0) raise_err(E_LENGTH);
   const unsigned long long n = min(ig.n, iv.n);
   const bool use_lds = G_groups <= kMaxLdsGroups;
   for (unsigned i = threadIdx.x; i < kMaxLdsGroups; i += kWG) hist[i] = 0;
@@ -908,40 +848,59 @@ __global__ __launch_bounds__(kWG) void k_group_sum(ColView gv, ColView vv, unsig
   const unsigned long long C = (n + kBlk - 1) / kBlk;
   unsigned long long cb, ce;
   segment(C, blockIdx.x, G, cb, ce);
-  for (unsigned long long c = cb + w; c < ce; c += kWaves) {
-    unsigned g[8], v[8];
-    decode_chunk(ig, c, lane, g);
-    decode_chunk(iv, c, lane, v);
-    const unsigned long long idx0 = c * kBlk + 8ull * lane;
+  unsigned *ldg = lds_all + w * kBlk, *ldv = lds_all + (kWaves + w) * kBlk;
+  bool bad = false;
+  unsigned long long c = cb + w;
+  if (c < ce) {
+    Raw rg = issue_chunk(ig, c, lane), rv = issue_chunk(iv, c, lane);
+    while (true) {
+      const unsigned long long cn = c + kWaves;
+      const bool more = cn < ce;
+      Raw ng, nv;
+      if (more) {
+        ng = issue_chunk(ig, cn, lane);
+        nv = issue_chunk(iv, cn, lane);
+      }
+      unsigned g[8], v[8];
+      finish_chunk(ig, rg, c, lane, ldg, g);
+      finish_chunk(iv, rv, c, lane, ldv, v);
+      const unsigned valid = valid_mask(c * kBlk + 8ull * lane, n);
 #pragma unroll
-    for (int i = 0; i < 8; i++) {
-      if (idx0 + i < n) {
-        if (g[i] >= G_groups) {
-          raise_err(E_RANGE);
-        } else if (use_lds) {
-          atomicAdd(&hist[g[i]], (unsigned long long)v[i]);
-        } else {
-          atomicAdd(&partials[g[i]], (unsigned long long)v[i]);
+      for (int i = 0; i < 8; i++) {
+        if ((valid >> i) & 1u) {
+          if (g[i] >= G_groups)
+            bad = true;
+          else if (use_lds)
+            atomicAdd(&hist[g[i]], (unsigned long long)v[i]);
+          else
+            atomicAdd(&partials[g[i]], (unsigned long long)v[i]);
         }
       }
+      if (!more) break;
+      rg = ng;
+      rv = nv;
+      c = cn;
     }
   }
+  if (bad) raise_err(E_RANGE);
   __syncthreads();
   if (use_lds) {
     for (unsigned q = threadIdx.x; q < G_groups; q += kWG)
       partials[(unsigned long long)blockIdx.x * G_groups + q] = hist[q];
   }
-  if (fin_arrive(slot, G)) {
-    if (use_lds) {
-      for (unsigned q = threadIdx.x; q < G_groups; q += kWG) {
-        unsigned long long t = 0;
-        for (unsigned b = 0; b < G; b++) t += partials[(unsigned long long)b * G_groups + q];
-        out[q] = t;
-      }
-    } else {
-      for (unsigned q = threadIdx.x; q < G_groups; q += kWG) out[q] = partials[q];
-    }
+}
+
+__global__ void k_group_sum_finish(const unsigned long long *partials, unsigned G, unsigned G_groups, unsigned lds,
+                                   unsigned long long *out) {
+  const unsigned q = blockIdx.x * blockDim.x + threadIdx.x;
+  if (q >= G_groups) return;
+  if (!lds) {
+    out[q] = partials[q];
+    return;
   }
+  unsigned long long t = 0;
+  for (unsigned b = 0; b < G; b++) t += partials[(unsigned long long)b * G_groups + q];
+  out[q] = t;
 }
 
 __global__ void k_set_hdr(ColHdr *h, unsigned long long n, unsigned long long runs, unsigned width,
@@ -973,34 +932,41 @@ __global__ void k_fill_u64(unsigned long long *p, unsigned long long n, unsigned
 // (inside chunks here, across chunk ends in k_check_order).
 __global__ __launch_bounds__(kWG) void k_bitmap(ColView posv, unsigned long long domain, unsigned *bitmap,
                                                 unsigned *chunk_first, unsigned *chunk_last) {
+  __shared__ unsigned lds_all[kWaves * kBlk];
   const InCol in = load_in(posv);
   const unsigned lane = lane_id(), w = threadIdx.x >> 6, G = gridDim.x;
   const unsigned long long C = (in.n + kBlk - 1) / kBlk;
   unsigned long long cb, ce;
   segment(C, blockIdx.x, G, cb, ce);
-  for (unsigned long long c = cb + w; c < ce; c += kWaves) {
-    unsigned v[8];
-    decode_chunk(in, c, lane, v);
+  bool bad_range = false, bad_order = false;
+  for_chunks(in, cb, ce, w, lane, lds_all + w * kBlk, [&](unsigned long long c, const unsigned (&v)[8]) {
     const unsigned long long idx0 = c * kBlk + 8ull * lane;
+    const unsigned valid = valid_mask(idx0, in.n);
     if (chunk_first) {
       const unsigned prev = __shfl_up(v[7], 1);
 #pragma unroll
       for (int i = 0; i < 8; i++) {
         const unsigned pv = i ? v[i - 1] : prev;
-        if (idx0 + i < in.n && (i > 0 || lane > 0) && v[i] <= pv) raise_err(E_NOT_SORTED);
+        if (((valid >> i) & 1u) && (i > 0 || lane > 0) && v[i] <= pv) bad_order = true;
       }
       const unsigned long long last_idx = min(in.n, (c + 1) * kBlk) - 1;
       if (lane == 0) chunk_first[c] = v[0];
-      if (idx0 <= last_idx && last_idx < idx0 + 8) chunk_last[c] = v[last_idx - idx0];
+      if (idx0 <= last_idx && last_idx < idx0 + 8) {
+        unsigned lv = v[0];
+#pragma unroll
+        for (int i = 1; i < 8; i++)
+          if (idx0 + i == last_idx) lv = v[i];
+        chunk_last[c] = lv;
+      }
     }
     // combine bits that land in the same word before the atomic
     unsigned cur_word = 0xFFFFFFFFu, bits = 0;
 #pragma unroll
     for (int i = 0; i < 8; i++) {
-      if (idx0 + i < in.n) {
+      if ((valid >> i) & 1u) {
         const unsigned p = v[i];
         if ((unsigned long long)p >= domain) {
-          raise_err(E_RANGE);
+          bad_range = true;
         } else {
           const unsigned wd = p >> 5;
           if (wd != cur_word) {
@@ -1013,7 +979,9 @@ __global__ __launch_bounds__(kWG) void k_bitmap(ColView posv, unsigned long long
       }
     }
     if (bits) atomicOr(&bitmap[cur_word], bits);
-  }
+  });
+  if (bad_range) raise_err(E_RANGE);
+  if (bad_order) raise_err(E_NOT_SORTED);
 }
 
 __global__ void k_check_order(const unsigned *chunk_first, const unsigned *chunk_last, ColView posv) {
@@ -1038,6 +1006,71 @@ __global__ __launch_bounds__(kWG) void k_shrink_payload(const unsigned *src, con
   }
 }
 
+// Per-launch timing: when enabled, every launch is bracketed by two events on its stream.
+namespace {
+struct ProfRec {
+  const char *name;
+  hipEvent_t a, b;
+};
+std::vector<ProfRec> g_prof;
+std::vector<hipEvent_t> g_ev_pool;
+std::mutex g_prof_mu;
+bool g_prof_on = false;
+
+hipEvent_t ev_get() {
+  if (!g_ev_pool.empty()) {
+    hipEvent_t e = g_ev_pool.back();
+    g_ev_pool.pop_back();
+    return e;
+  }
+  hipEvent_t e = nullptr;
+  if (hipEventCreate(&e) != hipSuccess) return nullptr;
+  return e;
+}
+
+struct ProfScope {
+  ProfRec r{nullptr, nullptr, nullptr};
+  hipStream_t s;
+  ProfScope(const char *name, void *stream) : s(reinterpret_cast<hipStream_t>(stream)) {
+    if (!g_prof_on) return;
+    std::lock_guard<std::mutex> g(g_prof_mu);
+    r.name = name;
+    r.a = ev_get();
+    r.b = ev_get();
+    if (r.a) (void)hipEventRecord(r.a, s);
+  }
+  ~ProfScope() {
+    if (!r.name) return;
+    if (r.b) (void)hipEventRecord(r.b, s);
+    std::lock_guard<std::mutex> g(g_prof_mu);
+    g_prof.push_back(r);
+  }
+};
+}  // namespace
+
+void prof_enable(bool on) { g_prof_on = on; }
+size_t prof_count() {
+  std::lock_guard<std::mutex> g(g_prof_mu);
+  return g_prof.size();
+}
+// name and duration (ms) of record i; the caller synchronises first.
+bool prof_get(size_t i, const char **name, float *ms) {
+  std::lock_guard<std::mutex> g(g_prof_mu);
+  if (i >= g_prof.size()) return false;
+  *name = g_prof[i].name;
+  *ms = 0.f;
+  if (g_prof[i].a && g_prof[i].b) (void)hipEventElapsedTime(ms, g_prof[i].a, g_prof[i].b);
+  return true;
+}
+void prof_reset() {
+  std::lock_guard<std::mutex> g(g_prof_mu);
+  for (auto &r : g_prof) {
+    if (r.a) g_ev_pool.push_back(r.a);
+    if (r.b) g_ev_pool.push_back(r.b);
+  }
+  g_prof.clear();
+}
+
 // ---------------------------------------------------------------------------------------------
 // Host-side launchers.
 static hipStream_t S(void *s) { return reinterpret_cast<hipStream_t>(s); }
@@ -1051,88 +1084,109 @@ unsigned read_and_clear_err(void *stream) {
   return e;
 }
 
+#define MS_LAUNCH(kern, grid, block, stream, ...)                                 \
+  do {                                                                            \
+    ProfScope ps_(#kern, stream);                                                 \
+    hipLaunchKernelGGL(kern, dim3(grid), dim3(block), 0, S(stream), __VA_ARGS__); \
+  } while (0)
+
 hipError_t launch_set_hdr(ColHdr *h, unsigned long long n, unsigned long long runs, unsigned width, unsigned or_all,
                           unsigned or_main, unsigned sorted, void *s) {
-  hipLaunchKernelGGL(k_set_hdr, dim3(1), dim3(64), 0, S(s), h, n, runs, width, or_all, or_main, sorted);
+  MS_LAUNCH(k_set_hdr, 1, 64, s, h, n, runs, width, or_all, or_main, sorted);
   return hipGetLastError();
 }
-hipError_t launch_colstats(const ColView &in, unsigned G, unsigned *partials, unsigned slot, void *s) {
-  hipLaunchKernelGGL(k_colstats, dim3(G), dim3(kWG), 0, S(s), in, partials, slot);
+hipError_t launch_finish(const FinishArgs &a, void *s) {
+  MS_LAUNCH(k_finish, 1, kWG, s, a);
+  return hipGetLastError();
+}
+hipError_t launch_colstats(const ColView &in, unsigned G, unsigned *partials, void *s) {
+  MS_LAUNCH(k_colstats, G, kWG, s, in, partials);
+  FinishArgs f{};
+  f.out = in;
+  f.n_src = in.hdr;
+  f.partials = partials;
+  f.G = G;
+  f.mode = 1;
+  MS_LAUNCH(k_finish, 1, kWG, s, f);
   return hipGetLastError();
 }
 hipError_t launch_morph(const ColView &in, const ColView &out, unsigned auto_w, unsigned G, unsigned *partials,
-                        unsigned slot, void *s) {
-  hipLaunchKernelGGL(k_morph, dim3(G), dim3(kWG), 0, S(s), in, out, auto_w, partials, slot);
+                        void *s) {
+  MS_LAUNCH(k_morph, G, kWG, s, in, out, auto_w, partials);
   return hipGetLastError();
 }
 hipError_t launch_decode(const ColView &in, unsigned *out, unsigned G, void *s) {
-  hipLaunchKernelGGL(k_decode, dim3(G), dim3(kWG), 0, S(s), in, out);
+  MS_LAUNCH(k_decode, G, kWG, s, in, out);
   return hipGetLastError();
 }
 hipError_t launch_rle(unsigned mode, const ColView &a, const ColView &b, const ColView &out, unsigned G,
-                      unsigned *seg_count, unsigned *partials, unsigned slot, void *s) {
+                      unsigned *seg_count, unsigned *partials, void *s) {
   ChunkSrc src;
   src.mode = mode;
   src.a = a;
   src.b = b;
-  hipLaunchKernelGGL(k_rle_count, dim3(G), dim3(kWG), 0, S(s), src, seg_count);
-  hipLaunchKernelGGL(k_rle_emit, dim3(G), dim3(kWG), 0, S(s), src, out, seg_count, partials, slot);
+  MS_LAUNCH(k_rle_count, G, kWG, s, src, seg_count);
+  MS_LAUNCH(k_rle_emit, G, kWG, s, src, out, seg_count, partials);
   return hipGetLastError();
 }
 hipError_t launch_project(const ColView &pos, const ColView &data, const ColView &out, unsigned auto_w, unsigned G,
-                          unsigned *partials, unsigned slot, void *s) {
-  hipLaunchKernelGGL(k_project, dim3(G), dim3(kWG), 0, S(s), pos, data, out, auto_w, partials, slot);
+                          unsigned *partials, void *s) {
+  MS_LAUNCH(k_project, G, kWG, s, pos, data, out, auto_w, partials);
   return hipGetLastError();
 }
 hipError_t launch_pred(const PredArgs &a, unsigned G, void *s) {
-  hipLaunchKernelGGL(k_pred, dim3(G), dim3(kWG), 0, S(s), a);
+  MS_LAUNCH(k_pred, G, kWG, s, a);
   return hipGetLastError();
 }
 hipError_t launch_emit(const EmitArgs &a, unsigned G, void *s) {
-  hipLaunchKernelGGL(k_emit, dim3(G), dim3(kWG), 0, S(s), a);
+  MS_LAUNCH(k_emit, G, kWG, s, a);
+  const unsigned k = a.out.kind;
+  if (k == STATIC_BP || k == DYN_BP || k == DELTA_DYN_BP || k == FOR_DYN_BP) MS_LAUNCH(k_emit_fix, G, kWG, s, a);
   return hipGetLastError();
 }
 hipError_t launch_sum(const ColView &in, unsigned long long *result, unsigned G, unsigned long long *partials,
-                      unsigned slot, void *s) {
-  hipLaunchKernelGGL(k_sum, dim3(G), dim3(kWG), 0, S(s), in, result, partials, slot);
+                      void *s) {
+  MS_LAUNCH(k_sum, G, kWG, s, in, partials);
+  MS_LAUNCH(k_sum_finish, 1, kWG, s, partials, G, result);
   return hipGetLastError();
 }
 hipError_t launch_group_sum(const ColView &g, const ColView &v, unsigned groups, unsigned long long *out, unsigned G,
-                            unsigned long long *partials, unsigned slot, void *s) {
-  hipLaunchKernelGGL(k_group_sum, dim3(G), dim3(kWG), 0, S(s), g, v, groups, out, partials, slot);
+                            unsigned long long *partials, void *s) {
+  MS_LAUNCH(k_group_sum, G, kWG, s, g, v, groups, partials);
+  const unsigned lds = groups <= kMaxLdsGroups ? 1u : 0u;
+  MS_LAUNCH(k_group_sum_finish, (groups + 255) / 256, 256, s, partials, G, groups, lds, out);
   return hipGetLastError();
 }
 hipError_t launch_fill_u32(unsigned *p, unsigned long long n, unsigned v, void *s) {
   if (n == 0) return hipSuccess;
-  unsigned blocks = (unsigned)std::min<unsigned long long>((n + 255) / 256, 2048ull);
-  hipLaunchKernelGGL(k_fill_u32, dim3(blocks), dim3(256), 0, S(s), p, n, v);
+  const unsigned blocks = (unsigned)std::min<unsigned long long>((n + 255) / 256, 2048ull);
+  MS_LAUNCH(k_fill_u32, blocks, 256, s, p, n, v);
   return hipGetLastError();
 }
 hipError_t launch_fill_u64(unsigned long long *p, unsigned long long n, unsigned long long v, void *s) {
   if (n == 0) return hipSuccess;
-  unsigned blocks = (unsigned)std::min<unsigned long long>((n + 255) / 256, 2048ull);
-  hipLaunchKernelGGL(k_fill_u64, dim3(blocks), dim3(256), 0, S(s), p, n, v);
+  const unsigned blocks = (unsigned)std::min<unsigned long long>((n + 255) / 256, 2048ull);
+  MS_LAUNCH(k_fill_u64, blocks, 256, s, p, n, v);
   return hipGetLastError();
 }
 hipError_t launch_bitmap(const ColView &pos, unsigned long long domain, unsigned *bitmap, unsigned G, void *s) {
-  hipLaunchKernelGGL(k_bitmap, dim3(G), dim3(kWG), 0, S(s), pos, domain, bitmap, (unsigned *)nullptr,
-                     (unsigned *)nullptr);
+  MS_LAUNCH(k_bitmap, G, kWG, s, pos, domain, bitmap, (unsigned *)nullptr, (unsigned *)nullptr);
   return hipGetLastError();
 }
 hipError_t launch_bitmap_checked(const ColView &pos, unsigned long long domain, unsigned *bitmap, unsigned *first,
                                  unsigned *last, unsigned G, void *s) {
-  hipLaunchKernelGGL(k_bitmap, dim3(G), dim3(kWG), 0, S(s), pos, domain, bitmap, first, last);
+  MS_LAUNCH(k_bitmap, G, kWG, s, pos, domain, bitmap, first, last);
   return hipGetLastError();
 }
 hipError_t launch_check_order(const unsigned *first, const unsigned *last, const ColView &pos, void *s) {
-  hipLaunchKernelGGL(k_check_order, dim3(256), dim3(256), 0, S(s), first, last, pos);
+  MS_LAUNCH(k_check_order, 256, 256, s, first, last, pos);
   return hipGetLastError();
 }
 hipError_t launch_shrink_payload(const unsigned *src, const unsigned *old_off, const unsigned char *widths,
                                  const unsigned *new_off, unsigned *dst, unsigned long long nb, void *s) {
   if (nb == 0) return hipSuccess;
-  unsigned blocks = (unsigned)std::min<unsigned long long>((nb + kWaves - 1) / kWaves, 4096ull);
-  hipLaunchKernelGGL(k_shrink_payload, dim3(blocks), dim3(kWG), 0, S(s), src, old_off, widths, new_off, dst, nb);
+  const unsigned blocks = (unsigned)std::min<unsigned long long>((nb + kWaves - 1) / kWaves, 4096ull);
+  MS_LAUNCH(k_shrink_payload, blocks, kWG, s, src, old_off, widths, new_off, dst, nb);
   return hipGetLastError();
 }
 

@@ -87,6 +87,14 @@ for _name, _args in _sigs.items():
     _f.restype = ctypes.c_int
 _lib.ms_last_error.restype = ctypes.c_char_p
 _lib.ms_last_error.argtypes = []
+_lib.ms_prof_enable.argtypes = [ctypes.c_int]
+_lib.ms_prof_enable.restype = None
+_lib.ms_prof_count.argtypes = []
+_lib.ms_prof_count.restype = ctypes.c_uint64
+_lib.ms_prof_get.argtypes = [ctypes.c_uint64, ctypes.POINTER(ctypes.c_char_p), ctypes.POINTER(ctypes.c_float)]
+_lib.ms_prof_get.restype = ctypes.c_int
+_lib.ms_prof_reset.argtypes = []
+_lib.ms_prof_reset.restype = None
 
 
 def lib():
@@ -284,6 +292,30 @@ def group_sum(groups: Column, vals: Column, G: int, out: torch.Tensor | None = N
 def sync(stream=None):
     """Synchronise and raise the first data-dependent device error, if any."""
     _check(_lib.ms_sync(_stream(stream)))
+
+
+def prof_enable(on: bool = True):
+    """Bracket every kernel launch with HIP events on its stream (see ms_prof_enable)."""
+    _lib.ms_prof_enable(1 if on else 0)
+
+
+def prof_count() -> int:
+    return int(_lib.ms_prof_count())
+
+
+def prof_records(start: int = 0) -> list:
+    """[(kernel name, milliseconds)] for records start.. (synchronise first)."""
+    out = []
+    name = ctypes.c_char_p()
+    ms = ctypes.c_float()
+    for i in range(start, prof_count()):
+        _check(_lib.ms_prof_get(i, ctypes.byref(name), ctypes.byref(ms)))
+        out.append((name.value.decode(), float(ms.value)))
+    return out
+
+
+def prof_reset():
+    _lib.ms_prof_reset()
 
 
 def u64(t: torch.Tensor) -> np.ndarray:
