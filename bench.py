@@ -186,8 +186,9 @@ class Sweep:
             kernels = [r[0] for r in recs]
             alg_k = {}
             for k in set(kernels):
-                if k in alg:
-                    alg_k[k] = alg[k]
+                base = k.split("<")[0]  # template instances share their family's byte accounting
+                if base in alg:
+                    alg_k[k] = alg[base]
             self.acct.append(dict(op=op, ue=ue, alg=sum(alg_k.values()), alg_by_kernel=alg_k, recs=recs,
                                   out_fp=oi["footprint"] if oi else 0))
             del out

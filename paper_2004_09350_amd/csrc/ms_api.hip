@@ -220,7 +220,7 @@ ms_status launched(hipError_t e, ms_column **out) {
 // Header of a count-known producer's output: count from `n_src`, ORs from the partials,
 // auto-width static BP narrowed to its main part.
 hipError_t finish_produced(const ColView &out, const ColHdr *n_src, const unsigned *partials, unsigned G,
-                           unsigned auto_w, unsigned sorted, void *stream) {
+                           unsigned auto_w, unsigned sorted, unsigned *narrow_tmp, void *stream) {
   FinishArgs f{};
   f.out = out;
   f.n_src = n_src;
@@ -229,8 +229,11 @@ hipError_t finish_produced(const ColView &out, const ColHdr *n_src, const unsign
   f.Wp = out.width;
   f.auto_w = auto_w;
   f.sorted = sorted;
-  f.mode = auto_w ? 2u : 0u;
-  return launch_finish(f, stream);
+  f.mode = 0;
+  hipError_t e = hipSuccess;
+  if (out.kind == MS_STATIC_BP && auto_w) e = launch_narrow(f, narrow_tmp, G, stream);
+  if (e == hipSuccess) e = launch_finish(f, stream);
+  return e;
 }
 
 ms_status read_hdr(const ms_column *c, void *stream, ColHdr &h) {
@@ -276,6 +279,7 @@ ms_status compaction(const ms_column *in, const PredArgs &pa_in, bool emit_value
   ea.chunk_last = pa.chunk_last;
   ea.stage_g = blocky ? sc.get<unsigned>(n_cap + 1) : nullptr;
   ea.partials = sc.get<unsigned>(2 * G);
+  unsigned *narrow_tmp = (fmt.kind == MS_STATIC_BP && auto_w) ? sc.get<unsigned>(n_cap + kPayloadSlackWords) : nullptr;
   if (!sc.ok) {
     free_column(*out);
     *out = nullptr;
@@ -283,18 +287,8 @@ ms_status compaction(const ms_column *in, const PredArgs &pa_in, bool emit_value
   }
   hipError_t e = launch_pred(pa, G, stream);
   if (e == hipSuccess) e = launch_emit(ea, G, stream);
-  if (e == hipSuccess && fmt.kind == MS_STATIC_BP && auto_w) {
-    FinishArgs f{};
-    f.out = (*out)->v;
-    f.n_src = nullptr;
-    f.partials = ea.partials;
-    f.G = G;
-    f.Wp = 32;
-    f.auto_w = 1;
-    f.sorted = 1;
-    f.mode = 2;  // provisional width is in the header
-    e = launch_finish(f, stream);
-  }
+  if (e == hipSuccess && fmt.kind == MS_STATIC_BP && auto_w)
+    e = finish_produced((*out)->v, nullptr, ea.partials, G, 1, 1, narrow_tmp, stream);
   st = launched(e, out);
   if (st == MS_OK) (*out)->sorted = 1;
   return st;
@@ -389,6 +383,7 @@ ms_status ms_morph(const ms_column *in, ms_format fmt, void *stream, ms_column *
   Scratch sc(stream);
   unsigned *partials = sc.get<unsigned>(2 * G);
   unsigned *seg = (fmt.kind == MS_RLE) ? sc.get<unsigned>(G) : nullptr;
+  unsigned *narrow_tmp = (fmt.kind == MS_STATIC_BP && auto_w) ? sc.get<unsigned>(n_cap + kPayloadSlackWords) : nullptr;
   if (!sc.ok) {
     free_column(*out);
     *out = nullptr;
@@ -399,7 +394,8 @@ ms_status ms_morph(const ms_column *in, ms_format fmt, void *stream, ms_column *
     e = launch_rle(0, in->v, in->v, (*out)->v, G, seg, partials, stream);
   else
     e = launch_morph(in->v, (*out)->v, auto_w, G, partials, stream);
-  if (e == hipSuccess) e = finish_produced((*out)->v, in->v.hdr, partials, G, auto_w, in->sorted, stream);
+  if (e == hipSuccess)
+    e = finish_produced((*out)->v, in->v.hdr, partials, G, auto_w, in->sorted, narrow_tmp, stream);
   st = launched(e, out);
   if (st == MS_OK) {
     (*out)->n_host = in->n_host;
@@ -743,6 +739,7 @@ ms_status ms_project(const ms_column *data, const ms_column *pos, ms_format fmt,
   Scratch sc(stream);
   unsigned *partials = sc.get<unsigned>(2 * G);
   unsigned *seg = (fmt.kind == MS_RLE) ? sc.get<unsigned>(G) : nullptr;
+  unsigned *narrow_tmp = (fmt.kind == MS_STATIC_BP && auto_w) ? sc.get<unsigned>(n_cap + kPayloadSlackWords) : nullptr;
   if (!sc.ok) {
     free_column(*out);
     *out = nullptr;
@@ -753,7 +750,7 @@ ms_status ms_project(const ms_column *data, const ms_column *pos, ms_format fmt,
     e = launch_rle(1, pos->v, data->v, (*out)->v, G, seg, partials, stream);
   else
     e = launch_project(pos->v, data->v, (*out)->v, auto_w, G, partials, stream);
-  if (e == hipSuccess) e = finish_produced((*out)->v, pos->v.hdr, partials, G, auto_w, 0, stream);
+  if (e == hipSuccess) e = finish_produced((*out)->v, pos->v.hdr, partials, G, auto_w, 0, narrow_tmp, stream);
   st = launched(e, out);
   if (st == MS_OK) (*out)->n_host = pos->n_host;
   return st;

@@ -259,6 +259,34 @@ __device__ __forceinline__ unsigned long long rle_find_in(const InCol &in, unsig
   return lo;
 }
 
+// Run holding value idx, found by the whole wave: each step probes 64 evenly spaced
+// runs at once.  Bounds: the run index of value idx lies in [idx - (n - R), idx].
+__device__ __forceinline__ unsigned long long rle_find_wave(const InCol &in, unsigned long long idx, unsigned lane,
+                                                           unsigned long long hint) {
+  const unsigned long long slack = in.n - in.runs;
+  unsigned long long lo = idx > slack ? idx - slack : 0ull;
+  unsigned long long hi = min(in.runs, idx + 1);
+  // hint: the run of an earlier value; the run of idx is at or after it
+  if (hint < hi && hint > lo) {
+    const unsigned sh = in.rstarts[hint];
+    if (sh <= idx) {
+      lo = hint;
+      hi = min(hi, hint + (idx - sh) + 1);  // at most one new run per value after run `hint` starts
+    }
+  }
+  if (lo >= hi) lo = hi ? hi - 1 : 0;
+  while (hi - lo > 1) {
+    const unsigned long long step = (hi - lo + 63) / 64;
+    const unsigned long long probe = lo + lane * step;
+    const bool ok = probe < hi && in.rstarts[probe] <= idx;
+    const unsigned long long m = __ballot(ok);
+    const unsigned j = m ? 63u - __clzll(m) : 0u;
+    lo = lo + j * step;
+    hi = min(hi, lo + step);
+  }
+  return lo;
+}
+
 __device__ __forceinline__ unsigned long long rle_find(const InCol &in, unsigned long long idx) {
   unsigned long long lo = 0, hi = in.runs;  // invariant: rstarts[lo] <= idx, answer in [lo, hi)
   while (hi - lo > 1) {
@@ -273,7 +301,8 @@ __device__ __forceinline__ unsigned long long rle_find(const InCol &in, unsigned
 
 // Decode chunk c (values 512c .. 512c+511); lane gets 8 consecutive values.  Values
 // at indices >= n are unspecified (callers mask them out).
-__device__ __forceinline__ void decode_chunk(const InCol &in, unsigned long long c, unsigned lane, unsigned (&v)[8]) {
+__device__ __forceinline__ void decode_chunk(const InCol &in, unsigned long long c, unsigned lane, unsigned (&v)[8],
+                                             unsigned long long &rle_hint) {
   const unsigned long long idx0 = c * kBlk + 8ull * lane;
   switch (in.kind) {
     case UNCOMPR: {
@@ -328,19 +357,41 @@ __device__ __forceinline__ void decode_chunk(const InCol &in, unsigned long long
       break;
     }
     case RLE: {
-      // run of the chunk's first value (one search per wave), then each lane searches
-      // the at most 8*lane + 1 runs between it and its own first value
+      // run of the chunk's first value by a 64-way search of the whole wave (bounded by
+      // the wave's previous chunk), then each lane finds its own run among the at most
+      // 8*lane + 1 runs that follow and reads the next 8 run starts at once
       const unsigned long long c0 = c * kBlk;
       unsigned long long r0 = 0;
-      if (lane == 0 && c0 < in.n) r0 = rle_find(in, c0);
-      r0 = __shfl(r0, 0);
+      if (c0 < in.n) {
+        r0 = rle_find_wave(in, c0, lane, rle_hint);
+        rle_hint = r0;
+      }
       if (idx0 < in.n) {
         const unsigned long long hi = min(in.runs, r0 + 8ull * lane + 1);
-        unsigned long long r = rle_find_in(in, idx0, r0, hi);
+        unsigned long long r;
+        if (in.rstarts[hi - 1] <= idx0) {  // dense runs: the upper bound itself
+          r = hi - 1;
+        } else {
+          unsigned long long lo = r0, step = 1;
+          while (lo + step < hi && in.rstarts[lo + step] <= idx0) {
+            lo += step;
+            step <<= 1;
+          }
+          r = rle_find_in(in, idx0, lo, min(hi, lo + step));
+        }
+        unsigned st[7], val[8];
+#pragma unroll
+        for (int k = 0; k < 7; k++) st[k] = (r + 1 + k < in.runs) ? in.rstarts[r + 1 + k] : 0xFFFFFFFFu;
+#pragma unroll
+        for (int k = 0; k < 8; k++) val[k] = (r + k < in.runs) ? in.rvalues[r + k] : 0u;
+        // value i is in run r + (number of run starts in (idx0, idx0 + i])
 #pragma unroll
         for (int i = 0; i < 8; i++) {
-          while (r + 1 < in.runs && in.rstarts[r + 1] <= idx0 + i) r++;
-          v[i] = in.rvalues[r];
+          unsigned x = val[0];
+#pragma unroll
+          for (int k = 0; k < 7; k++)
+            if (k < i && st[k] <= idx0 + i) x = val[k + 1];
+          v[i] = x;
         }
       } else {
 #pragma unroll
@@ -352,6 +403,11 @@ __device__ __forceinline__ void decode_chunk(const InCol &in, unsigned long long
 #pragma unroll
       for (int i = 0; i < 8; i++) v[i] = 0;
   }
+}
+
+__device__ __forceinline__ void decode_chunk(const InCol &in, unsigned long long c, unsigned lane, unsigned (&v)[8]) {
+  unsigned long long hint = 0;
+  decode_chunk(in, c, lane, v, hint);
 }
 
 // ---------------------------------------------------------------------------------------------
@@ -450,6 +506,146 @@ __device__ __forceinline__ void finish_chunk(const InCol &in, const Raw &r, unsi
   }
 }
 
+// ---------------------------------------------------------------------------------------------
+// DMA-pipelined chunk stream.  Each wave keeps kRing chunks in flight in a ring of
+// 512-word LDS buffers, filled by direct global->LDS loads (16 bytes per lane, no
+// VGPRs).  Every chunk costs exactly two such loads (a chunk that needs fewer, or
+// takes the direct path, repeats a load of a valid address), so the wait before
+// chunk j is "vmcnt <= 2 * (chunks issued after j)".  Loads return in order, so
+// other loads or stores issued in between only make that wait stricter.
+constexpr int kRing = 4;
+
+typedef __attribute__((address_space(1))) void gvoid_t;
+typedef __attribute__((address_space(3))) void lvoid_t;
+
+__device__ __forceinline__ void dma16(const void *gsrc, unsigned *lds_dst) {
+  __builtin_amdgcn_global_load_lds((gvoid_t *)gsrc, (lvoid_t *)lds_dst, 16, 0, 0);
+}
+
+// s_waitcnt vmcnt(k) leaving the other counters untouched (gfx9 encoding).
+__device__ __forceinline__ void wait_vm(unsigned k) {
+  switch (k) {
+    case 0: __builtin_amdgcn_s_waitcnt(0x0F70); break;
+    case 1: case 2: __builtin_amdgcn_s_waitcnt(0x0F72); break;
+    case 3: case 4: __builtin_amdgcn_s_waitcnt(0x0F74); break;
+    case 5: case 6: __builtin_amdgcn_s_waitcnt(0x0F76); break;
+    default: __builtin_amdgcn_s_waitcnt(0x0F70); break;
+  }
+}
+
+__device__ __forceinline__ void compiler_fence() { asm volatile("" ::: "memory"); }
+
+// How chunk c is read: 0 packed block via LDS, 1 uncompressed via LDS, 2 direct path.
+__device__ __forceinline__ unsigned chunk_mode(const InCol &in, unsigned long long c, unsigned &W,
+                                               unsigned long long &off) {
+  const unsigned long long c0 = c * kBlk;
+  W = 0;
+  off = 0;
+  switch (in.kind) {
+    case UNCOMPR: return (c0 + kBlk <= in.n) ? 1u : 2u;
+    case STATIC_BP:
+      if (c0 + kBlk <= in.n_main && in.W <= 32) {
+        W = in.W;
+        off = c * 16ull * in.W;
+        return 0u;
+      }
+      return 2u;
+    case DYN_BP:
+    case DELTA_DYN_BP:
+    case FOR_DYN_BP:
+      if (c < in.nb) {
+        W = in.widths[c];
+        off = in.offsets[c];
+        if (W > 32 || off + 16ull * W > in.payload_cap) {  // a corrupt directory never reads out of bounds
+          W = 0;
+          off = 0;
+        }
+        return 0u;
+      }
+      return 2u;
+    default: return 2u;
+  }
+}
+
+__device__ __forceinline__ void issue_dma(const InCol &in, unsigned long long c, unsigned lane, unsigned *buf,
+                                          const void *dummy) {
+  unsigned W;
+  unsigned long long off;
+  const unsigned mode = chunk_mode(in, c, W, off);
+  const uint4 *a0 = reinterpret_cast<const uint4 *>(dummy), *a1 = a0;
+  if (mode == 1) {
+    const uint4 *p4 = reinterpret_cast<const uint4 *>(in.payload + c * kBlk);
+    a0 = p4 + lane;
+    a1 = p4 + 64 + lane;
+  } else if (mode == 0 && W > 0) {
+    const uint4 *b4 = reinterpret_cast<const uint4 *>(in.payload + off);
+    const unsigned nq = 4u * W;
+    a0 = (lane < nq) ? b4 + lane : b4;
+    a1 = (lane + 64 < nq) ? b4 + 64 + lane : b4;
+  }
+  compiler_fence();
+  dma16(a0, buf);
+  dma16(a1, buf + 256);
+  compiler_fence();
+}
+
+__device__ __forceinline__ void consume_chunk(const InCol &in, unsigned long long c, unsigned lane,
+                                              const unsigned *buf, unsigned (&v)[8], unsigned long long &rle_hint) {
+  unsigned W;
+  unsigned long long off;
+  const unsigned mode = chunk_mode(in, c, W, off);
+  if (mode == 1) {
+    const uint4 *b4 = reinterpret_cast<const uint4 *>(buf) + 2 * lane;
+    const uint4 a = b4[0], b = b4[1];
+    v[0] = a.x; v[1] = a.y; v[2] = a.z; v[3] = a.w;
+    v[4] = b.x; v[5] = b.y; v[6] = b.z; v[7] = b.w;
+    return;
+  }
+  if (mode == 2) {
+    decode_chunk(in, c, lane, v, rle_hint);
+    return;
+  }
+  unpack8_rt(W, buf, lane, v);
+  if (in.kind == FOR_DYN_BP) {
+    const unsigned ref = in.bases[c];
+#pragma unroll
+    for (int i = 0; i < 8; i++) v[i] += ref;
+  } else if (in.kind == DELTA_DYN_BP) {
+#pragma unroll
+    for (int i = 1; i < 8; i++) v[i] += v[i - 1];
+    const unsigned excl = wave_excl_scan(v[7], lane) + in.bases[c];
+#pragma unroll
+    for (int i = 0; i < 8; i++) v[i] += excl;
+  }
+}
+
+// Walk the wave's chunks cb + w + kWaves*j < ce with kRing chunks in flight.
+// ring: the wave's kRing * 512 LDS words; dummy: any valid 16-byte global address.
+template <class Body>
+__device__ __forceinline__ void stream_chunks(const InCol &in, unsigned long long cb, unsigned long long ce,
+                                              unsigned w, unsigned lane, unsigned *ring, const void *dummy,
+                                              Body &&body) {
+  const unsigned long long first = cb + w;
+  if (first >= ce) return;
+  const unsigned long long nj = (ce - first + kWaves - 1) / kWaves;
+  const unsigned long long pre = min(nj, (unsigned long long)kRing);
+  for (unsigned long long j = 0; j < pre; j++) issue_dma(in, first + kWaves * j, lane, ring + kBlk * j, dummy);
+  unsigned long long rle_hint = 0;
+  for (unsigned long long j = 0; j < nj; j++) {
+    const unsigned long long ahead = min(nj - 1 - j, (unsigned long long)kRing - 1);
+    wait_vm(2u * (unsigned)ahead);
+    compiler_fence();
+    unsigned *buf = ring + kBlk * (j % kRing);
+    const unsigned long long c = first + kWaves * j;
+    unsigned v[8];
+    consume_chunk(in, c, lane, buf, v, rle_hint);
+    body(c, v);
+    compiler_fence();
+    if (j + kRing < nj) issue_dma(in, first + kWaves * (j + kRing), lane, buf, dummy);
+  }
+  wait_vm(0);
+}
+
 // Walk chunks cb + w, cb + w + kWaves, ... < ce with one chunk of look-ahead;
 // body(c, v) gets the decoded values.  lds: the wave's 512-word buffer.
 template <class Body>
@@ -532,14 +728,71 @@ __device__ __forceinline__ void gather8_kind(const InCol &d, unsigned (&v)[8], u
   }
 }
 
-__device__ __forceinline__ void gather8(const InCol &d, unsigned (&v)[8], unsigned valid, bool &bad) {
+__device__ __forceinline__ unsigned long long wave_min64(unsigned long long x) {
+#pragma unroll
+  for (int d = 32; d >= 1; d >>= 1) {
+    const unsigned long long y = __shfl_xor(x, d);
+    x = y < x ? y : x;
+  }
+  return x;
+}
+
+// Block-wise gather for formats without cheap random access (DELTA needs the prefix of
+// its block, RLE a run search): the wave decodes each touched 512-block once into
+// `blk` and serves every lane's positions inside it.  Up to 16 blocks per call (enough
+// for sorted positions); positions left over take the per-value path.
+__device__ __forceinline__ void gather8_blocks(const InCol &d, unsigned (&v)[8], unsigned valid, bool &bad,
+                                               unsigned lane, unsigned *blk, unsigned *stage) {
+  unsigned pend = 0, res[8];
+#pragma unroll
+  for (int i = 0; i < 8; i++) {
+    res[i] = 0;
+    if ((valid >> i) & 1u) {
+      if (v[i] < d.n)
+        pend |= 1u << i;
+      else
+        bad = true;
+    }
+  }
+  for (int it = 0; it < 16; it++) {
+    unsigned long long mine = ~0ull;
+#pragma unroll
+    for (int i = 0; i < 8; i++)
+      if ((pend >> i) & 1u) mine = min(mine, (unsigned long long)(v[i] >> 9));
+    const unsigned long long k = wave_min64(mine);
+    if (k == ~0ull) break;
+    const Raw r = issue_chunk(d, k, lane);
+    unsigned x[8];
+    finish_chunk(d, r, k, lane, stage, x);
+#pragma unroll
+    for (int i = 0; i < 8; i++) blk[8 * lane + i] = x[i];
+    wave_sync();
+#pragma unroll
+    for (int i = 0; i < 8; i++) {
+      if (((pend >> i) & 1u) && (v[i] >> 9) == k) {
+        res[i] = blk[v[i] & 511];
+        pend &= ~(1u << i);
+      }
+    }
+    wave_sync();
+  }
+#pragma unroll
+  for (int i = 0; i < 8; i++)
+    if ((pend >> i) & 1u) res[i] = value_at(d, v[i]);
+#pragma unroll
+  for (int i = 0; i < 8; i++) v[i] = res[i];
+}
+
+// blk, stage: the wave's two 512-word LDS buffers (used for DELTA and RLE data only).
+__device__ __forceinline__ void gather8(const InCol &d, unsigned (&v)[8], unsigned valid, bool &bad, unsigned lane,
+                                        unsigned *blk, unsigned *stage) {
   switch (d.kind) {
     case UNCOMPR: gather8_kind<UNCOMPR>(d, v, valid, bad); break;
     case STATIC_BP: gather8_kind<STATIC_BP>(d, v, valid, bad); break;
     case DYN_BP: gather8_kind<DYN_BP>(d, v, valid, bad); break;
-    case DELTA_DYN_BP: gather8_kind<DELTA_DYN_BP>(d, v, valid, bad); break;
+    case DELTA_DYN_BP:
+    case RLE: gather8_blocks(d, v, valid, bad, lane, blk, stage); break;
     case FOR_DYN_BP: gather8_kind<FOR_DYN_BP>(d, v, valid, bad); break;
-    case RLE: gather8_kind<RLE>(d, v, valid, bad); break;
     default: break;
   }
 }

@@ -50,6 +50,7 @@ bool prof_get(size_t i, const char **name, float *ms);
 void prof_reset();
 hipError_t launch_colstats(const ColView &in, unsigned G, unsigned *partials, void *s);
 hipError_t launch_finish(const FinishArgs &a, void *s);
+hipError_t launch_narrow(const FinishArgs &a, unsigned *tmp, unsigned G, void *s);
 hipError_t launch_set_hdr(ColHdr *h, unsigned long long n, unsigned long long runs, unsigned width, unsigned or_all,
                           unsigned or_main, unsigned sorted, void *s);
 hipError_t launch_morph(const ColView &in, const ColView &out, unsigned auto_w, unsigned G, unsigned *partials,

@@ -149,6 +149,7 @@ __device__ __forceinline__ void encode_sbp_chunk(const OutCol &o, unsigned long 
 
 // Write output chunk c of a count-known operator (output index = chunk position).
 // Handles UNCOMPR, STATIC_BP and the DynBP family (RLE outputs take the two-phase path).
+template <unsigned OK>
 __device__ __forceinline__ void write_chunk_known(const OutCol &o, unsigned long long c, const unsigned (&v)[8],
                                                   unsigned lane, unsigned *lds, unsigned &or_all,
                                                   unsigned &or_main) {
@@ -156,7 +157,7 @@ __device__ __forceinline__ void write_chunk_known(const OutCol &o, unsigned long
 #pragma unroll
   for (int i = 0; i < 8; i++)
     if (idx0 + i < o.n) or_all |= v[i];
-  switch (o.c.kind) {
+  switch (OK) {
     case UNCOMPR: {
       if (idx0 + 8 <= o.n) {
         uint4 *p = reinterpret_cast<uint4 *>(o.c.payload + idx0);
@@ -188,15 +189,10 @@ __device__ __forceinline__ void write_chunk_known(const OutCol &o, unsigned long
 
 // ---------------------------------------------------------------------------------------------
 // Finish: one workgroup after a column-producing kernel.  Reduces the per-workgroup
-// {OR of all values, OR of the main part}, writes the header and, for an auto-width
-// static BP column whose main part needs fewer bits than the provisional width,
-// repacks it in place (chunk by chunk in increasing order: output chunk c only
-// overlaps input chunks <= c).
+// {OR of all values, OR of the main part} and writes the header.
 __global__ __launch_bounds__(kWG) void k_finish(FinishArgs a) {
-  __shared__ unsigned lds_all[kWaves * kBlk];
   __shared__ unsigned red[kWaves];
   __shared__ unsigned long long s_n;
-  const unsigned lane = lane_id(), w = threadIdx.x >> 6;
   unsigned ao = 0, mo = 0;
   for (unsigned i = threadIdx.x; i < a.G; i += kWG) {
     ao |= a.partials[2 * i];
@@ -219,28 +215,7 @@ __global__ __launch_bounds__(kWG) void k_finish(FinishArgs a) {
   __syncthreads();
   const unsigned Wprov = s_wp;  // the width the producer packed at
   unsigned W = Wprov;
-  if (a.out.kind == STATIC_BP && a.auto_w) {
-    const unsigned Wt = bw(mo);
-    const unsigned long long n_main = n & ~31ull;
-    if (Wt < Wprov && Wprov <= 32 && n_main > 0) {
-      unsigned *lds = lds_all + w * kBlk;
-      const unsigned long long C = (n_main + kBlk - 1) / kBlk;
-      for (unsigned long long c0 = 0; c0 < C; c0 += kWaves) {
-        const unsigned long long cc = c0 + w;
-        unsigned v[8] = {0, 0, 0, 0, 0, 0, 0, 0};
-        if (cc < C) unpack8_rt(Wprov, a.out.payload + cc * 16ull * Wprov, lane, v);
-        __syncthreads();
-        if (cc < C) {
-          const unsigned long long idx0 = cc * kBlk + 8ull * lane;
-#pragma unroll
-          for (int i = 0; i < 8; i++) v[i] = (idx0 + i < n_main) ? v[i] : 0u;
-          pack_block(Wt, v, lane, lds, a.out.payload + cc * 16ull * Wt);
-        }
-        __syncthreads();
-      }
-    }
-    W = Wt;
-  }
+  if (a.out.kind == STATIC_BP && a.auto_w) W = min(bw(mo), Wprov);  // k_narrow repacked when smaller
   if (threadIdx.x == 0) {
     a.out.hdr->n = n;
     a.out.hdr->or_all = ao;
@@ -251,10 +226,56 @@ __global__ __launch_bounds__(kWG) void k_finish(FinishArgs a) {
   }
 }
 
+// Narrowing of an auto-width static BP column whose main part needs fewer bits than
+// the width it was packed at: k_narrow repacks every chunk into `tmp` at the narrow
+// width, k_narrow_copy copies it back.  Both exit at once when nothing narrows.
+__device__ __forceinline__ bool narrow_plan(const FinishArgs &a, unsigned long long &n_main, unsigned &Wf,
+                                            unsigned &Wt, unsigned *red) {
+  unsigned mo = 0;
+  for (unsigned i = threadIdx.x; i < a.G; i += kWG) mo |= a.partials[2 * i + 1];
+  mo = wg_or(mo, red);
+  const unsigned long long n = a.n_src ? a.n_src->n : a.out.hdr->n;
+  n_main = n & ~31ull;
+  Wf = a.out.hdr->sbp_width;
+  Wt = bw(mo);
+  return Wf <= 32 && Wt < Wf && n_main > 0;
+}
+
+__global__ __launch_bounds__(kWG) void k_narrow(FinishArgs a, unsigned *tmp) {
+  __shared__ unsigned lds_all[kWaves * kBlk];
+  __shared__ unsigned red[kWaves];
+  unsigned long long n_main;
+  unsigned Wf, Wt;
+  if (!narrow_plan(a, n_main, Wf, Wt, red)) return;
+  const unsigned lane = lane_id(), w = threadIdx.x >> 6;
+  unsigned *lds = lds_all + w * kBlk;
+  const unsigned long long C = (n_main + kBlk - 1) / kBlk;
+  for (unsigned long long c = (unsigned long long)blockIdx.x * kWaves + w; c < C;
+       c += (unsigned long long)gridDim.x * kWaves) {
+    unsigned v[8];
+    unpack8_rt(Wf, a.out.payload + c * 16ull * Wf, lane, v);
+    const unsigned long long idx0 = c * kBlk + 8ull * lane;
+#pragma unroll
+    for (int i = 0; i < 8; i++) v[i] = (idx0 + i < n_main) ? v[i] : 0u;
+    pack_block(Wt, v, lane, lds, tmp + c * 16ull * Wt);
+  }
+}
+
+__global__ __launch_bounds__(kWG) void k_narrow_copy(FinishArgs a, const unsigned *tmp) {
+  __shared__ unsigned red[kWaves];
+  unsigned long long n_main;
+  unsigned Wf, Wt;
+  if (!narrow_plan(a, n_main, Wf, Wt, red)) return;
+  const unsigned long long words = n_main * Wt / 32;  // n_main is a multiple of 32
+  for (unsigned long long q = (unsigned long long)blockIdx.x * kWG + threadIdx.x; q < words;
+       q += (unsigned long long)gridDim.x * kWG)
+    a.out.payload[q] = tmp[q];
+}
+
 // ---------------------------------------------------------------------------------------------
 // Column statistics needed by later operators: OR of all values (width bound).
 __global__ __launch_bounds__(kWG) void k_colstats(ColView inv, unsigned *partials) {
-  __shared__ unsigned lds_all[kWaves * kBlk];
+  __shared__ unsigned ring[kWaves * kRing * kBlk];
   __shared__ unsigned red[kWaves];
   const InCol in = load_in(inv);
   const unsigned lane = lane_id(), w = threadIdx.x >> 6, G = gridDim.x;
@@ -263,7 +284,7 @@ __global__ __launch_bounds__(kWG) void k_colstats(ColView inv, unsigned *partial
   segment(C, blockIdx.x, G, cb, ce);
   unsigned a = 0, m = 0;
   const unsigned long long nm32 = in.n & ~31ull;
-  for_chunks(in, cb, ce, w, lane, lds_all + w * kBlk, [&](unsigned long long c, const unsigned (&v)[8]) {
+  stream_chunks(in, cb, ce, w, lane, ring + w * kRing * kBlk, inv.hdr, [&](unsigned long long c, const unsigned (&v)[8]) {
     const unsigned long long idx0 = c * kBlk + 8ull * lane;
 #pragma unroll
     for (int i = 0; i < 8; i++) {
@@ -281,7 +302,9 @@ __global__ __launch_bounds__(kWG) void k_colstats(ColView inv, unsigned *partial
 
 // ---------------------------------------------------------------------------------------------
 // Morph (and encode): out = encode_fmt(decode(in)), count known.
+template <unsigned OK>
 __global__ __launch_bounds__(kWG) void k_morph(ColView inv, ColView outv, unsigned auto_w, unsigned *partials) {
+  __shared__ unsigned ring[kWaves * kRing * kBlk];
   __shared__ unsigned lds_all[kWaves * kBlk];
   __shared__ unsigned red[kWaves];
   const InCol in = load_in(inv);
@@ -295,8 +318,8 @@ __global__ __launch_bounds__(kWG) void k_morph(ColView inv, ColView outv, unsign
   segment(C, blockIdx.x, G, cb, ce);
   unsigned or_all = 0, or_main = 0;
   unsigned *lds = lds_all + w * kBlk;
-  for_chunks(in, cb, ce, w, lane, lds, [&](unsigned long long c, const unsigned (&v)[8]) {
-    write_chunk_known(o, c, v, lane, lds, or_all, or_main);
+  stream_chunks(in, cb, ce, w, lane, ring + w * kRing * kBlk, inv.hdr, [&](unsigned long long c, const unsigned (&v)[8]) {
+    write_chunk_known<OK>(o, c, v, lane, lds, or_all, or_main);
   });
   or_all = wg_or(or_all, red);
   or_main = wg_or(or_main, red);
@@ -308,13 +331,13 @@ __global__ __launch_bounds__(kWG) void k_morph(ColView inv, ColView outv, unsign
 
 // Decode into a plain device array.
 __global__ __launch_bounds__(kWG) void k_decode(ColView inv, unsigned *__restrict__ out) {
-  __shared__ unsigned lds_all[kWaves * kBlk];
+  __shared__ unsigned ring[kWaves * kRing * kBlk];
   const InCol in = load_in(inv);
   const unsigned lane = lane_id(), w = threadIdx.x >> 6, G = gridDim.x;
   const unsigned long long C = (in.n + kBlk - 1) / kBlk;
   unsigned long long cb, ce;
   segment(C, blockIdx.x, G, cb, ce);
-  for_chunks(in, cb, ce, w, lane, lds_all + w * kBlk, [&](unsigned long long c, const unsigned (&v)[8]) {
+  stream_chunks(in, cb, ce, w, lane, ring + w * kRing * kBlk, inv.hdr, [&](unsigned long long c, const unsigned (&v)[8]) {
     const unsigned long long idx0 = c * kBlk + 8ull * lane;
     if (idx0 + 8 <= in.n) {
       uint4 *p = reinterpret_cast<uint4 *>(out + idx0);
@@ -330,8 +353,11 @@ __global__ __launch_bounds__(kWG) void k_decode(ColView inv, unsigned *__restric
 
 // ---------------------------------------------------------------------------------------------
 // Project: out_j = data[pos_j].
+template <unsigned OK>
 __global__ __launch_bounds__(kWG) void k_project(ColView posv, ColView datav, ColView outv, unsigned auto_w,
                                                  unsigned *partials) {
+  __shared__ unsigned ring[kWaves * kRing * kBlk];
+  __shared__ unsigned gblk[kWaves * kBlk];
   __shared__ unsigned lds_all[kWaves * kBlk];
   __shared__ unsigned red[kWaves];
   const InCol ip = load_in(posv);
@@ -347,12 +373,12 @@ __global__ __launch_bounds__(kWG) void k_project(ColView posv, ColView datav, Co
   unsigned or_all = 0, or_main = 0;
   unsigned *lds = lds_all + w * kBlk;
   bool bad = false;
-  for_chunks(ip, cb, ce, w, lane, lds, [&](unsigned long long c, const unsigned (&pv)[8]) {
+  stream_chunks(ip, cb, ce, w, lane, ring + w * kRing * kBlk, posv.hdr, [&](unsigned long long c, const unsigned (&pv)[8]) {
     unsigned v[8];
 #pragma unroll
     for (int i = 0; i < 8; i++) v[i] = pv[i];
-    gather8(id, v, valid_mask(c * kBlk + 8ull * lane, ip.n), bad);
-    write_chunk_known(o, c, v, lane, lds, or_all, or_main);
+    gather8(id, v, valid_mask(c * kBlk + 8ull * lane, ip.n), bad, lane, gblk + w * kBlk, lds);
+    write_chunk_known<OK>(o, c, v, lane, lds, or_all, or_main);
   });
   if (bad) raise_err(E_RANGE);
   or_all = wg_or(or_all, red);
@@ -378,50 +404,19 @@ __device__ __forceinline__ unsigned src_value(const ChunkSrc &s, const InCol &ia
   return x;
 }
 
-// Run starts among the lane's 8 values (bit i set when value i starts a run).
-__device__ __forceinline__ unsigned run_flags(const ChunkSrc &s, const InCol &ia, const InCol &ib,
-                                              unsigned long long c, unsigned lane, const unsigned (&v)[8]) {
-  const unsigned long long idx0 = c * kBlk + 8ull * lane;
-  unsigned prev = __shfl_up(v[7], 1);
-  if (lane == 0) prev = (c > 0) ? src_value(s, ia, ib, c * kBlk - 1) : ~v[0];
-  unsigned flags = 0;
-#pragma unroll
-  for (int i = 0; i < 8; i++) {
-    const unsigned pv = i ? v[i - 1] : prev;
-    if (idx0 + i < ia.n && (idx0 + i == 0 || v[i] != pv)) flags |= 1u << i;
-  }
-  return flags;
-}
-
-__global__ __launch_bounds__(kWG) void k_rle_count(ChunkSrc s, unsigned *seg_count) {
+// Both RLE phases walk the segment's chunks in lockstep, kWaves at a time, so that the
+// value before a chunk (needed to see whether the chunk starts a new run) is the last
+// value of the neighbouring wave's chunk, passed through LDS.
+template <bool EMIT>
+__device__ __forceinline__ void rle_walk(const ChunkSrc &s, const ColView &outv, const unsigned *seg_count,
+                                         unsigned *seg_out, unsigned *partials) {
   __shared__ unsigned lds_all[kWaves * kBlk];
-  __shared__ unsigned long long red[kWaves];
-  const InCol ia = load_in(s.a);
-  InCol ib = ia;
-  if (s.mode == 1) ib = load_in(s.b);
-  const unsigned lane = lane_id(), w = threadIdx.x >> 6, G = gridDim.x;
-  const unsigned long long C = (ia.n + kBlk - 1) / kBlk;
-  unsigned long long cb, ce;
-  segment(C, blockIdx.x, G, cb, ce);
-  unsigned cnt = 0;
-  bool bad = false;
-  unsigned *lds = lds_all + w * kBlk;
-  for_chunks(ia, cb, ce, w, lane, lds, [&](unsigned long long c, const unsigned (&dv)[8]) {
-    unsigned v[8];
-#pragma unroll
-    for (int i = 0; i < 8; i++) v[i] = dv[i];
-    if (s.mode == 1) gather8(ib, v, valid_mask(c * kBlk + 8ull * lane, ia.n), bad);
-    cnt += __popc(run_flags(s, ia, ib, c, lane, v));
-  });
-  const unsigned long long t = wg_add64(cnt, red);
-  if (threadIdx.x == 0) seg_count[blockIdx.x] = (unsigned)t;
-}
-
-__global__ __launch_bounds__(kWG) void k_rle_emit(ChunkSrc s, ColView outv, const unsigned *seg_count,
-                                                  unsigned *partials) {
-  __shared__ unsigned lds_all[kWaves * kBlk];
+  __shared__ unsigned gblk[kWaves * kBlk];
+  __shared__ unsigned gstage[kWaves * kBlk];
   __shared__ unsigned long long red[kWaves];
   __shared__ unsigned s_chunk_runs[kWaves];
+  __shared__ unsigned s_last[kWaves];
+  __shared__ unsigned s_first_prev;
   __shared__ unsigned redu[kWaves];
   const InCol ia = load_in(s.a);
   InCol ib = ia;
@@ -431,22 +426,26 @@ __global__ __launch_bounds__(kWG) void k_rle_emit(ChunkSrc s, ColView outv, cons
   const unsigned long long C = (n + kBlk - 1) / kBlk;
   unsigned long long cb, ce;
   segment(C, blockIdx.x, G, cb, ce);
-  unsigned long long before = 0, total = 0;
-  for (unsigned i = threadIdx.x; i < G; i += kWG) {
-    total += seg_count[i];
-    if (i < blockIdx.x) before += seg_count[i];
+  unsigned long long base = 0, total = 0;
+  if (EMIT) {
+    unsigned long long before = 0;
+    for (unsigned i = threadIdx.x; i < G; i += kWG) {
+      total += seg_count[i];
+      if (i < blockIdx.x) before += seg_count[i];
+    }
+    base = wg_add64(before, red);
+    total = wg_add64(total, red);
+    if (blockIdx.x == 0 && threadIdx.x == 0) {
+      outv.hdr->n = n;
+      outv.hdr->runs = total;
+    }
   }
-  before = wg_add64(before, red);
-  total = wg_add64(total, red);
-  if (blockIdx.x == 0 && threadIdx.x == 0) {
-    outv.hdr->n = n;
-    outv.hdr->runs = total;
-  }
-  unsigned or_all = 0;
+  if (threadIdx.x == 0 && cb > 0 && cb < ce) s_first_prev = src_value(s, ia, ib, cb * kBlk - 1);
+  __syncthreads();
+  unsigned carry = s_first_prev;  // last value before the current round's first chunk
+  unsigned or_all = 0, cnt_all = 0;
   bool bad = false;
   unsigned *lds = lds_all + w * kBlk;
-  // Chunks are taken in order, kWaves at a time, so run indices stay ordered.
-  unsigned long long base = before;
   Raw cur;
   if (cb + w < ce) cur = issue_chunk(ia, cb + w, lane);
   for (unsigned long long c0 = cb; c0 < ce; c0 += kWaves) {
@@ -454,51 +453,82 @@ __global__ __launch_bounds__(kWG) void k_rle_emit(ChunkSrc s, ColView outv, cons
     Raw nxt;
     if (c + kWaves < ce) nxt = issue_chunk(ia, c + kWaves, lane);
     unsigned v[8] = {0, 0, 0, 0, 0, 0, 0, 0};
-    unsigned flags = 0;
     if (c < ce) {
       finish_chunk(ia, cur, c, lane, lds, v);
-      if (s.mode == 1) gather8(ib, v, valid_mask(c * kBlk + 8ull * lane, n), bad);
-      flags = run_flags(s, ia, ib, c, lane, v);
-      const unsigned long long idx0 = c * kBlk + 8ull * lane;
-#pragma unroll
-      for (int i = 0; i < 8; i++)
-        if (idx0 + i < n) or_all |= v[i];
+      if (s.mode == 1)
+        gather8(ib, v, valid_mask(c * kBlk + 8ull * lane, n), bad, lane, gblk + w * kBlk, gstage + w * kBlk);
+      if (lane == 63) s_last[w] = v[7];
     }
-    const unsigned cnt = __popc(flags);
-    const unsigned off = wave_excl_scan(cnt, lane);
-    const unsigned chunk_total = __shfl(off + cnt, 63);
-    if (lane == 0) s_chunk_runs[w] = chunk_total;
     __syncthreads();
-    unsigned long long my = base;
-    for (unsigned j = 0; j < w; j++) my += s_chunk_runs[j];
-    unsigned long long all = base;
-    for (unsigned j = 0; j < kWaves; j++) all += s_chunk_runs[j];
-    __syncthreads();
+    const unsigned before_chunk = (w > 0) ? s_last[w - 1] : carry;
+    const unsigned next_carry = s_last[kWaves - 1];
+    unsigned flags = 0;
     if (c < ce) {
-      unsigned long long r = my + off;
       const unsigned long long idx0 = c * kBlk + 8ull * lane;
+      unsigned prev = __shfl_up(v[7], 1);
+      if (lane == 0) prev = before_chunk;
 #pragma unroll
       for (int i = 0; i < 8; i++) {
-        if (flags & (1u << i)) {
-          if (r < outv.n_cap) {
-            outv.rvalues[r] = v[i];
-            outv.rstarts[r] = (unsigned)(idx0 + i);
-          } else {
-            raise_err(E_INVALID);
-          }
-          r++;
+        const unsigned pv = i ? v[i - 1] : prev;
+        if (idx0 + i < n) {
+          or_all |= v[i];
+          if (idx0 + i == 0 || v[i] != pv) flags |= 1u << i;
         }
       }
     }
-    base = all;
+    const unsigned cnt = __popc(flags);
+    cnt_all += cnt;
+    if (EMIT) {
+      const unsigned off = wave_excl_scan(cnt, lane);
+      const unsigned chunk_total = __shfl(off + cnt, 63);
+      if (lane == 0) s_chunk_runs[w] = chunk_total;
+      __syncthreads();
+      unsigned long long my = base;
+      for (unsigned j = 0; j < w; j++) my += s_chunk_runs[j];
+      unsigned long long all = base;
+      for (unsigned j = 0; j < kWaves; j++) all += s_chunk_runs[j];
+      if (c < ce) {
+        unsigned long long r = my + off;
+        const unsigned long long idx0 = c * kBlk + 8ull * lane;
+#pragma unroll
+        for (int i = 0; i < 8; i++) {
+          if (flags & (1u << i)) {
+            if (r < outv.n_cap) {
+              outv.rvalues[r] = v[i];
+              outv.rstarts[r] = (unsigned)(idx0 + i);
+            } else {
+              raise_err(E_INVALID);
+            }
+            r++;
+          }
+        }
+      }
+      base = all;
+    }
+    __syncthreads();  // s_last and s_chunk_runs are rewritten next round
+    carry = next_carry;
     cur = nxt;
   }
   if (bad) raise_err(E_RANGE);
-  or_all = wg_or(or_all, redu);
-  if (threadIdx.x == 0) {
-    partials[2 * blockIdx.x] = or_all;
-    partials[2 * blockIdx.x + 1] = 0;
+  if (EMIT) {
+    or_all = wg_or(or_all, redu);
+    if (threadIdx.x == 0) {
+      partials[2 * blockIdx.x] = or_all;
+      partials[2 * blockIdx.x + 1] = 0;
+    }
+  } else {
+    const unsigned long long t = wg_add64(cnt_all, red);
+    if (threadIdx.x == 0) seg_out[blockIdx.x] = (unsigned)t;
   }
+}
+
+__global__ __launch_bounds__(kWG) void k_rle_count(ChunkSrc s, unsigned *seg_count) {
+  rle_walk<false>(s, s.a, nullptr, seg_count, nullptr);
+}
+
+__global__ __launch_bounds__(kWG) void k_rle_emit(ChunkSrc s, ColView outv, const unsigned *seg_count,
+                                                  unsigned *partials) {
+  rle_walk<true>(s, outv, seg_count, nullptr, partials);
 }
 
 // ---------------------------------------------------------------------------------------------
@@ -506,8 +536,9 @@ __global__ __launch_bounds__(kWG) void k_rle_emit(ChunkSrc s, ColView outv, cons
 // mode 0: range predicate ((v - lo) <= span) != neg, emits positions
 // mode 1: bitmap predicate v < domain && bit(v), emits positions (semi-join)
 // mode 2: bitmap predicate on values, emits values, checks strict increase (intersect)
+template <unsigned MODE>
 __global__ __launch_bounds__(kWG) void k_pred(PredArgs a) {
-  __shared__ unsigned lds_all[kWaves * kBlk];
+  __shared__ unsigned ring[kWaves * kRing * kBlk];
   __shared__ unsigned long long red[kWaves];
   __shared__ unsigned redo[kWaves];
   const InCol in = load_in(a.in);
@@ -517,25 +548,32 @@ __global__ __launch_bounds__(kWG) void k_pred(PredArgs a) {
   segment(C, blockIdx.x, G, cb, ce);
   unsigned cnt = 0, orv = 0;
   bool unsorted = false;
-  for_chunks(in, cb, ce, w, lane, lds_all + w * kBlk, [&](unsigned long long c, const unsigned (&v)[8]) {
+  constexpr unsigned mode = MODE;
+  const unsigned lo = a.lo, span = a.span;
+  const bool neg = a.neg != 0;
+  const unsigned long long domain = a.domain;
+  const unsigned *bitmap = a.bitmap;
+  unsigned char *bitmask = a.bitmask;
+  unsigned *chunk_first = a.chunk_first, *chunk_last = a.chunk_last;
+  stream_chunks(in, cb, ce, w, lane, ring + w * kRing * kBlk, a.in.hdr, [&](unsigned long long c, const unsigned (&v)[8]) {
     const unsigned long long idx0 = c * kBlk + 8ull * lane;
     const unsigned valid = valid_mask(idx0, in.n);
     unsigned mask = 0;
-    if (a.mode == 0) {
+    if constexpr (mode == 0) {
 #pragma unroll
       for (int i = 0; i < 8; i++)
-        if (((v[i] - a.lo) <= a.span) != (a.neg != 0)) mask |= 1u << i;
+        if (((v[i] - lo) <= span) != neg) mask |= 1u << i;
     } else {
 #pragma unroll
       for (int i = 0; i < 8; i++) {
         const unsigned x = v[i];
-        if ((unsigned long long)x < a.domain && ((a.bitmap[x >> 5] >> (x & 31)) & 1u)) mask |= 1u << i;
+        if ((unsigned long long)x < domain && ((bitmap[x >> 5] >> (x & 31)) & 1u)) mask |= 1u << i;
       }
     }
     mask &= valid;
-    a.bitmask[c * 64 + lane] = (unsigned char)mask;
+    bitmask[c * 64 + lane] = (unsigned char)mask;
     cnt += __popc(mask);
-    if (a.mode == 2) {
+    if constexpr (mode == 2) {
 #pragma unroll
       for (int i = 0; i < 8; i++)
         if (mask & (1u << i)) orv |= v[i];
@@ -547,13 +585,13 @@ __global__ __launch_bounds__(kWG) void k_pred(PredArgs a) {
         if (((valid >> i) & 1u) && (i > 0 || lane > 0) && v[i] <= pv) unsorted = true;
       }
       const unsigned long long last_idx = min(in.n, (c + 1) * kBlk) - 1;
-      if (lane == 0) a.chunk_first[c] = v[0];
+      if (lane == 0) chunk_first[c] = v[0];
       if (idx0 <= last_idx && last_idx < idx0 + 8) {
         unsigned lv = v[0];
 #pragma unroll
         for (int i = 1; i < 8; i++)
           if (idx0 + i == last_idx) lv = v[i];
-        a.chunk_last[c] = lv;
+        chunk_last[c] = lv;
       }
     } else if (mask) {
       orv |= (unsigned)idx0 | (31u - __clz(mask));  // positions: bit width of the largest
@@ -659,16 +697,27 @@ __global__ __launch_bounds__(kWG) void k_emit(EmitArgs a) {
   unsigned *lds = lds_all + w * kBlk;
   const unsigned long long n_main_o = o.n_main;
 
+  // bitmask bytes of the next tile are loaded while the current one is emitted
+  unsigned nmsk[2];
+#pragma unroll
+  for (int j = 0; j < 2; j++) {
+    const unsigned long long c = cb + 2 * w + j;
+    nmsk[j] = (c < ce) ? a.bitmask[c * 64 + lane] : 0u;
+  }
   for (unsigned long long t0 = cb; t0 < ce; t0 += kEmitChunks) {
     unsigned v[2][8];
     unsigned msk[2], off[2];
 #pragma unroll
     for (int j = 0; j < 2; j++) {
+      msk[j] = nmsk[j];
+      const unsigned long long cn = t0 + kEmitChunks + 2 * w + j;
+      nmsk[j] = (cn < ce) ? a.bitmask[cn * 64 + lane] : 0u;
+    }
+#pragma unroll
+    for (int j = 0; j < 2; j++) {
       const unsigned lc = 2 * w + j;
       const unsigned long long c = t0 + lc;
-      msk[j] = 0;
       if (c < ce) {
-        msk[j] = a.bitmask[c * 64 + lane];
         if (a.emit_values) decode_chunk(in, c, lane, v[j]);
       }
       const unsigned cntl = __popc(msk[j]);
@@ -792,7 +841,7 @@ __global__ __launch_bounds__(kWG) void k_emit_fix(EmitArgs a) {
 // ---------------------------------------------------------------------------------------------
 // Sum and group-sum.
 __global__ __launch_bounds__(kWG) void k_sum(ColView inv, unsigned long long *partials) {
-  __shared__ unsigned lds_all[kWaves * kBlk];
+  __shared__ unsigned ring[kWaves * kRing * kBlk];
   __shared__ unsigned long long red[kWaves];
   const InCol in = load_in(inv);
   const unsigned lane = lane_id(), w = threadIdx.x >> 6, G = gridDim.x;
@@ -810,7 +859,7 @@ __global__ __launch_bounds__(kWG) void k_sum(ColView inv, unsigned long long *pa
     const unsigned long long C = (in.n + kBlk - 1) / kBlk;
     unsigned long long cb, ce;
     segment(C, blockIdx.x, G, cb, ce);
-    for_chunks(in, cb, ce, w, lane, lds_all + w * kBlk, [&](unsigned long long c, const unsigned (&v)[8]) {
+    stream_chunks(in, cb, ce, w, lane, ring + w * kRing * kBlk, inv.hdr, [&](unsigned long long c, const unsigned (&v)[8]) {
       const unsigned valid = valid_mask(c * kBlk + 8ull * lane, in.n);
       unsigned long long t = 0;
 #pragma unroll
@@ -932,14 +981,14 @@ __global__ void k_fill_u64(unsigned long long *p, unsigned long long n, unsigned
 // (inside chunks here, across chunk ends in k_check_order).
 __global__ __launch_bounds__(kWG) void k_bitmap(ColView posv, unsigned long long domain, unsigned *bitmap,
                                                 unsigned *chunk_first, unsigned *chunk_last) {
-  __shared__ unsigned lds_all[kWaves * kBlk];
+  __shared__ unsigned ring[kWaves * kRing * kBlk];
   const InCol in = load_in(posv);
   const unsigned lane = lane_id(), w = threadIdx.x >> 6, G = gridDim.x;
   const unsigned long long C = (in.n + kBlk - 1) / kBlk;
   unsigned long long cb, ce;
   segment(C, blockIdx.x, G, cb, ce);
   bool bad_range = false, bad_order = false;
-  for_chunks(in, cb, ce, w, lane, lds_all + w * kBlk, [&](unsigned long long c, const unsigned (&v)[8]) {
+  stream_chunks(in, cb, ce, w, lane, ring + w * kRing * kBlk, posv.hdr, [&](unsigned long long c, const unsigned (&v)[8]) {
     const unsigned long long idx0 = c * kBlk + 8ull * lane;
     const unsigned valid = valid_mask(idx0, in.n);
     if (chunk_first) {
@@ -1099,6 +1148,11 @@ hipError_t launch_finish(const FinishArgs &a, void *s) {
   MS_LAUNCH(k_finish, 1, kWG, s, a);
   return hipGetLastError();
 }
+hipError_t launch_narrow(const FinishArgs &a, unsigned *tmp, unsigned G, void *s) {
+  MS_LAUNCH(k_narrow, G, kWG, s, a, tmp);
+  MS_LAUNCH(k_narrow_copy, G, kWG, s, a, tmp);
+  return hipGetLastError();
+}
 hipError_t launch_colstats(const ColView &in, unsigned G, unsigned *partials, void *s) {
   MS_LAUNCH(k_colstats, G, kWG, s, in, partials);
   FinishArgs f{};
@@ -1110,9 +1164,21 @@ hipError_t launch_colstats(const ColView &in, unsigned G, unsigned *partials, vo
   MS_LAUNCH(k_finish, 1, kWG, s, f);
   return hipGetLastError();
 }
+#define MS_BY_OUT_KIND(K, LAUNCH)                  \
+  switch (K) {                                     \
+    case UNCOMPR: LAUNCH(UNCOMPR); break;          \
+    case STATIC_BP: LAUNCH(STATIC_BP); break;      \
+    case DYN_BP: LAUNCH(DYN_BP); break;            \
+    case DELTA_DYN_BP: LAUNCH(DELTA_DYN_BP); break; \
+    case FOR_DYN_BP: LAUNCH(FOR_DYN_BP); break;    \
+    default: return hipErrorInvalidValue;          \
+  }
+
 hipError_t launch_morph(const ColView &in, const ColView &out, unsigned auto_w, unsigned G, unsigned *partials,
                         void *s) {
-  MS_LAUNCH(k_morph, G, kWG, s, in, out, auto_w, partials);
+#define MS_L(K) MS_LAUNCH(k_morph<K>, G, kWG, s, in, out, auto_w, partials)
+  MS_BY_OUT_KIND(out.kind, MS_L)
+#undef MS_L
   return hipGetLastError();
 }
 hipError_t launch_decode(const ColView &in, unsigned *out, unsigned G, void *s) {
@@ -1131,11 +1197,18 @@ hipError_t launch_rle(unsigned mode, const ColView &a, const ColView &b, const C
 }
 hipError_t launch_project(const ColView &pos, const ColView &data, const ColView &out, unsigned auto_w, unsigned G,
                           unsigned *partials, void *s) {
-  MS_LAUNCH(k_project, G, kWG, s, pos, data, out, auto_w, partials);
+#define MS_L(K) MS_LAUNCH(k_project<K>, G, kWG, s, pos, data, out, auto_w, partials)
+  MS_BY_OUT_KIND(out.kind, MS_L)
+#undef MS_L
   return hipGetLastError();
 }
 hipError_t launch_pred(const PredArgs &a, unsigned G, void *s) {
-  MS_LAUNCH(k_pred, G, kWG, s, a);
+  if (a.mode == 0)
+    MS_LAUNCH(k_pred<0>, G, kWG, s, a);
+  else if (a.mode == 1)
+    MS_LAUNCH(k_pred<1>, G, kWG, s, a);
+  else
+    MS_LAUNCH(k_pred<2>, G, kWG, s, a);
   return hipGetLastError();
 }
 hipError_t launch_emit(const EmitArgs &a, unsigned G, void *s) {
