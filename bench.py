@@ -44,6 +44,9 @@ def parse():
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--quick", action="store_true", help="fewer operators (for profiling runs)")
     ap.add_argument("--dump", default=None, help="write per-operator kernel timings (JSON) to this file")
+    ap.add_argument("--calib-copy", action="store_true",
+                    help="decode one uncompressed column first (k_decode: 4 B read + 4 B written per row), the "
+                         "known-size reference for scaling HBM counters")
     return ap.parse_args()
 
 
@@ -279,6 +282,11 @@ def main():
     log = lambda *a: print(*a, file=sys.stderr, flush=True)
     M.init()
     sw = Sweep(M, gen, args.rows, args.quick, log)
+    if args.calib_copy:
+        dst = sw.cols[("U32", M.UNCOMPR)].decode()
+        M.sync()
+        log(f"calibration copy: k_decode of {args.rows} rows ({4 * args.rows} B read, {4 * args.rows} B written)")
+        del dst
     sw.account()
     log("accounting pass done")
     if args.dump:
