@@ -155,6 +155,59 @@ ms_status ms_sum(const ms_column *in, uint64_t *dev_result, void *stream);
 ms_status ms_group_sum(const ms_column *groups, const ms_column *vals, uint32_t G, uint64_t *dev_out,
                        void *stream);
 
+/* Exact footprint in bytes of the column in each of the six formats (section 5.2:
+ * exhaustive format selection tries every format; footprints are what it compares).
+ * dev_bytes6[kind] (device, 6 x uint64, indexed by ms_kind) receives the size that
+ * ms_column_encode / ms_morph would give the column in that format, by the section
+ * rule used for ms_column_info.footprint: UNCOMPR 4 B/value; STATIC_BP at its
+ * automatic width (bit width of the OR of the main part) plus 4 B per remainder value;
+ * DynBP family 1 B width + 4 B directory (+ 4 B base for DELTA/FOR) per 512-block,
+ * 64 x width B of payload per block, 4 B per remainder value; RLE 8 B per run.
+ * One pass over the column; nothing is encoded. */
+ms_status ms_footprints(const ms_column *in, uint64_t *dev_bytes6, void *stream);
+
+/* Data characteristics for format selection (section 5.2 names the number of values,
+ * the bit-width histogram and the sort order among them).  dev_features32 (device,
+ * 32 floats) receives, over a sample of at most 128 chunks of 512 consecutive values
+ * (all values when n <= 65536; otherwise chunk floor(s * floor(n/512) / 128), s < 128):
+ *   [0..11]  fraction of values whose bit width b falls in class 0 (b = 0) or
+ *            1 + (b - 1) / 3;
+ *   [12..19] fraction of neighbouring pairs inside a chunk whose difference (mod 2^32)
+ *            has bit width class 0 or 1 + (b - 1) / 5;
+ *   [20] fraction of pairs in non-decreasing order (1 if there are none);
+ *   [21] log2(mean run length) / 32, runs counted inside chunks;
+ *   [22] log2(1 + HyperLogLog distinct estimate) / 32 (256 registers, SplitMix64
+ *        finaliser of v + 0x9E3779B97F4A7C15, small-range correction);
+ *   [23] log2(max - min + 1) / 32; [24] log2(n + 1) / 32;
+ *   [25..27] mean per-chunk bit width of the OR, of the chunk-minimum residuals and of
+ *        the neighbour differences, / 32;
+ *   [28] bw(min) / 32; [29] bw(max) / 32; [30] bw(floor(mean)) / 32;
+ *   [31] fraction of sampled chunks holding one distinct value.
+ * An empty column gives all zeros except [20] = 1.  Computed in double, stored as float. */
+ms_status ms_stats(const ms_column *in, float *dev_features32, void *stream);
+
+/* Learned format selector: a 32-64-64-6 perceptron with ReLU hidden layers that maps
+ * the 32 features to the predicted size of each format (bits per value / 32, index =
+ * ms_kind); the selection is the smallest output (section 5.2 selects formats by a
+ * cost model over data characteristics; the network is this library's cost model).
+ * Parameters: one device float vector of ms_mlp_nparam() = 6662 values, row-major
+ * W1[64][32], b1[64], W2[64][64], b2[64], W3[6][64], b3[6].  All buffers device,
+ * float, batch-major (x: n x 32, y and targets: n x 6). */
+uint32_t ms_mlp_nparam(void);
+/* y (may be NULL) receives the outputs, pick (may be NULL) the argmin (ties to the
+ * lower kind).  n = 0 is a no-op. */
+ms_status ms_mlp_forward(const float *params, const float *x, uint64_t n, float *y, uint32_t *pick, void *stream);
+/* Gradient of the mean squared error over the n x 6 outputs into grad (6662 floats);
+ * loss (device float, may be NULL) receives the loss.  Deterministic: partial sums in a
+ * fixed order.  n must be in [1, 2^26). */
+ms_status ms_mlp_grad(const float *params, const float *x, const float *t, uint64_t n, float *grad, float *loss,
+                      void *stream);
+/* One Adam step (Kingma & Ba 2015) with bias correction for step number `step` >= 1:
+ * m, v are the moment vectors (6662 floats each, zero before step 1), updated in place
+ * with params. */
+ms_status ms_adam_step(float *params, const float *grad, float *m, float *v, uint64_t step, float lr, float beta1,
+                       float beta2, float eps, void *stream);
+
 /* Launch timing.  While enabled, every kernel launch is bracketed by two HIP events
  * recorded on its own stream.  Records are kept in launch order until ms_prof_reset.
  * ms_prof_get needs the launches to have finished (call ms_sync first); *name points

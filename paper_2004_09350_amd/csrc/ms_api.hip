@@ -2,6 +2,7 @@
 #include <hip/hip_runtime.h>
 
 #include <algorithm>
+#include <cmath>
 #include <atomic>
 #include <cstdio>
 #include <cstring>
@@ -791,6 +792,76 @@ ms_status ms_group_sum(const ms_column *groups, const ms_column *vals, uint32_t 
   if (e == hipSuccess)
     e = launch_group_sum(groups->v, vals->v, G_groups, reinterpret_cast<unsigned long long *>(dev_out), G, partials,
                          stream);
+  return e == hipSuccess ? MS_OK : hip_fail(e, "kernel launch");
+}
+
+ms_status ms_footprints(const ms_column *in, uint64_t *dev_bytes6, void *stream) {
+  ms_status st = check_init();
+  if (st != MS_OK) return st;
+  if (!in || !dev_bytes6) return fail(MS_ERR_INVALID_ARG, "NULL argument");
+  const uint64_t n_cap = in->n_host != kUnknown ? in->n_host : in->n_cap;
+  const uint64_t C = chunks_of(n_cap);
+  const unsigned G = grid_for(C);
+  const unsigned G2 = (unsigned)std::min<uint64_t>(std::max<uint64_t>((C + kWG - 1) / kWG, 1), 1024);
+  Scratch sc(stream);
+  unsigned long long *part = sc.get<unsigned long long>(5ull * G);
+  unsigned long long *bpart = sc.get<unsigned long long>(G2);
+  unsigned *first = sc.get<unsigned>(C);
+  unsigned *last = sc.get<unsigned>(C);
+  if (!sc.ok) return fail(MS_ERR_OOM, "scratch allocation failed");
+  hipError_t e = launch_footprints(in->v, G, part, first, last, bpart, G2,
+                                   reinterpret_cast<unsigned long long *>(dev_bytes6), stream);
+  return e == hipSuccess ? MS_OK : hip_fail(e, "kernel launch");
+}
+
+ms_status ms_stats(const ms_column *in, float *dev_features32, void *stream) {
+  ms_status st = check_init();
+  if (st != MS_OK) return st;
+  if (!in || !dev_features32) return fail(MS_ERR_INVALID_ARG, "NULL argument");
+  Scratch sc(stream);
+  void *chunks = sc.get<unsigned char>(stats_scratch_bytes());
+  if (!sc.ok) return fail(MS_ERR_OOM, "scratch allocation failed");
+  hipError_t e = launch_stats(in->v, chunks, dev_features32, stream);
+  return e == hipSuccess ? MS_OK : hip_fail(e, "kernel launch");
+}
+
+uint32_t ms_mlp_nparam(void) { return mlp_nparam(); }
+
+ms_status ms_mlp_forward(const float *params, const float *x, uint64_t n, float *y, uint32_t *pick, void *stream) {
+  ms_status st = check_init();
+  if (st != MS_OK) return st;
+  if (n && (!params || !x || (!y && !pick))) return fail(MS_ERR_INVALID_ARG, "NULL argument");
+  if (n >= (1ull << 31)) return fail(MS_ERR_INVALID_ARG, "batch too large");
+  hipError_t e = launch_mlp_forward(params, x, (unsigned)n, y, pick, stream);
+  return e == hipSuccess ? MS_OK : hip_fail(e, "kernel launch");
+}
+
+ms_status ms_mlp_grad(const float *params, const float *x, const float *t, uint64_t n, float *grad, float *loss,
+                      void *stream) {
+  ms_status st = check_init();
+  if (st != MS_OK) return st;
+  if (!params || !grad || (n && (!x || !t))) return fail(MS_ERR_INVALID_ARG, "NULL argument");
+  if (n == 0) return fail(MS_ERR_INVALID_ARG, "empty batch");
+  if (n >= (1ull << 26)) return fail(MS_ERR_INVALID_ARG, "batch too large");
+  const unsigned nwg = mlp_grad_workgroups((unsigned)n);
+  Scratch sc(stream);
+  float *gpart = sc.get<float>((uint64_t)nwg * mlp_nparam());
+  float *lpart = sc.get<float>(nwg);
+  if (!sc.ok) return fail(MS_ERR_OOM, "scratch allocation failed");
+  hipError_t e = launch_mlp_grad(params, x, t, (unsigned)n, gpart, lpart, grad, loss, stream);
+  return e == hipSuccess ? MS_OK : hip_fail(e, "kernel launch");
+}
+
+ms_status ms_adam_step(float *params, const float *grad, float *m, float *v, uint64_t step, float lr, float beta1,
+                       float beta2, float eps, void *stream) {
+  ms_status st = check_init();
+  if (st != MS_OK) return st;
+  if (!params || !grad || !m || !v) return fail(MS_ERR_INVALID_ARG, "NULL argument");
+  if (step == 0) return fail(MS_ERR_INVALID_ARG, "step counts from 1");
+  if (!(beta1 >= 0.f && beta1 < 1.f && beta2 >= 0.f && beta2 < 1.f)) return fail(MS_ERR_INVALID_ARG, "beta out of range");
+  const float c1 = (float)(1.0 - std::pow((double)beta1, (double)step));
+  const float c2 = (float)(1.0 - std::pow((double)beta2, (double)step));
+  hipError_t e = launch_adam(params, grad, m, v, lr, beta1, beta2, eps, c1, c2, stream);
   return e == hipSuccess ? MS_OK : hip_fail(e, "kernel launch");
 }
 

@@ -75,4 +75,16 @@ hipError_t launch_check_order(const unsigned *first, const unsigned *last, const
 hipError_t launch_shrink_payload(const unsigned *src, const unsigned *old_off, const unsigned char *widths,
                                  const unsigned *new_off, unsigned *dst, unsigned long long nb, void *s);
 
+hipError_t launch_footprints(const ColView &in, unsigned G, unsigned long long *part, unsigned *first, unsigned *last,
+                             unsigned long long *bpart, unsigned G2, unsigned long long *out6, void *s);
+size_t stats_scratch_bytes();
+hipError_t launch_stats(const ColView &in, void *chunks, float *feat, void *s);
+unsigned mlp_nparam();
+unsigned mlp_grad_workgroups(unsigned n);
+hipError_t launch_mlp_forward(const float *params, const float *x, unsigned n, float *y, unsigned *pick, void *s);
+hipError_t launch_mlp_grad(const float *params, const float *x, const float *t, unsigned n, float *gpart,
+                           float *lpart, float *grad, float *loss, void *s);
+hipError_t launch_adam(float *p, const float *g, float *m, float *v, float lr, float b1, float b2, float eps, float c1,
+                       float c2, void *s);
+
 }  // namespace ms

@@ -1055,6 +1055,9 @@ __global__ __launch_bounds__(kWG) void k_shrink_payload(const unsigned *src, con
   }
 }
 
+#include "ms_stats.inc"
+#include "ms_mlp.inc"
+
 // Per-launch timing: when enabled, every launch is bracketed by two events on its stream.
 namespace {
 struct ProfRec {
@@ -1260,6 +1263,41 @@ hipError_t launch_shrink_payload(const unsigned *src, const unsigned *old_off, c
   if (nb == 0) return hipSuccess;
   const unsigned blocks = (unsigned)std::min<unsigned long long>((nb + kWaves - 1) / kWaves, 4096ull);
   MS_LAUNCH(k_shrink_payload, blocks, kWG, s, src, old_off, widths, new_off, dst, nb);
+  return hipGetLastError();
+}
+
+hipError_t launch_footprints(const ColView &in, unsigned G, unsigned long long *part, unsigned *first, unsigned *last,
+                             unsigned long long *bpart, unsigned G2, unsigned long long *out6, void *s) {
+  FpArgs a{in, part, first, last};
+  MS_LAUNCH(k_footprints, G, kWG, s, a);
+  MS_LAUNCH(k_chunk_changes, G2, kWG, s, first, last, in, bpart);
+  MS_LAUNCH(k_footprints_finish, 1, kWG, s, part, G, bpart, G2, in, out6);
+  return hipGetLastError();
+}
+size_t stats_scratch_bytes() { return sizeof(StatChunk) * kStatChunks; }
+hipError_t launch_stats(const ColView &in, void *chunks, float *feat, void *s) {
+  StatChunk *c = static_cast<StatChunk *>(chunks);
+  MS_LAUNCH(k_stats_chunk, kStatChunks, 64, s, in, c);
+  MS_LAUNCH(k_stats_finish, 1, kWG, s, in, c, feat);
+  return hipGetLastError();
+}
+unsigned mlp_nparam() { return kNParam; }
+hipError_t launch_mlp_forward(const float *params, const float *x, unsigned n, float *y, unsigned *pick, void *s) {
+  if (n == 0) return hipSuccess;
+  MS_LAUNCH(k_mlp_forward, (n + 63) / 64, 64, s, params, x, n, y, pick);
+  return hipGetLastError();
+}
+unsigned mlp_grad_workgroups(unsigned n) { return (n + kGradSamples - 1) / kGradSamples; }
+hipError_t launch_mlp_grad(const float *params, const float *x, const float *t, unsigned n, float *gpart,
+                           float *lpart, float *grad, float *loss, void *s) {
+  const unsigned nwg = mlp_grad_workgroups(n);
+  MS_LAUNCH(k_mlp_grad, nwg, kWG, s, params, x, t, n, gpart, lpart);
+  MS_LAUNCH(k_mlp_grad_reduce, (kNParam + kWG - 1) / kWG, kWG, s, gpart, lpart, nwg, grad, loss);
+  return hipGetLastError();
+}
+hipError_t launch_adam(float *p, const float *g, float *m, float *v, float lr, float b1, float b2, float eps, float c1,
+                       float c2, void *s) {
+  MS_LAUNCH(k_adam, (kNParam + kWG - 1) / kWG, kWG, s, p, g, m, v, lr, b1, b2, eps, c1, c2);
   return hipGetLastError();
 }
 

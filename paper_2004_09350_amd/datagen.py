@@ -115,6 +115,15 @@ def he_uniform(seed: int, fan_in: int, count: int) -> np.ndarray:
     return ((2.0 * u - 1.0) * limit).astype(np.float32)
 
 
+
+def mlp_init(seed: int) -> np.ndarray:
+    """Initial parameters of the 32-64-64-6 selector network, float32[6662]:
+    He-uniform weights (seeds seed, seed+1, seed+2 for the three layers), zero biases,
+    in the order W1[64][32], b1[64], W2[64][64], b2[64], W3[6][64], b3[6]."""
+    return np.concatenate([he_uniform(seed, 32, 64 * 32), np.zeros(64, np.float32),
+                           he_uniform(seed + 1, 64, 64 * 64), np.zeros(64, np.float32),
+                           he_uniform(seed + 2, 64, 6 * 64), np.zeros(6, np.float32)])
+
 # Star-style query workload: fact table with four foreign keys and two measures,
 # four dimensions with a filter attribute each; dimension 3 also carries a
 # 250-valued group attribute (floor(k / 10) over 2,500 rows).

@@ -80,6 +80,11 @@ _sigs = {
     "ms_sum": [_P, _P, _P],
     "ms_group_sum": [_P, _P, _U32, _P, _P],
     "ms_sync": [_P],
+    "ms_footprints": [_P, _P, _P],
+    "ms_stats": [_P, _P, _P],
+    "ms_mlp_forward": [_P, _P, _U64, _P, _P, _P],
+    "ms_mlp_grad": [_P, _P, _P, _U64, _P, _P, _P],
+    "ms_adam_step": [_P, _P, _P, _P, _U64, ctypes.c_float, ctypes.c_float, ctypes.c_float, ctypes.c_float, _P],
 }
 for _name, _args in _sigs.items():
     _f = getattr(_lib, _name)
@@ -95,6 +100,9 @@ _lib.ms_prof_get.argtypes = [ctypes.c_uint64, ctypes.POINTER(ctypes.c_char_p), c
 _lib.ms_prof_get.restype = ctypes.c_int
 _lib.ms_prof_reset.argtypes = []
 _lib.ms_prof_reset.restype = None
+_lib.ms_mlp_nparam.argtypes = []
+_lib.ms_mlp_nparam.restype = ctypes.c_uint32
+MLP_NPARAM = int(_lib.ms_mlp_nparam())
 
 
 def lib():
@@ -287,6 +295,66 @@ def group_sum(groups: Column, vals: Column, G: int, out: torch.Tensor | None = N
         out = torch.empty(max(G, 1), dtype=torch.int64, device="cuda")
     _check(_lib.ms_group_sum(groups.handle, vals.handle, G, out.data_ptr(), _stream(stream)))
     return out[:G]
+
+
+def footprints(col: Column, out: torch.Tensor | None = None, stream=None) -> torch.Tensor:
+    """Exact bytes of the column in each of the six formats (int64[6], index = kind)."""
+    if out is None:
+        out = torch.empty(6, dtype=torch.int64, device="cuda")
+    _check(_lib.ms_footprints(col.handle, out.data_ptr(), _stream(stream)))
+    return out
+
+
+def stats(col: Column, out: torch.Tensor | None = None, stream=None) -> torch.Tensor:
+    """The 32 selector features of the column (float32[32], see ms_stats)."""
+    if out is None:
+        out = torch.empty(32, dtype=torch.float32, device="cuda")
+    _check(_lib.ms_stats(col.handle, out.data_ptr(), _stream(stream)))
+    return out
+
+
+def _f32(t: torch.Tensor, *shape) -> torch.Tensor:
+    if t.dtype != torch.float32 or not t.is_cuda or not t.is_contiguous():
+        raise ValueError("expected a contiguous float32 CUDA tensor")
+    if shape and tuple(t.shape) != shape:
+        raise ValueError(f"expected shape {shape}, got {tuple(t.shape)}")
+    return t
+
+
+def mlp_forward(params: torch.Tensor, x: torch.Tensor, want_y: bool = True, want_pick: bool = True, stream=None):
+    """Selector network outputs (n x 6) and argmin picks (n) for features x (n x 32)."""
+    _f32(params, MLP_NPARAM)
+    n = x.shape[0]
+    _f32(x, n, 32)
+    y = torch.empty((n, 6), dtype=torch.float32, device="cuda") if want_y else None
+    pick = torch.empty(n, dtype=torch.int32, device="cuda") if want_pick else None
+    _check(_lib.ms_mlp_forward(params.data_ptr(), x.data_ptr(), n, y.data_ptr() if y is not None else None,
+                               pick.data_ptr() if pick is not None else None, _stream(stream)))
+    return y, pick
+
+
+def mlp_grad(params: torch.Tensor, x: torch.Tensor, t: torch.Tensor, grad: torch.Tensor | None = None,
+             stream=None):
+    """Gradient (6662) and loss (1) of the mean squared error of the network on (x, t)."""
+    _f32(params, MLP_NPARAM)
+    n = x.shape[0]
+    _f32(x, n, 32)
+    _f32(t, n, 6)
+    if grad is None:
+        grad = torch.empty(MLP_NPARAM, dtype=torch.float32, device="cuda")
+    loss = torch.empty(1, dtype=torch.float32, device="cuda")
+    _check(_lib.ms_mlp_grad(params.data_ptr(), x.data_ptr(), t.data_ptr(), n, grad.data_ptr(), loss.data_ptr(),
+                            _stream(stream)))
+    return grad, loss
+
+
+def adam_step(params: torch.Tensor, grad: torch.Tensor, m: torch.Tensor, v: torch.Tensor, step: int,
+              lr: float = 1e-3, beta1: float = 0.9, beta2: float = 0.999, eps: float = 1e-8, stream=None):
+    """One Adam update of params, m and v in place (step counts from 1)."""
+    for t in (params, grad, m, v):
+        _f32(t, MLP_NPARAM)
+    _check(_lib.ms_adam_step(params.data_ptr(), grad.data_ptr(), m.data_ptr(), v.data_ptr(), step, lr, beta1, beta2,
+                             eps, _stream(stream)))
 
 
 def sync(stream=None):
