@@ -54,7 +54,7 @@ def source_sha() -> str:
     h = hashlib.sha256()
     d = os.path.join(ROOT, "paper_2004_09350_amd", "csrc")
     for f in sorted(os.listdir(d)):
-        if f.endswith((".hip", ".h")):
+        if f.endswith((".hip", ".h", ".inc")):
             h.update(open(os.path.join(d, f), "rb").read())
     return h.hexdigest()[:16]
 

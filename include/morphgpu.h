@@ -208,6 +208,78 @@ ms_status ms_mlp_grad(const float *params, const float *x, const float *t, uint6
 ms_status ms_adam_step(float *params, const float *grad, float *m, float *v, uint64_t step, float lr, float beta1,
                        float beta2, float eps, void *stream);
 
+/* ------------------------------------------------------------------------------------
+ * Plans (section 3.3: a query is a plan of operators; every intermediate is materialised
+ * in the format chosen for it; the plan must be consistent, i.e. each operator reads its
+ * inputs in the formats their producers wrote).  A plan is an ordered list of steps over
+ * input columns; it runs eagerly (one launch sequence per step) or as one captured HIP
+ * graph that is replayed.  Independent steps may run on parallel branches (streams).
+ * ---------------------------------------------------------------------------------- */
+typedef enum {
+  MS_OP_MORPH = 0,      /* a -> column in `out`                                        */
+  MS_OP_SELECT = 1,     /* a, cmp, c0, c1 -> position column                           */
+  MS_OP_BITMAP = 2,     /* a (positions), param = domain -> device bitmap              */
+  MS_OP_SEMIJOIN = 3,   /* a (keys), b (a BITMAP step), param = domain -> positions    */
+  MS_OP_PROJECT = 4,    /* a (data), b (positions) -> column                           */
+  MS_OP_INTERSECT = 5,  /* a, b (positions), param = domain -> positions               */
+  MS_OP_SUM = 6,        /* a -> uint64[1]                                              */
+  MS_OP_GROUP_SUM = 7,  /* a (groups), b (values), param = G -> uint64[G]              */
+  MS_OP_FOOTPRINTS = 8, /* a -> uint64[6] (ms_footprints)                              */
+  MS_OP_STATS = 9       /* a -> float[32] (ms_stats)                                   */
+} ms_op_kind;
+
+/* Operand references: k >= 0 is the result of step k (k < this step); -1 - j is input
+ * column j.  Unused operands are ignored. */
+typedef struct {
+  uint32_t op;          /* ms_op_kind */
+  int32_t a, b;
+  uint32_t cmp, c0, c1; /* MS_OP_SELECT */
+  uint64_t param;       /* domain (BITMAP, SEMIJOIN, INTERSECT) or group count (GROUP_SUM) */
+  ms_format out;        /* output format of column-producing steps */
+} ms_step;
+
+/* Launch shape: parallel branches (1..16) and the persistent-grid cap in workgroups per
+ * compute unit (1..32). */
+typedef struct {
+  uint32_t branches;
+  uint32_t wg_per_cu;
+} ms_tune;
+
+typedef struct ms_plan ms_plan;
+
+/* Validates the steps (operand kinds and order) and borrows the input columns, which
+ * must outlive the plan.  Default tune: 1 branch, 8 workgroups per CU. */
+ms_status ms_plan_create(const ms_step *steps, uint32_t n_steps, const ms_column *const *inputs, uint32_t n_inputs,
+                         ms_plan **out);
+ms_status ms_plan_destroy(ms_plan *plan);
+/* Change a step's output format or the launch shape (drops a captured graph). */
+ms_status ms_plan_set_format(ms_plan *plan, uint32_t step, ms_format fmt);
+ms_status ms_plan_set_tune(ms_plan *plan, const ms_tune *tune);
+ms_status ms_plan_get_tune(const ms_plan *plan, ms_tune *tune);
+/* Eager run on `stream`: frees the previous run's results (after synchronising), then
+ * launches step by step through the allocator given to ms_init. */
+ms_status ms_plan_run(ms_plan *plan, void *stream);
+/* Graph run: the first call (or the first after a change) captures the plan into a HIP
+ * graph whose intermediates live in one arena owned by the plan, then every call
+ * replays it on `stream`.  Results stay valid until the next capture or destroy.
+ * Nothing is allocated on replay. */
+ms_status ms_plan_launch(ms_plan *plan, void *stream);
+/* Result of a step of the last run (borrowed): the column for column steps, else the
+ * device pointer of the bitmap / uint64 / float output.  NULL before the first run. */
+ms_status ms_plan_result(const ms_plan *plan, uint32_t step, const ms_column **col, void **dev_ptr);
+/* Copy up to `bytes` of a non-column result of the last run to host memory (synchronises
+ * `stream`); *copied (may be NULL) receives the byte count. */
+ms_status ms_plan_read_result(const ms_plan *plan, uint32_t step, void *host_dst, uint64_t bytes, void *stream,
+                              uint64_t *copied);
+/* Arena bytes of the captured graph (0 before the first ms_plan_launch). */
+uint64_t ms_plan_arena_bytes(const ms_plan *plan);
+/* Autotuner: times ms_plan_launch for every (branches, wg_per_cu) candidate over `reps`
+ * replays and keeps the fastest.  With cache_path, a tune recorded there for the same
+ * plan signature (steps and input shapes) is applied without timing, and new results are
+ * appended.  best (may be NULL) receives the tune; best_ms (may be NULL) its time. */
+ms_status ms_plan_autotune(ms_plan *plan, void *stream, uint32_t reps, const char *cache_path, ms_tune *best,
+                           float *best_ms);
+
 /* Launch timing.  While enabled, every kernel launch is bracketed by two HIP events
  * recorded on its own stream.  Records are kept in launch order until ms_prof_reset.
  * ms_prof_get needs the launches to have finished (call ms_sync first); *name points

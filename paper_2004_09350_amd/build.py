@@ -14,14 +14,14 @@ COMMON = ["-O3", "-std=c++17", "-fPIC", f"--offload-arch={ARCH}",
           "-Xclang", "-target-feature", "-Xclang", "-packed-fp32-ops", "-Wno-unused-command-line-argument"]
 
 LIBS = {
-    "libmorphgpu.so": ["ms_kernels.hip", "ms_api.hip", "ms_mlp.hip", "ms_batch.hip"],
+    "libmorphgpu.so": ["ms_kernels.hip", "ms_api.hip", "ms_plan.hip"],
     "libmsgen.so": ["datagen.hip"],
 }
 
 
 def build_lib(name: str, verbose: bool = True) -> str:
     out = os.path.join(HERE, name)
-    srcs = [os.path.join(CSRC, s) for s in LIBS[name] if os.path.exists(os.path.join(CSRC, s))]
+    srcs = [os.path.join(CSRC, s) for s in LIBS[name]]
     objs = []
     for s in srcs:
         o = os.path.join(CSRC, "_build", os.path.basename(s) + ".o")

@@ -11,6 +11,7 @@
 
 #include "../../include/morphgpu.h"
 #include "ms_kernels.h"
+#include "ms_runtime.h"
 
 using namespace ms;
 
@@ -26,6 +27,7 @@ struct ms_column {
   void *stream;            // stream the buffer was allocated on
   ColView v;
   uint32_t sorted;
+  bool arena;              // buffer lives in a plan's arena (never freed on its own)
 };
 
 namespace {
@@ -48,8 +50,20 @@ ms_status hip_fail(hipError_t e, const char *what) {
   return fail(MS_ERR_HIP, std::string(what) + ": " + hipGetErrorString(e));
 }
 
+// Allocation goes to the calling thread's arena while one is set (plan capture), else to
+// the registered callbacks, else to hipMallocAsync.
+thread_local rt::Arena *t_arena = nullptr;
+thread_local unsigned t_wg_per_cu = 8;
+
 void *dev_alloc(uint64_t bytes, void *stream) {
   if (bytes == 0) bytes = 256;
+  if (t_arena) {
+    const uint64_t at = (t_arena->used + 255) & ~255ull;
+    t_arena->used = at + bytes;
+    if (t_arena->measure) return reinterpret_cast<void *>(rt::kMeasureBase + at);
+    if (t_arena->used > t_arena->size) return nullptr;
+    return t_arena->base + at;
+  }
   if (g_alloc) return g_alloc(bytes, stream, g_ctx);
   void *p = nullptr;
   if (hipMallocAsync(&p, bytes, reinterpret_cast<hipStream_t>(stream)) != hipSuccess) return nullptr;
@@ -57,7 +71,7 @@ void *dev_alloc(uint64_t bytes, void *stream) {
 }
 
 void dev_free(void *p, uint64_t bytes, void *stream) {
-  if (!p) return;
+  if (!p || t_arena) return;
   if (bytes == 0) bytes = 256;
   if (g_free)
     g_free(p, bytes, stream, g_ctx);
@@ -65,8 +79,6 @@ void dev_free(void *p, uint64_t bytes, void *stream) {
     (void)hipFreeAsync(p, reinterpret_cast<hipStream_t>(stream));
 }
 
-
-// Stream-ordered scratch released at scope exit.
 struct Scratch {
   void *stream;
   std::vector<std::pair<void *, uint64_t>> blocks;
@@ -91,7 +103,7 @@ struct Scratch {
 uint64_t align256(uint64_t x) { return (x + 255) & ~255ull; }
 
 unsigned grid_for(uint64_t chunks) {
-  uint64_t max_wg = (uint64_t)g_cus * 8;
+  uint64_t max_wg = (uint64_t)g_cus * t_wg_per_cu;
   uint64_t g = (chunks + 3) / 4;
   if (g < 1) g = 1;
   if (g > max_wg) g = max_wg;
@@ -114,6 +126,7 @@ ms_status alloc_column(uint32_t kind, uint32_t width, uint64_t n_cap, uint64_t n
   c->n_host = kUnknown;
   c->stream = stream;
   c->sorted = 0;
+  c->arena = t_arena != nullptr;
   std::memset(&c->v, 0, sizeof(c->v));
   c->v.kind = kind;
   c->v.width = width;
@@ -184,7 +197,7 @@ ms_status alloc_column(uint32_t kind, uint32_t width, uint64_t n_cap, uint64_t n
 
 void free_column(ms_column *c) {
   if (!c) return;
-  dev_free(c->buf, c->buf_bytes, c->stream);
+  if (!c->arena) dev_free(c->buf, c->buf_bytes, c->stream);
   delete c;
 }
 
@@ -296,6 +309,21 @@ ms_status compaction(const ms_column *in, const PredArgs &pa_in, bool emit_value
 }
 
 }  // namespace
+
+namespace ms {
+namespace rt {
+void set_thread_arena(Arena *a) { t_arena = a; }
+Arena *thread_arena() { return t_arena; }
+void set_thread_wg_per_cu(unsigned w) { t_wg_per_cu = w ? w : 8; }
+unsigned thread_wg_per_cu() { return t_wg_per_cu; }
+void *alloc(uint64_t bytes, void *stream) { return dev_alloc(bytes, stream); }
+void free(void *p, uint64_t bytes, void *stream) { dev_free(p, bytes, stream); }
+unsigned cus() { return (unsigned)g_cus; }
+bool initialized() { return g_init; }
+void set_error(const char *msg) { t_err = msg; }
+uint64_t column_rows_cap(const ms_column *c) { return c->n_host != kUnknown ? c->n_host : c->n_cap; }
+}  // namespace rt
+}  // namespace ms
 
 extern "C" {
 
@@ -409,6 +437,7 @@ ms_status ms_column_shrink(ms_column *col, void *stream) {
   ms_status st = check_init();
   if (st != MS_OK) return st;
   if (!col) return fail(MS_ERR_INVALID_ARG, "column is NULL");
+  if (col->arena) return fail(MS_ERR_INVALID_ARG, "a plan's result column cannot be shrunk");
   ColHdr h;
   st = read_hdr(col, stream, h);
   if (st != MS_OK) return st;

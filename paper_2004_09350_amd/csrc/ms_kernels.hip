@@ -1068,6 +1068,7 @@ std::vector<ProfRec> g_prof;
 std::vector<hipEvent_t> g_ev_pool;
 std::mutex g_prof_mu;
 bool g_prof_on = false;
+thread_local bool t_prof_suspended = false;
 
 hipEvent_t ev_get() {
   if (!g_ev_pool.empty()) {
@@ -1084,7 +1085,7 @@ struct ProfScope {
   ProfRec r{nullptr, nullptr, nullptr};
   hipStream_t s;
   ProfScope(const char *name, void *stream) : s(reinterpret_cast<hipStream_t>(stream)) {
-    if (!g_prof_on) return;
+    if (!g_prof_on || t_prof_suspended) return;
     std::lock_guard<std::mutex> g(g_prof_mu);
     r.name = name;
     r.a = ev_get();
@@ -1101,6 +1102,7 @@ struct ProfScope {
 }  // namespace
 
 void prof_enable(bool on) { g_prof_on = on; }
+void prof_suspend(bool on) { t_prof_suspended = on; }
 size_t prof_count() {
   std::lock_guard<std::mutex> g(g_prof_mu);
   return g_prof.size();

@@ -62,6 +62,15 @@ _PP = ctypes.POINTER(ctypes.c_void_p)
 _ALLOC_T = ctypes.CFUNCTYPE(ctypes.c_void_p, ctypes.c_uint64, ctypes.c_void_p, ctypes.c_void_p)
 _FREE_T = ctypes.CFUNCTYPE(None, ctypes.c_void_p, ctypes.c_uint64, ctypes.c_void_p, ctypes.c_void_p)
 
+class Step(ctypes.Structure):
+    _fields_ = [("op", ctypes.c_uint32), ("a", ctypes.c_int32), ("b", ctypes.c_int32), ("cmp", ctypes.c_uint32),
+                ("c0", ctypes.c_uint32), ("c1", ctypes.c_uint32), ("param", ctypes.c_uint64), ("out", Format)]
+
+
+class Tune(ctypes.Structure):
+    _fields_ = [("branches", ctypes.c_uint32), ("wg_per_cu", ctypes.c_uint32)]
+
+
 _sigs = {
     "ms_init": [_ALLOC_T, _FREE_T, _P],
     "ms_column_encode": [_P, _U64, Format, _P, _PP],
@@ -84,6 +93,16 @@ _sigs = {
     "ms_stats": [_P, _P, _P],
     "ms_mlp_forward": [_P, _P, _U64, _P, _P, _P],
     "ms_mlp_grad": [_P, _P, _P, _U64, _P, _P, _P],
+    "ms_plan_create": [ctypes.POINTER(Step), _U32, ctypes.POINTER(_P), _U32, _PP],
+    "ms_plan_destroy": [_P],
+    "ms_plan_set_format": [_P, _U32, Format],
+    "ms_plan_set_tune": [_P, ctypes.POINTER(Tune)],
+    "ms_plan_get_tune": [_P, ctypes.POINTER(Tune)],
+    "ms_plan_run": [_P, _P],
+    "ms_plan_launch": [_P, _P],
+    "ms_plan_result": [_P, _U32, _PP, _PP],
+    "ms_plan_read_result": [_P, _U32, _P, _U64, _P, ctypes.POINTER(_U64)],
+    "ms_plan_autotune": [_P, _P, _U32, ctypes.c_char_p, ctypes.POINTER(Tune), ctypes.POINTER(ctypes.c_float)],
     "ms_adam_step": [_P, _P, _P, _P, _U64, ctypes.c_float, ctypes.c_float, ctypes.c_float, ctypes.c_float, _P],
 }
 for _name, _args in _sigs.items():
@@ -103,6 +122,8 @@ _lib.ms_prof_reset.restype = None
 _lib.ms_mlp_nparam.argtypes = []
 _lib.ms_mlp_nparam.restype = ctypes.c_uint32
 MLP_NPARAM = int(_lib.ms_mlp_nparam())
+_lib.ms_plan_arena_bytes.argtypes = [_P]
+_lib.ms_plan_arena_bytes.restype = ctypes.c_uint64
 
 
 def lib():
@@ -161,19 +182,20 @@ def init(use_torch_allocator: bool = True):
 class Column:
     """A compressed column on the device (owns an ms_column*)."""
 
-    def __init__(self, handle: int, keep=None, stream=None):
+    def __init__(self, handle: int, keep=None, stream=None, owned: bool = True):
         self._h = ctypes.c_void_p(handle)
-        self._keep = keep  # device tensors a wrapped column borrows
+        self._keep = keep  # device tensors a wrapped column borrows (or the plan owning a result)
         self._stream = _stream(stream)
+        self._owned = owned
 
     @property
     def handle(self):
         return self._h
 
     def free(self):
-        if self._h and self._h.value:
+        if self._h and self._h.value and self._owned:
             _lib.ms_column_free(self._h)
-            self._h = ctypes.c_void_p(0)
+        self._h = ctypes.c_void_p(0)
 
     def __del__(self):
         try:
@@ -355,6 +377,96 @@ def adam_step(params: torch.Tensor, grad: torch.Tensor, m: torch.Tensor, v: torc
         _f32(t, MLP_NPARAM)
     _check(_lib.ms_adam_step(params.data_ptr(), grad.data_ptr(), m.data_ptr(), v.data_ptr(), step, lr, beta1, beta2,
                              eps, _stream(stream)))
+
+
+# ----------------------------------------------------------------------------------- plans
+OP_MORPH, OP_SELECT, OP_BITMAP, OP_SEMIJOIN, OP_PROJECT, OP_INTERSECT, OP_SUM, OP_GROUP_SUM, OP_FOOTPRINTS, \
+    OP_STATS = range(10)
+_RESULT_BYTES = {OP_SUM: lambda p: 8, OP_GROUP_SUM: lambda p: 8 * max(p, 1), OP_FOOTPRINTS: lambda p: 48,
+                 OP_STATS: lambda p: 128, OP_BITMAP: lambda p: 4 * ((p + 31) // 32)}
+
+
+def step(op: int, a: int = -1, b: int = -1, out: Format | None = None, cmp: int = 0, c0: int = 0, c1: int = 0,
+         param: int = 0) -> Step:
+    """One plan step; operands: k >= 0 the result of step k, -1 - j input column j."""
+    return Step(op, a, b, cmp, c0 & 0xFFFFFFFF, c1 & 0xFFFFFFFF, param, out if out is not None else fmt(UNCOMPR))
+
+
+def inp(j: int) -> int:
+    """Operand reference to input column j."""
+    return -1 - j
+
+
+class Plan:
+    """An operator plan over input columns, run eagerly (run) or as a replayed HIP graph (launch)."""
+
+    def __init__(self, steps, inputs):
+        self.steps = list(steps)
+        self.inputs = list(inputs)  # kept alive: the plan borrows them
+        arr = (Step * max(len(self.steps), 1))(*self.steps)
+        ins = (_P * max(len(self.inputs), 1))(*[c.handle.value for c in self.inputs])
+        h = ctypes.c_void_p(0)
+        _check(_lib.ms_plan_create(arr, len(self.steps), ins, len(self.inputs), ctypes.byref(h)))
+        self._h = h
+
+    def close(self):
+        if self._h and self._h.value:
+            _lib.ms_plan_destroy(self._h)
+            self._h = ctypes.c_void_p(0)
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+    def set_format(self, i: int, f: Format):
+        _check(_lib.ms_plan_set_format(self._h, i, f))
+        self.steps[i].out = f
+
+    def set_tune(self, branches: int, wg_per_cu: int):
+        t = Tune(branches, wg_per_cu)
+        _check(_lib.ms_plan_set_tune(self._h, ctypes.byref(t)))
+
+    def tune(self) -> tuple:
+        t = Tune()
+        _check(_lib.ms_plan_get_tune(self._h, ctypes.byref(t)))
+        return t.branches, t.wg_per_cu
+
+    def run(self, stream=None):
+        _check(_lib.ms_plan_run(self._h, _stream(stream)))
+
+    def launch(self, stream=None):
+        _check(_lib.ms_plan_launch(self._h, _stream(stream)))
+
+    def autotune(self, reps: int = 3, cache: str | None = None, stream=None):
+        t = Tune()
+        ms = ctypes.c_float(0)
+        _check(_lib.ms_plan_autotune(self._h, _stream(stream), reps, cache.encode() if cache else None,
+                                     ctypes.byref(t), ctypes.byref(ms)))
+        return (t.branches, t.wg_per_cu), ms.value
+
+    def arena_bytes(self) -> int:
+        return int(_lib.ms_plan_arena_bytes(self._h))
+
+    def column(self, i: int) -> Column:
+        """Borrowed view of step i's result column (valid until the next run, capture or close)."""
+        c = ctypes.c_void_p(0)
+        _check(_lib.ms_plan_result(self._h, i, ctypes.byref(c), None))
+        if not c.value:
+            raise MorphError(1, "step has no column result")
+        return Column(c.value, keep=self, owned=False)
+
+    def read(self, i: int, stream=None) -> np.ndarray:
+        """Host copy of a non-column result: uint64 for sums, group sums and footprints,
+        float32 for statistics, uint32 words for bitmaps."""
+        s = self.steps[i]
+        nbytes = _RESULT_BYTES[s.op](s.param)
+        buf = np.zeros(max(nbytes, 8), np.uint8)
+        got = _U64(0)
+        _check(_lib.ms_plan_read_result(self._h, i, buf.ctypes.data, nbytes, _stream(stream), ctypes.byref(got)))
+        dt = {OP_STATS: np.float32, OP_BITMAP: np.uint32}.get(s.op, np.uint64)
+        return buf[: got.value].view(dt).copy()
 
 
 def sync(stream=None):

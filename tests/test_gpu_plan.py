@@ -1,0 +1,189 @@
+"""GPU parity of whole plans (eager and captured-graph runs) against the oracle's plans:
+Q1 and the star query Q3 under every format policy, parallel branches, graph replays
+interleaved with other work, and the autotuner's cache."""
+import numpy as np
+import pytest
+
+import oracle as O
+import oracle.queries as OQ
+from paper_2004_09350_amd import datagen
+
+pytestmark = pytest.mark.gpu
+
+
+@pytest.fixture(scope="module")
+def M():
+    import torch
+    if not torch.cuda.is_available():
+        pytest.skip("no GPU")
+    from paper_2004_09350_amd import morphgpu
+    morphgpu.init()
+    return morphgpu
+
+
+@pytest.fixture(scope="module")
+def Q():
+    from paper_2004_09350_amd import queries
+    return queries
+
+
+def dec(M, col):
+    return M.u32(col.decode())
+
+
+def q1_inputs(M, n):
+    a = datagen.uniform_bits(1, n, 10)
+    b = datagen.uniform_bits(2, n, 20)
+    return a, b, M.encode(a, M.fmt(M.STATIC_BP, 10)), M.encode(b, M.fmt(M.STATIC_BP, 20))
+
+
+@pytest.mark.parametrize("n", [0, 1, 100_003, 1_000_000, 1 << 20])
+def test_q1_eager_and_graph(M, Q, n):
+    a, b, A, B = q1_inputs(M, n)
+    want = OQ.q1(a, b, 103)
+    plan = Q.q1_plan(A, B, 103)
+    plan.run()
+    assert int(plan.read(2)[0]) == want["sum"]
+    np.testing.assert_array_equal(dec(M, plan.column(0)), want["P"])
+    np.testing.assert_array_equal(dec(M, plan.column(1)), want["Bp"])
+    other = M.encode(datagen.uniform_bits(3, 70_001, 7), M.fmt(M.DYN_BP))
+    for rep in range(4):  # replays with unrelated eager work and syncs in between
+        plan.launch()
+        M.sync()
+        assert int(plan.read(2)[0]) == want["sum"], rep
+        np.testing.assert_array_equal(dec(M, plan.column(0)), want["P"])
+        np.testing.assert_array_equal(dec(M, plan.column(1)), want["Bp"])
+        s = M.sum_(other)
+        M.sync()
+        assert int(s.cpu()) & 0xFFFFFFFFFFFFFFFF == O.sum_(datagen.uniform_bits(3, 70_001, 7))
+    assert plan.arena_bytes() > 0
+    plan.close()
+
+
+N_FACT = 400_003
+SEL = (0.20, 0.20, 0.20, 0.20)
+
+
+@pytest.fixture(scope="module")
+def star(M):
+    cols = datagen.star_columns(5, N_FACT)
+    thr = datagen.star_thresholds(SEL)
+    want = OQ.q3(cols, thr, datagen.STAR_DIM_SIZES)
+    enc = {k: M.encode(v, M.fmt(M.STATIC_BP)) for k, v in cols.items()}
+    return cols, thr, want, enc
+
+
+def check_q3(M, q3, want, intermediates=True):
+    o1, o2 = q3.results()
+    np.testing.assert_array_equal(o1, want["out1"])
+    np.testing.assert_array_equal(o2, want["out2"])
+    if intermediates:
+        for name, i in q3.names.items():
+            np.testing.assert_array_equal(dec(M, q3.plan.column(i)), want["intermediates"][name], err_msg=name)
+
+
+@pytest.mark.parametrize("policy", ["default", "uncompr", "static", "mixed"])
+def test_q3_policies(M, Q, star, policy):
+    cols, thr, want, enc = star
+    q3 = Q.Q3(enc, thr, datagen.STAR_DIM_SIZES, N_FACT)
+    names = list(q3.names)
+    if policy == "uncompr":
+        q3.set_formats(Q.uniform_formats(names, M.UNCOMPR))
+    elif policy == "static":
+        q3.set_formats(Q.uniform_formats(names, M.STATIC_BP))
+    elif policy == "mixed":
+        q3.set_formats({n: M.fmt(k % 6) for k, n in enumerate(names)})
+    q3.plan.run()
+    check_q3(M, q3, want)
+    q3.plan.launch()
+    M.sync()
+    check_q3(M, q3, want, intermediates=(policy == "mixed"))
+    q3.plan.close()
+
+
+def test_q3_exhaustive_matches_oracle(M, Q, star):
+    cols, thr, want, enc = star
+    q3 = Q.Q3(enc, thr, datagen.STAR_DIM_SIZES, N_FACT)
+    q3.plan.run()
+    fmts, fps = Q.exhaustive_formats(q3.plan, q3.names)
+    ofp = OQ.plan_footprints(want["intermediates"])
+    for name in q3.names:
+        np.testing.assert_array_equal(fps[name], ofp[name], err_msg=name)
+    ochoice = OQ.exhaustive_choice(want["intermediates"])
+    assert {n: f.kind for n, f in fmts.items()} == ochoice
+    q3.set_formats(fmts)
+    q3.plan.launch()
+    M.sync()
+    check_q3(M, q3, want)
+    assert q3.footprint() == sum(int(ofp[n][ochoice[n]]) for n in q3.names)
+    q3.plan.close()
+
+
+@pytest.mark.parametrize("tune", [(2, 4), (4, 8), (8, 2)])
+def test_q3_branches(M, Q, star, tune):
+    cols, thr, want, enc = star
+    q3 = Q.Q3(enc, thr, datagen.STAR_DIM_SIZES, N_FACT)
+    q3.plan.set_tune(*tune)
+    assert q3.plan.tune() == tune
+    q3.plan.run()
+    check_q3(M, q3, want)
+    for _ in range(3):
+        q3.plan.launch()
+        M.sync()
+        check_q3(M, q3, want, intermediates=False)
+    q3.plan.close()
+
+
+def test_q3_stats_and_footprint_steps(M, Q, star):
+    cols, thr, want, enc = star
+    q3 = Q.Q3(enc, thr, datagen.STAR_DIM_SIZES, N_FACT, extra=("stats", "footprints"))
+    q3.plan.launch()
+    M.sync()
+    ofp = OQ.plan_footprints(want["intermediates"])
+    for name in q3.names:
+        np.testing.assert_array_equal(q3.plan.read(q3.fp_step[name]), ofp[name], err_msg=name)
+        np.testing.assert_allclose(q3.plan.read(q3.stats_step[name]).astype(np.float64),
+                                   O.stats(want["intermediates"][name]), rtol=0, atol=1e-6, err_msg=name)
+    q3.plan.close()
+
+
+def test_autotune_and_cache(M, Q, tmp_path):
+    a, b, A, B = q1_inputs(M, 300_000)
+    want = OQ.q1(a, b, 103)
+    cache = str(tmp_path / "tune.txt")
+    plan = Q.q1_plan(A, B, 103)
+    best, ms = plan.autotune(reps=2, cache=cache)
+    assert best[0] in (1, 2, 4, 8) and best[1] in (2, 4, 8, 16) and ms > 0
+    assert plan.tune() == best
+    lines = open(cache).read().split()
+    assert len(lines) == 4 and (int(lines[1]), int(lines[2])) == best
+    plan.launch()
+    assert int(plan.read(2)[0]) == want["sum"]
+    plan2 = Q.q1_plan(A, B, 103)
+    best2, ms2 = plan2.autotune(reps=2, cache=cache)  # from the cache, no timing
+    assert best2 == best and abs(ms2 - float(lines[3])) < 1e-3
+    plan2.run()
+    assert int(plan2.read(2)[0]) == want["sum"]
+    plan.close()
+    plan2.close()
+
+
+def test_plan_errors(M):
+    col = M.encode(datagen.uniform_bits(1, 1000, 5), M.fmt(M.UNCOMPR))
+    with pytest.raises(M.MorphError):  # forward reference
+        M.Plan([M.step(M.OP_SUM, a=1), M.step(M.OP_SUM, a=M.inp(0))], [col])
+    with pytest.raises(M.MorphError):  # semi-join operand is not a bitmap step
+        M.Plan([M.step(M.OP_SELECT, a=M.inp(0), cmp=M.LT, c0=3),
+                M.step(M.OP_SEMIJOIN, a=M.inp(0), b=0, param=32)], [col])
+    with pytest.raises(M.MorphError):  # input out of range
+        M.Plan([M.step(M.OP_SUM, a=M.inp(1))], [col])
+    with pytest.raises(M.MorphError):  # a sum is not a column
+        M.Plan([M.step(M.OP_SUM, a=M.inp(0)), M.step(M.OP_MORPH, a=0)], [col])
+    p = M.Plan([M.step(M.OP_SUM, a=M.inp(0))], [col])
+    with pytest.raises(M.MorphError):
+        p.set_format(0, M.fmt(M.RLE))
+    with pytest.raises(M.MorphError):
+        p.set_tune(0, 8)
+    p.run()
+    assert int(p.read(0)[0]) == O.sum_(datagen.uniform_bits(1, 1000, 5))
+    p.close()
