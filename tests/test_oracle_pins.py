@@ -403,3 +403,33 @@ def test_adam_first_step_closed_form():
     O.adam_step(p, g, m, v, 1, 0.01)
     # after one step the bias-corrected moments are g and g^2: the update is lr * g / (|g| + eps)
     np.testing.assert_allclose(p, p0 - 0.01 * g / (np.abs(g) + 1e-8), rtol=1e-12)
+
+
+# ----------------------------------------------------------------------------- query plans
+def test_q1_plan_matches_numpy():
+    import oracle.queries as OQ
+    a = datagen.uniform_bits(41, 50_000, 10)
+    b = datagen.uniform_bits(42, 50_000, 20)
+    r = OQ.q1(a, b, 103)
+    np.testing.assert_array_equal(r["P"], np.nonzero(a < 103)[0])
+    np.testing.assert_array_equal(r["Bp"], b[a < 103])
+    assert r["sum"] == int(b[a < 103].astype(np.uint64).sum())
+
+
+def test_q3_plan_matches_numpy():
+    """The star plan as one numpy expression: a fact row qualifies when every foreign key
+    points at a dimension row passing its filter; group by floor(fk3 / 10)."""
+    import oracle.queries as OQ
+    dims = (2000, 30_000, 20_000, 2500)
+    n = 60_000
+    cols = datagen.star_columns(9, n, dims)
+    thr = datagen.star_thresholds((0.2, 0.3, 0.5, 0.4))
+    r = OQ.q3(cols, thr, dims)
+    ok = np.ones(n, bool)
+    for d in range(4):
+        ok &= (cols[f"dimattr{d}"] < thr[d])[cols[f"fk{d}"]]
+    g = cols["fk3"][ok] // 10
+    np.testing.assert_array_equal(r["intermediates"]["P"], np.nonzero(ok)[0])
+    np.testing.assert_array_equal(r["out1"], np.bincount(g, weights=cols["m1"][ok], minlength=250).astype(np.uint64))
+    np.testing.assert_array_equal(r["out2"], np.bincount(g, weights=cols["m2"][ok], minlength=250).astype(np.uint64))
+    assert ok.sum() > 100
