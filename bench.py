@@ -37,10 +37,18 @@ SELECTIVITIES = (0.01, 0.10, 0.50)
 def parse():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
+    ap.add_argument("--workload", default="sweep", choices=("sweep", "star", "batch", "q1"),
+                    help="sweep: operator/format sweep (default); star: star query under every format "
+                         "policy; batch: 512 mixed tasks, one graph vs one launch sequence per task; "
+                         "q1: the simple select-project-sum query")
     ap.add_argument("--steps", type=int, default=3)
     ap.add_argument("--warmup", type=int, default=1)
-    ap.add_argument("--rows", type=int, default=100_000_000)
-    ap.add_argument("--cpu-rows", type=int, default=600_000)
+    ap.add_argument("--rows", type=int, default=None, help="rows per column (default per workload)")
+    ap.add_argument("--seeds", default="1", help="star: comma-separated instance seeds")
+    ap.add_argument("--tasks", type=int, default=512, help="batch: number of tasks")
+    ap.add_argument("--weights", default=None, help="star: selector weights (.npy); default: the packaged ones")
+    ap.add_argument("--cpu-rows", type=int, default=None,
+                    help="rows of the CPU oracle sample (default per workload: sweep 1.2e6, star 4e7, batch 1e6 per task)")
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--quick", action="store_true", help="fewer operators (for profiling runs)")
     ap.add_argument("--dump", default=None, help="write per-operator kernel timings (JSON) to this file")
@@ -268,36 +276,51 @@ def cpu_baseline(rows: int):
                        f"{dt:.1f} s", seconds=round(dt, 2))
 
 
-def main():
-    args = parse()
-    if args.gpus != 1:
-        print(json.dumps({"error": "this build runs on one GPU; --gpus must be 1 (multi-GPU sharding is "
-                                   "described in DESIGN.md but not built)"}))
-        sys.exit(2)
-    import torch
+KIND_NAMES = ("UNCOMPR", "STATIC_BP", "DYN_BP", "DELTA_DYN_BP", "FOR_DYN_BP", "RLE")
 
-    from paper_2004_09350_amd import gen_gpu as gen
-    from paper_2004_09350_amd import morphgpu as M
 
-    log = lambda *a: print(*a, file=sys.stderr, flush=True)
-    M.init()
-    sw = Sweep(M, gen, args.rows, args.quick, log)
+def traffic_for(kernel: str):
+    """HBM bytes per launch of `kernel` from the committed counter summary, while its
+    source hash matches the kernels being measured (else None)."""
+    f = os.path.join(ROOT, "profiles", "traffic.json")
+    if not os.path.exists(f):
+        return None
+    try:
+        t = json.load(open(f))
+        if t.get("source_sha") == source_sha() and kernel in t.get("kernels", {}):
+            return t["kernels"][kernel]["bytes_per_launch"]
+    except Exception:
+        pass
+    return None
+
+
+def base_line(args, metric, value, unit, dt, workload, extra_config=None):
+    cfg = {"workload": workload}
+    cfg.update(extra_config or {})
+    return {"metric": metric, "value": value, "unit": unit, "n_gpus": 1, "steps": args.steps,
+            "warmup": args.warmup, "ms_per_step": round(dt * 1e3, 3), "higher_is_better": True,
+            "scaling": "weak", "vs_baseline": None, "dtype": "u32", "data": "synthetic", "config": cfg}
+
+
+def run_sweep(args, M, gen, torch, log):
+    rows = args.rows or 100_000_000
+    sw = Sweep(M, gen, rows, args.quick, log)
     if args.calib_copy:
         dst = sw.cols[("U32", M.UNCOMPR)].decode()
         M.sync()
-        log(f"calibration copy: k_decode of {args.rows} rows ({4 * args.rows} B read, {4 * args.rows} B written)")
+        log(f"calibration copy: k_decode of {rows} rows ({4 * rows} B read, {4 * rows} B written)")
         del dst
     sw.account()
     log("accounting pass done")
     if args.dump:
         KN = M.KIND_NAMES
-        rows = []
+        rows_ = []
         for a in sw.acct:
             name, key, c, kout = a["op"]
-            rows.append(dict(op=name, dist=key[0] if key else None, kin=KN[key[1]] if key else None, c=c,
-                             kout=KN[kout] if kout is not None else None, recs=a["recs"], alg=a["alg"],
-                             ue=a["ue"], out_fp=a["out_fp"]))
-        json.dump(rows, open(args.dump, "w"))
+            rows_.append(dict(op=name, dist=key[0] if key else None, kin=KN[key[1]] if key else None, c=c,
+                              kout=KN[kout] if kout is not None else None, recs=a["recs"], alg=a["alg"],
+                              ue=a["ue"], out_fp=a["out_fp"]))
+        json.dump(rows_, open(args.dump, "w"))
     for _ in range(args.warmup):
         sw.step()
     M.sync()
@@ -313,38 +336,432 @@ def main():
     ue = sum(a["ue"] for a in sw.acct)
     alg = sum(a["alg"] for a in sw.acct)
     dom, roof, dominfo = roofline(sw.acct)
-    res = {
-        "metric": "uncompressed-equivalent GB/s of the fused operator sweep (plus %HBM roofline on compressed bytes)",
-        "value": round(ue / dt / 1e9, 2),
-        "unit": "GB/s",
-        "n_gpus": 1,
-        "steps": args.steps,
-        "warmup": args.warmup,
-        "ms_per_step": round(dt * 1e3, 3),
-        "higher_is_better": True,
-        "scaling": "weak",
-        "vs_baseline": None,
-        "dtype": "u32",
-        "data": "synthetic",
-        "config": {"workload": "operator/format sweep: 6 distributions x 6 formats of 1e8-row uint32 columns; "
-                               "select 1/10/50 % -> 6 formats, project at a 10 % position list -> 6 formats, "
-                               "sum, intersect -> 6 formats, morph between all 30 format pairs",
-                   "rows": args.rows, "operators_per_step": len(sw.ops)},
-        "hbm_frac_step": round(alg / dt / 1e9 / HBM_PEAK_GBS, 4),
-        "roofline": roof,
-        "dominant_kernel": dominfo,
-        "source_sha": source_sha(),
-    }
-    traffic_file = os.path.join(ROOT, "profiles", "traffic.json")
-    if os.path.exists(traffic_file):
-        try:
-            t = json.load(open(traffic_file))
-            if t.get("source_sha") == res["source_sha"] and dom in t.get("kernels", {}):
-                res["roofline"]["traffic"] = t["kernels"][dom]["bytes_per_launch"]
-        except Exception:
-            pass
+    res = base_line(args, "uncompressed-equivalent GB/s of the fused operator sweep (plus %HBM roofline on "
+                          "compressed bytes)", round(ue / dt / 1e9, 2), "GB/s", dt,
+                    "operator/format sweep: 6 distributions x 6 formats of 1e8-row uint32 columns; select "
+                    "1/10/50 % -> 6 formats, project at a 10 % position list -> 6 formats, sum, intersect -> 6 "
+                    "formats, morph between all 30 format pairs", {"rows": rows, "operators_per_step": len(sw.ops)})
+    res.update(hbm_frac_step=round(alg / dt / 1e9 / HBM_PEAK_GBS, 4), roofline=roof, dominant_kernel=dominfo,
+               source_sha=source_sha())
+    res["roofline"]["traffic"] = traffic_for(dom)
     if not args.no_cpu_baseline:
-        res["cpu_baseline"] = cpu_baseline(args.cpu_rows)
+        res["cpu_baseline"] = cpu_baseline(args.cpu_rows or 1_200_000)
+    return res
+
+
+# ------------------------------------------------------------------------------ plans
+def sectors_touched(M, pos_col) -> int:
+    """Distinct 64-byte sectors of a 4-byte column touched by a position list."""
+    import torch
+    p = pos_col.decode().to(torch.int64) & 0xFFFFFFFF
+    return int(torch.unique(p >> 4).numel()) if p.numel() else 0
+
+
+def plan_account(M, plan, inputs, log=None):
+    """Uncompressed-equivalent and algorithmic bytes of every step of a plan's last run,
+    the latter split over the kernels each step launches (same rules as the sweep)."""
+    steps = plan.steps
+    info = {}
+
+    def col(ref):
+        return inputs[-1 - ref] if ref < 0 else plan.column(ref)
+
+    def inf(ref):
+        if ref not in info:
+            info[ref] = col(ref).info()
+        return info[ref]
+
+    ue_total, alg = 0, {}
+
+    def add(k, b):
+        alg[k] = alg.get(k, 0) + int(b)
+
+    for i, s in enumerate(steps):
+        op = s.op
+        if op in (M.OP_MORPH, M.OP_SELECT, M.OP_SEMIJOIN, M.OP_PROJECT, M.OP_INTERSECT):
+            out = inf(i)
+            kout = KIND_NAMES[s.out.kind]
+        if op == M.OP_MORPH:
+            a = inf(s.a)
+            ue_total += 8 * a["n"]
+            if s.out.kind == M.RLE:
+                add("k_rle_count", a["footprint"]); add("k_rle_emit", out["footprint"])
+            else:
+                add(f"k_morph<{kout}>", a["footprint"] + out["footprint"])
+        elif op in (M.OP_SELECT, M.OP_SEMIJOIN):
+            a = inf(s.a)
+            ue_total += 4 * (a["n"] + out["n"])
+            add("k_pred<0>" if op == M.OP_SELECT else "k_pred<1>", a["footprint"])
+            add("k_emit", out["footprint"])
+        elif op == M.OP_BITMAP:
+            a = inf(s.a)
+            ue_total += 4 * a["n"]
+            add("k_bitmap", a["footprint"])
+        elif op == M.OP_INTERSECT:
+            a, b = inf(s.a), inf(s.b)
+            ue_total += 4 * (a["n"] + b["n"] + out["n"])
+            probe, build = (a, b) if a["capacity_bytes"] <= b["capacity_bytes"] else (b, a)
+            add("k_bitmap", build["footprint"]); add("k_pred<2>", probe["footprint"]); add("k_emit", out["footprint"])
+        elif op == M.OP_PROJECT:
+            d, p = inf(s.a), inf(s.b)
+            sec = sectors_touched(M, col(s.b))
+            nsec = max((d["n"] + 15) // 16, 1)
+            data = int(d["footprint"] * sec / nsec)
+            ue_total += 8 * p["n"] + 64 * sec
+            if s.out.kind == M.RLE:
+                add("k_rle_count", p["footprint"] + data); add("k_rle_emit", out["footprint"])
+            else:
+                add(f"k_project<{kout}>", p["footprint"] + out["footprint"] + data)
+        elif op == M.OP_SUM:
+            a = inf(s.a)
+            ue_total += 4 * a["n"] + 8
+            add("k_sum", a["footprint"])
+        elif op == M.OP_GROUP_SUM:
+            g, v = inf(s.a), inf(s.b)
+            ue_total += 4 * (g["n"] + v["n"]) + 8 * s.param
+            add("k_group_sum", g["footprint"] + v["footprint"] + 8 * s.param)
+    return ue_total, alg
+
+
+def plan_roofline(M, plan, alg):
+    """Dominant kernel of one profiled eager run; achieved = its algorithmic bytes per
+    launch / its mean launch time."""
+    M.sync()
+    tune = plan.tune()
+    plan.set_tune(1, tune[1])  # one branch: concurrent kernels would inflate each launch's events
+    M.prof_enable(True)
+    M.prof_reset()
+    plan.run()
+    M.sync()
+    recs = M.prof_records(0)
+    M.prof_enable(False)
+    M.prof_reset()
+    plan.set_tune(*tune)
+    tot, cnt = {}, {}
+    for k, ms in recs:
+        tot[k] = tot.get(k, 0.0) + ms
+        cnt[k] = cnt.get(k, 0) + 1
+    dom = max(tot, key=tot.get)
+    avg_ms = tot[dom] / cnt[dom]
+    bpl = alg.get(dom, 0) / cnt[dom]
+    ach = bpl / (avg_ms * 1e-3) / 1e9
+    roof = dict(bound="hbm", achieved=round(ach, 1), peak=HBM_PEAK_GBS, unit="GB/s",
+                frac=round(ach / HBM_PEAK_GBS, 4), traffic=traffic_for(dom))
+    info = dict(kernel=dom, launches=cnt[dom], avg_ms=round(avg_ms, 4), bytes_per_launch=int(bpl),
+                share_of_run=round(tot[dom] / sum(tot.values()), 3),
+                per_kernel_ms={k: round(v, 3) for k, v in sorted(tot.items())})
+    return roof, info
+
+
+def time_graph(torch, plan, reps):
+    plan.launch()
+    torch.cuda.synchronize()
+    e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+    e0.record()
+    for _ in range(reps):
+        plan.launch()
+    e1.record()
+    e1.synchronize()
+    return e0.elapsed_time(e1) / reps / 1e3
+
+
+def time_eager(torch, plan, reps):
+    plan.run()
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    for _ in range(reps):
+        plan.run()
+    torch.cuda.synchronize()
+    return (time.perf_counter() - t0) / reps
+
+
+# ------------------------------------------------------------------------------ star query
+POLICIES = ("uncompr", "static", "exhaustive", "learned")
+
+
+def run_star(args, M, gen, torch, log):
+    from paper_2004_09350_amd import datagen, queries, selector
+    n = args.rows or 600_000_000
+    wpath = args.weights or os.path.join(ROOT, "paper_2004_09350_amd", "selector_weights.npy")
+    if os.path.exists(wpath):
+        params = selector.load(wpath)
+        wsrc = os.path.relpath(wpath, ROOT)
+    else:
+        log("no selector weights: training on 300 star plans")
+        X, F, N, _ = selector.collect(300, log=log)
+        params = selector.train(X, selector.targets(F, N), epochs=60, log=log)
+        wsrc = "trained in this run on 300 plans"
+    settings = (("wide", datagen.STAR_WIDE), ("narrow", datagen.STAR_NARROW))
+    results, ue_sum, t_sum = [], 0, 0.0
+    roof = dom = None
+    for seed in [int(x) for x in args.seeds.split(",")]:
+        t0 = time.time()
+        cols, _ = selector.star_inputs(seed, n)
+        torch.cuda.synchronize()
+        base_fp = sum(c.info()["footprint"] for c in cols.values())
+        log(f"seed {seed}: base columns {base_fp / 1e9:.2f} GB compressed, {time.time() - t0:.1f}s")
+        for sname, sel in settings:
+            thr = datagen.star_thresholds(sel)
+            probe = queries.Q3(cols, thr, datagen.STAR_DIM_SIZES, n, extra=("stats", "footprints"))
+            probe.plan.run()
+            fps = {k: probe.plan.read(probe.fp_step[k]) for k in probe.names}
+            feats = np.stack([probe.plan.read(probe.stats_step[k]) for k in probe.names])
+            ref = probe.results()
+            probe.plan.close()
+            picks = selector.pick(params, feats)
+            fmts = {"uncompr": queries.uniform_formats(fps, M.UNCOMPR),
+                    "static": queries.uniform_formats(fps, M.STATIC_BP),
+                    "exhaustive": {k: M.fmt(int(np.argmin(f))) for k, f in fps.items()},
+                    "learned": {k: M.fmt(int(p)) for k, p in zip(fps, picks)}}
+            row = dict(seed=seed, setting=sname, rows_final=0, policies={})
+            for pol in POLICIES:
+                q = queries.Q3(cols, thr, datagen.STAR_DIM_SIZES, n, formats=fmts[pol])
+                q.plan.set_tune(2, 8)
+                tg = time_graph(torch, q.plan, args.steps)
+                te = time_eager(torch, q.plan, max(1, args.steps // 2))
+                o1, o2 = q.results()
+                if not (np.array_equal(o1, ref[0]) and np.array_equal(o2, ref[1])):
+                    raise SystemExit(f"star query answers differ under policy {pol}")
+                fp = sum(int(fps[k][fmts[pol][k].kind]) for k in fps)
+                ue, alg = plan_account(M, q.plan, q.plan.inputs)
+                row["rows_final"] = int(q.plan.column(q.names["P"]).info()["n"])
+                row["policies"][pol] = dict(graph_ms=round(tg * 1e3, 3), eager_ms=round(te * 1e3, 3),
+                                            intermediates_bytes=fp, ue_gbs=round(ue / tg / 1e9, 1))
+                if pol == "learned":
+                    ue_sum += ue
+                    t_sum += tg
+                    if roof is None:
+                        roof, dom = plan_roofline(M, q.plan, alg)
+                q.plan.close()
+                del q
+            ex = row["policies"]["exhaustive"]["intermediates_bytes"]
+            row["regret_learned"] = round(row["policies"]["learned"]["intermediates_bytes"] / ex - 1, 5)
+            results.append(row)
+            log(json.dumps(row))
+        del cols
+    res = base_line(args, "uncompressed-equivalent GB/s of the star query (learned formats, captured graph)",
+                    round(ue_sum / t_sum / 1e9, 2), "GB/s", t_sum / len(results),
+                    f"star query: {n}-row fact table, 4 foreign keys over dimensions of "
+                    f"{'/'.join(str(d) for d in datagen.STAR_DIM_SIZES)} rows, 2 measures, semi-joins via "
+                    "dimension bitmaps, intersect of 4 position lists, group-sum into 250 groups; wide and narrow "
+                    "filters", {"rows": n, "selector_weights": wsrc})
+    res.update(roofline=roof, dominant_kernel=dom, runs=results, source_sha=source_sha())
+    if not args.no_cpu_baseline:
+        res["cpu_baseline"] = cpu_baseline_star(min(n, args.cpu_rows or 40_000_000))
+    return res
+
+
+def _sectors(pos) -> int:
+    return int(np.unique(np.asarray(pos, np.int64) >> 4).size)
+
+
+def cpu_baseline_star(rows: int):
+    """The oracle's star query (wide filters) on a bounded fact table, single thread;
+    bytes counted by the rules of plan_account."""
+    import oracle.queries as OQ
+    from paper_2004_09350_amd import datagen
+    cols = datagen.star_columns(1, rows)
+    thr = datagen.star_thresholds(datagen.STAR_WIDE)
+    t0 = time.perf_counter()
+    reps = 0
+    while reps == 0 or time.perf_counter() - t0 < 10.0:  # repeat to a measurable CPU time
+        r = OQ.q3(cols, thr, datagen.STAR_DIM_SIZES)
+        reps += 1
+    dt = (time.perf_counter() - t0) / reps
+    it = r["intermediates"]
+    D = datagen.STAR_DIM_SIZES
+    ue = 0
+    for d in range(4):
+        s, pd = it[f"S{d}"].size, it[f"P{d}"].size
+        ue += 4 * (D[d] + s) + 4 * s + 4 * (rows + pd)
+    ue += 4 * (it["P0"].size + it["P1"].size + it["P01"].size)
+    ue += 4 * (it["P01"].size + it["P2"].size + it["P012"].size)
+    ue += 4 * (it["P012"].size + it["P3"].size + it["P"].size)
+    P = it["P"]
+    ue += 3 * (8 * P.size + 64 * _sectors(P)) + 8 * it["kp"].size + 64 * _sectors(it["kp"])
+    ue += 2 * (4 * 2 * P.size + 8 * 250)
+    return dict(value=round(ue / dt / 1e9, 4), unit="GB/s", cores=1, kind="oracle",
+                sample=f"the star query (wide filters) on a {rows}-row fact table, single thread, "
+                       f"{reps} runs of {dt:.2f} s", seconds=round(dt * reps, 2))
+
+
+# ------------------------------------------------------------------------------ batch
+BATCH_OPS = ("select", "project", "intersect", "sum", "morph")
+
+
+def batch_spec(T: int, seed: int = 4242):
+    """T tasks: rows log-uniform in [1e4, 5e7]; operator, distribution, formats and
+    selectivity uniform over the sweep's sets."""
+    from paper_2004_09350_amd import datagen
+    u = (datagen.stream(seed, 0, 8 * T).astype(np.float64) / 2.0 ** 64).reshape(T, 8)
+    out = []
+    for t in range(T):
+        n_t = int(np.exp(np.log(1e4) + u[t, 0] * (np.log(5e7) - np.log(1e4))))
+        kin, kout = int(u[t, 3] * 6), int(u[t, 4] * 6)
+        op = BATCH_OPS[int(u[t, 1] * 5)]
+        if op == "morph" and kout == kin:
+            kout = (kin + 1) % 6
+        out.append(dict(n=n_t, op=op, dist=DISTS[int(u[t, 2] * 6)], kin=kin, kout=kout,
+                        si=int(u[t, 5] * 3), seed=50_000 + t))
+    return out
+
+
+def run_batch(args, M, gen, torch, log):
+    T = args.tasks
+    spec = batch_spec(T)
+    inputs, steps = [], []
+    t0 = time.time()
+    for t, sp in enumerate(spec):
+        n_t = sp["n"]
+        raw = gen.sweep_column(sp["dist"], sp["seed"], n_t)
+        if sp["op"] in ("select", "sum", "morph", "project"):
+            inputs.append(M.encode(raw, M.fmt(sp["kin"])))
+            j = len(inputs) - 1
+        if sp["op"] == "select":
+            probe = (lambda s, raw=raw: int(raw[min(n_t - 1, int(s * n_t))].item()) & 0xFFFFFFFF)
+            c = thresholds(sp["dist"], probe if sp["dist"] == "SORTED" else None)[sp["si"]]
+            steps.append(M.step(M.OP_SELECT, a=M.inp(j), cmp=M.LT, c0=c, out=M.fmt(sp["kout"])))
+        elif sp["op"] == "sum":
+            steps.append(M.step(M.OP_SUM, a=M.inp(j)))
+        elif sp["op"] == "morph":
+            steps.append(M.step(M.OP_MORPH, a=M.inp(j), out=M.fmt(sp["kout"])))
+        elif sp["op"] == "project":
+            u12 = M.encode(gen.uniform_bits(sp["seed"] + 100_000, n_t, 12), M.fmt(M.STATIC_BP))
+            inputs.append(M.select(u12, M.LT, 410, 0, M.fmt(M.DELTA_DYN_BP)))
+            steps.append(M.step(M.OP_PROJECT, a=M.inp(j), b=M.inp(j + 1), out=M.fmt(sp["kout"])))
+        else:  # intersect of a 10 % and a 50 % position list over n_t rows
+            a = M.encode(gen.uniform_bits(sp["seed"] + 200_000, n_t, 12), M.fmt(M.STATIC_BP))
+            b = M.encode(gen.uniform_bits(sp["seed"] + 300_000, n_t, 12), M.fmt(M.STATIC_BP))
+            inputs.append(M.select(a, M.LT, 410, 0, M.fmt(sp["kin"] if sp["kin"] != M.RLE else M.DELTA_DYN_BP)))
+            inputs.append(M.select(b, M.LT, 2048, 0, M.fmt(M.DELTA_DYN_BP)))
+            steps.append(M.step(M.OP_INTERSECT, a=M.inp(len(inputs) - 2), b=M.inp(len(inputs) - 1), param=n_t,
+                                out=M.fmt(sp["kout"])))
+        del raw
+    M.sync()
+    rows = sum(sp["n"] for sp in spec)
+    log(f"batch: {T} tasks, {rows} rows, inputs ready in {time.time() - t0:.1f}s")
+    plan = M.Plan(steps, inputs)
+    reps = max(1, args.steps)
+    te1 = time_eager(torch, plan, reps)
+    plan.set_tune(8, 8)
+    te8 = time_eager(torch, plan, reps)
+    log(f"eager one stream {te1 * 1e3:.2f} ms, eager 8 streams {te8 * 1e3:.2f} ms")
+    cache = os.path.join(ROOT, "gpurun_out", "plan_tune_cache.txt")
+    os.makedirs(os.path.dirname(cache), exist_ok=True)
+    best, best_ms = plan.autotune(reps=2, cache=cache)
+    tg = time_graph(torch, plan, reps)
+    log(f"autotuned {best} ({best_ms:.2f} ms in tuning), graph {tg * 1e3:.2f} ms")
+    ue, alg = plan_account(M, plan, inputs)
+    roof, dom = plan_roofline(M, plan, alg)
+    res = base_line(args, "uncompressed-equivalent GB/s of 512 mixed column-operator tasks in one captured graph",
+                    round(ue / tg / 1e9, 2), "GB/s", tg,
+                    f"batch: {T} tasks, rows log-uniform in [1e4, 5e7] ({rows} rows), operator "
+                    "(select/project/intersect/sum/morph), distribution and formats uniform over the sweep's sets",
+                    {"tasks": T, "rows_total": rows})
+    res.update(graph_ms=round(tg * 1e3, 3), eager_one_stream_ms=round(te1 * 1e3, 3),
+               eager_8_streams_ms=round(te8 * 1e3, 3), speedup_vs_one_launch_sequence_per_task=round(te1 / tg, 3),
+               tune={"branches": best[0], "wg_per_cu": best[1]}, arena_gb=round(plan.arena_bytes() / 1e9, 2),
+               roofline=roof, dominant_kernel=dom, source_sha=source_sha())
+    if not args.no_cpu_baseline:
+        res["cpu_baseline"] = cpu_baseline_batch(spec, cap=args.cpu_rows or 1_000_000, max_tasks=len(spec))
+    plan.close()
+    return res
+
+
+def cpu_baseline_batch(spec, cap: int, max_tasks: int):
+    """The oracle on the first tasks of the batch, each cut to at most `cap` rows."""
+    import oracle as O
+    from paper_2004_09350_amd import datagen
+    ue, dt = 0, 0.0
+    for sp in spec[:max_tasks]:
+        n_t = min(sp["n"], cap)
+        v = datagen.sweep_column(sp["dist"], sp["seed"], n_t)
+        enc = O.encode(v, sp["kin"])
+        t0 = time.perf_counter()
+        if sp["op"] == "select":
+            c = thresholds(sp["dist"], (lambda s: int(v[min(n_t - 1, int(s * n_t))])))[sp["si"]]
+            p = O.select(O.decode(enc), O.LT, c)
+            O.encode(p, sp["kout"])
+            ue += 4 * (n_t + p.size)
+        elif sp["op"] == "sum":
+            O.sum_(O.decode(enc))
+            ue += 4 * n_t + 8
+        elif sp["op"] == "morph":
+            O.encode(O.decode(enc), sp["kout"])
+            ue += 8 * n_t
+        elif sp["op"] == "project":
+            pos = O.select(datagen.uniform_bits(sp["seed"] + 100_000, n_t, 12), O.LT, 410)
+            O.encode(O.project(O.decode(enc), pos), sp["kout"])
+            ue += 8 * pos.size + 64 * _sectors(pos)
+        else:
+            pa = O.select(datagen.uniform_bits(sp["seed"] + 200_000, n_t, 12), O.LT, 410)
+            pb = O.select(datagen.uniform_bits(sp["seed"] + 300_000, n_t, 12), O.LT, 2048)
+            r = O.intersect(pa, pb)
+            O.encode(r, sp["kout"])
+            ue += 4 * (pa.size + pb.size + r.size)
+        dt += time.perf_counter() - t0
+    return dict(value=round(ue / dt / 1e9, 4), unit="GB/s", cores=1, kind="oracle",
+                sample=f"the first {max_tasks} batch tasks cut to at most {cap} rows each, single thread, "
+                       f"{dt:.1f} s", seconds=round(dt, 2))
+
+
+# ------------------------------------------------------------------------------ Q1
+def run_q1(args, M, gen, torch, log):
+    from paper_2004_09350_amd import queries
+    n = args.rows or 1_000_000
+    A = M.encode(gen.uniform_bits(1, n, 10), M.fmt(M.STATIC_BP, 10))
+    B = M.encode(gen.uniform_bits(2, n, 20), M.fmt(M.STATIC_BP, 20))
+    plan = queries.q1_plan(A, B, 103)
+    reps = max(10, args.steps)
+    tg = time_graph(torch, plan, reps)
+    te = time_eager(torch, plan, reps)
+    ue, alg = plan_account(M, plan, [A, B])
+    roof, dom = plan_roofline(M, plan, alg)
+    res = base_line(args, "uncompressed-equivalent GB/s of Q1 (select -> project -> sum, captured graph)",
+                    round(ue / tg / 1e9, 2), "GB/s", tg,
+                    f"Q1: {n} rows, A uniform 10-bit static BP, B uniform 20-bit static BP, positions of A < 103 "
+                    "as delta+DynBP, project B (static BP auto), sum", {"rows": n})
+    res.update(graph_ms=round(tg * 1e3, 4), eager_ms=round(te * 1e3, 4), sum=int(plan.read(2)[0]),
+               roofline=roof, dominant_kernel=dom, source_sha=source_sha())
+    if not args.no_cpu_baseline:
+        import oracle.queries as OQ
+        from paper_2004_09350_amd import datagen
+        a, b = datagen.uniform_bits(1, n, 10), datagen.uniform_bits(2, n, 20)
+        t0 = time.perf_counter()
+        reps_c = 0
+        while time.perf_counter() - t0 < 10.0:
+            r = OQ.q1(a, b, 103)
+            reps_c += 1
+        dt = (time.perf_counter() - t0) / reps_c
+        ue_c = 4 * (n + r["P"].size) + 8 * r["P"].size + 64 * _sectors(r["P"]) + 4 * r["Bp"].size + 8
+        res["cpu_baseline"] = dict(value=round(ue_c / dt / 1e9, 4), unit="GB/s", cores=1, kind="oracle",
+                                   sample=f"Q1 on the same {n} rows, {reps_c} runs, single thread",
+                                   seconds=round(dt, 3))
+    plan.close()
+    return res
+
+
+def main():
+    args = parse()
+    if args.gpus != 1:
+        print(json.dumps({"error": "this build runs on one GPU; --gpus must be 1 (multi-GPU sharding is "
+                                   "described in DESIGN.md but not built)"}))
+        sys.exit(2)
+    import torch
+
+    from paper_2004_09350_amd import gen_gpu as gen
+    from paper_2004_09350_amd import morphgpu as M
+
+    log = lambda *a: print(*a, file=sys.stderr, flush=True)
+    M.init()
+    if args.workload == "sweep":
+        res = run_sweep(args, M, gen, torch, log)
+    elif args.workload == "star":
+        res = run_star(args, M, gen, torch, log)
+    elif args.workload == "batch":
+        res = run_batch(args, M, gen, torch, log)
+    else:
+        res = run_q1(args, M, gen, torch, log)
     print(json.dumps(res))
 
 

@@ -619,12 +619,136 @@ __device__ __forceinline__ void consume_chunk(const InCol &in, unsigned long lon
   }
 }
 
+// v[k] for a lane-varying k in 0..7, as a chain of selects (an indexed read of the
+// register array would go through scratch memory).
+__device__ __forceinline__ unsigned select8(const unsigned (&v)[8], unsigned k) {
+  unsigned x = v[0];
+#pragma unroll
+  for (int i = 1; i < 8; i++) {
+    x = k == (unsigned)i ? v[i] : x;
+    asm volatile("" : "+v"(x));
+  }
+  return x;
+}
+
+// RLE input walked run by run.  Wave w takes a contiguous quarter of the chunks
+// [cb, ce).  The runs [r, whi) it needs are staged in a ring of kRunCap (start, value)
+// pairs in its LDS (run q in slot q mod kRunCap); each lane finds its 8 values there.
+// While a chunk's body runs, the runs the next chunks will need are already being
+// loaded (coalesced) into registers, so sparse and dense runs both stream without a
+// load round trip per chunk.  lds: 2 * kRunCap words.
+constexpr unsigned kRunCap = 1024;
+constexpr unsigned kRunMask = kRunCap - 1;
+constexpr unsigned kRunPre = 9;  // prefetch rounds of 64 runs (576 runs at most)
+static_assert(2 * kRunCap <= kRing * kBlk, "run staging fits the wave's ring buffer");
+static_assert((kRunCap & kRunMask) == 0, "ring size is a power of two");
+
+template <class Body>
+__device__ __forceinline__ void rle_stream(const InCol &in, unsigned long long cb, unsigned long long ce, unsigned w,
+                                           unsigned lane, unsigned *lds, Body &&body) {
+  const unsigned long long nseg = ce - cb;
+  const unsigned long long c_begin = cb + nseg * w / kWaves, c_end = cb + nseg * (w + 1) / kWaves;
+  if (c_begin >= c_end) return;
+  unsigned *S = lds, *V = lds + kRunCap;
+  unsigned long long r = (in.runs > 0) ? rle_find_wave(in, c_begin * kBlk, lane, 0) : 0ull;
+  unsigned long long whi = r;  // runs [r, whi) are staged
+  unsigned est = 64;           // runs per chunk, as the last chunk had
+  unsigned pst[kRunPre], pval[kRunPre];
+  unsigned npre = 0;           // rounds of 64 in flight in pst/pval, for runs [whi, whi + 64 * npre)
+
+  auto issue = [&](unsigned rounds) {
+#pragma unroll
+    for (unsigned k = 0; k < kRunPre; k++) {
+      if (k < rounds) {
+        const unsigned long long q = whi + 64ull * k + lane;
+        pst[k] = (q < in.runs) ? in.rstarts[q] : 0xFFFFFFFFu;
+        pval[k] = (q < in.runs) ? in.rvalues[q] : 0u;
+      }
+    }
+    npre = rounds;
+  };
+  auto land = [&]() {
+#pragma unroll
+    for (unsigned k = 0; k < kRunPre; k++) {
+      if (k < npre) {
+        const unsigned slot = (unsigned)((whi + 64ull * k + lane) & kRunMask);
+        S[slot] = pst[k];
+        V[slot] = pval[k];
+      }
+    }
+    whi += 64ull * npre;
+    npre = 0;
+    wave_sync();
+  };
+
+  for (unsigned long long c = c_begin; c < c_end; c++) {
+    const unsigned long long c0 = c * kBlk;
+    const unsigned long long c1 = min(c0 + kBlk, in.n);
+    // make sure the staged runs reach past c1 (or the last run)
+    while (true) {
+      const bool covered = whi >= in.runs || (whi > r && (unsigned long long)S[(whi - 1) & kRunMask] >= c1);
+      if (covered || whi - r + 64 > kRunCap) break;
+      const unsigned room = (unsigned)(kRunCap - (whi - r)) / 64;
+      issue(min(min(room, kRunPre), max(1u, (est + 63) / 64 + 1)));
+      land();
+    }
+    const unsigned long long nst = whi - r;  // staged runs from r
+    const unsigned long long idx0 = c0 + 8ull * lane;
+    unsigned v[8];
+    unsigned j = 0;  // staged index relative to r
+    if (idx0 < c1) {
+      const unsigned x0 = (unsigned)idx0;
+      unsigned lo = 0, hi = (unsigned)nst;  // last staged run starting at or before idx0
+      while (hi - lo > 1) {
+        const unsigned mid = (lo + hi) >> 1;
+        if (S[(r + mid) & kRunMask] <= x0)
+          lo = mid;
+        else
+          hi = mid;
+      }
+      j = lo;
+      v[0] = V[(r + j) & kRunMask];
+#pragma unroll
+      for (int i = 1; i < 8; i++) {
+        const unsigned nxt = (j + 1 < nst) ? S[(r + j + 1) & kRunMask] : 0xFFFFFFFFu;
+        if (nxt <= x0 + (unsigned)i) j++;  // runs start at distinct indices: at most one per step
+        v[i] = V[(r + j) & kRunMask];
+      }
+    } else {
+#pragma unroll
+      for (int i = 0; i < 8; i++) v[i] = 0u;
+    }
+    // the run holding c1, the first value of the next chunk
+    const unsigned jl = __shfl(j, 63);
+    const unsigned nxt = (jl + 1 < nst) ? S[(r + jl + 1) & kRunMask] : 0xFFFFFFFFu;
+    wave_sync();
+    est = jl + 1;
+    r += jl + (((unsigned long long)nxt == c1) ? 1u : 0u);
+    // keep about two chunks of runs ahead: start their loads now, land them after the body
+    if (c + 1 < c_end && whi < in.runs) {
+      const unsigned long long ahead = whi - r;
+      const unsigned long long want = min(2ull * est + 64ull, (unsigned long long)(kRunCap - 64));
+      if (ahead < want) {
+        const unsigned room = (unsigned)((kRunCap - ahead) / 64);
+        const unsigned rounds = min(min(room, kRunPre), (unsigned)((want - ahead + 63) / 64));
+        if (rounds > 0) issue(rounds);
+      }
+    }
+    body(c, v);
+    if (npre) land();
+  }
+}
+
 // Walk the wave's chunks cb + w + kWaves*j < ce with kRing chunks in flight.
 // ring: the wave's kRing * 512 LDS words; dummy: any valid 16-byte global address.
 template <class Body>
 __device__ __forceinline__ void stream_chunks(const InCol &in, unsigned long long cb, unsigned long long ce,
                                               unsigned w, unsigned lane, unsigned *ring, const void *dummy,
                                               Body &&body) {
+  if (in.kind == RLE) {
+    rle_stream(in, cb, ce, w, lane, ring, body);
+    return;
+  }
   const unsigned long long first = cb + w;
   if (first >= ce) return;
   const unsigned long long nj = (ce - first + kWaves - 1) / kWaves;

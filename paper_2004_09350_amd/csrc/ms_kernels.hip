@@ -242,7 +242,7 @@ __device__ __forceinline__ bool narrow_plan(const FinishArgs &a, unsigned long l
 }
 
 __global__ __launch_bounds__(kWG) void k_narrow(FinishArgs a, unsigned *tmp) {
-  __shared__ unsigned lds_all[kWaves * kBlk];
+  __shared__ __attribute__((aligned(16))) unsigned lds_all[kWaves * kBlk];
   __shared__ unsigned red[kWaves];
   unsigned long long n_main;
   unsigned Wf, Wt;
@@ -275,7 +275,7 @@ __global__ __launch_bounds__(kWG) void k_narrow_copy(FinishArgs a, const unsigne
 // ---------------------------------------------------------------------------------------------
 // Column statistics needed by later operators: OR of all values (width bound).
 __global__ __launch_bounds__(kWG) void k_colstats(ColView inv, unsigned *partials) {
-  __shared__ unsigned ring[kWaves * kRing * kBlk];
+  __shared__ __attribute__((aligned(16))) unsigned ring[kWaves * kRing * kBlk];
   __shared__ unsigned red[kWaves];
   const InCol in = load_in(inv);
   const unsigned lane = lane_id(), w = threadIdx.x >> 6, G = gridDim.x;
@@ -304,8 +304,8 @@ __global__ __launch_bounds__(kWG) void k_colstats(ColView inv, unsigned *partial
 // Morph (and encode): out = encode_fmt(decode(in)), count known.
 template <unsigned OK>
 __global__ __launch_bounds__(kWG) void k_morph(ColView inv, ColView outv, unsigned auto_w, unsigned *partials) {
-  __shared__ unsigned ring[kWaves * kRing * kBlk];
-  __shared__ unsigned lds_all[kWaves * kBlk];
+  __shared__ __attribute__((aligned(16))) unsigned ring[kWaves * kRing * kBlk];
+  __shared__ __attribute__((aligned(16))) unsigned lds_all[kWaves * kBlk];
   __shared__ unsigned red[kWaves];
   const InCol in = load_in(inv);
   const unsigned lane = lane_id(), w = threadIdx.x >> 6, G = gridDim.x;
@@ -331,7 +331,7 @@ __global__ __launch_bounds__(kWG) void k_morph(ColView inv, ColView outv, unsign
 
 // Decode into a plain device array.
 __global__ __launch_bounds__(kWG) void k_decode(ColView inv, unsigned *__restrict__ out) {
-  __shared__ unsigned ring[kWaves * kRing * kBlk];
+  __shared__ __attribute__((aligned(16))) unsigned ring[kWaves * kRing * kBlk];
   const InCol in = load_in(inv);
   const unsigned lane = lane_id(), w = threadIdx.x >> 6, G = gridDim.x;
   const unsigned long long C = (in.n + kBlk - 1) / kBlk;
@@ -356,9 +356,9 @@ __global__ __launch_bounds__(kWG) void k_decode(ColView inv, unsigned *__restric
 template <unsigned OK>
 __global__ __launch_bounds__(kWG) void k_project(ColView posv, ColView datav, ColView outv, unsigned auto_w,
                                                  unsigned *partials) {
-  __shared__ unsigned ring[kWaves * kRing * kBlk];
-  __shared__ unsigned gblk[kWaves * kBlk];
-  __shared__ unsigned lds_all[kWaves * kBlk];
+  __shared__ __attribute__((aligned(16))) unsigned ring[kWaves * kRing * kBlk];
+  __shared__ __attribute__((aligned(16))) unsigned gblk[kWaves * kBlk];
+  __shared__ __attribute__((aligned(16))) unsigned lds_all[kWaves * kBlk];
   __shared__ unsigned red[kWaves];
   const InCol ip = load_in(posv);
   const InCol id = load_in(datav);
@@ -410,8 +410,8 @@ __device__ __forceinline__ unsigned src_value(const ChunkSrc &s, const InCol &ia
 template <bool EMIT>
 __device__ __forceinline__ void rle_walk(const ChunkSrc &s, const ColView &outv, const unsigned *seg_count,
                                          unsigned *seg_out, unsigned *partials) {
-  __shared__ unsigned lds_all[kWaves * kBlk];
-  __shared__ unsigned gblk[kWaves * kBlk];
+  __shared__ __attribute__((aligned(16))) unsigned lds_all[kWaves * kBlk];
+  __shared__ __attribute__((aligned(16))) unsigned gblk[kWaves * kBlk];
   __shared__ unsigned gstage[kWaves * kBlk];
   __shared__ unsigned long long red[kWaves];
   __shared__ unsigned s_chunk_runs[kWaves];
@@ -538,7 +538,7 @@ __global__ __launch_bounds__(kWG) void k_rle_emit(ChunkSrc s, ColView outv, cons
 // mode 2: bitmap predicate on values, emits values, checks strict increase (intersect)
 template <unsigned MODE>
 __global__ __launch_bounds__(kWG) void k_pred(PredArgs a) {
-  __shared__ unsigned ring[kWaves * kRing * kBlk];
+  __shared__ __attribute__((aligned(16))) unsigned ring[kWaves * kRing * kBlk];
   __shared__ unsigned long long red[kWaves];
   __shared__ unsigned redo[kWaves];
   const InCol in = load_in(a.in);
@@ -586,13 +586,7 @@ __global__ __launch_bounds__(kWG) void k_pred(PredArgs a) {
       }
       const unsigned long long last_idx = min(in.n, (c + 1) * kBlk) - 1;
       if (lane == 0) chunk_first[c] = v[0];
-      if (idx0 <= last_idx && last_idx < idx0 + 8) {
-        unsigned lv = v[0];
-#pragma unroll
-        for (int i = 1; i < 8; i++)
-          if (idx0 + i == last_idx) lv = v[i];
-        chunk_last[c] = lv;
-      }
+      if (idx0 <= last_idx && last_idx < idx0 + 8) chunk_last[c] = select8(v, (unsigned)(last_idx - idx0));
     } else if (mask) {
       orv |= (unsigned)idx0 | (31u - __clz(mask));  // positions: bit width of the largest
     }
@@ -647,8 +641,8 @@ __device__ __forceinline__ unsigned emit_width(const EmitArgs &a, unsigned orv) 
 }
 
 __global__ __launch_bounds__(kWG) void k_emit(EmitArgs a) {
-  __shared__ unsigned stage[kStage];
-  __shared__ unsigned lds_all[kWaves * kBlk];
+  __shared__ __attribute__((aligned(16))) unsigned stage[kStage];
+  __shared__ __attribute__((aligned(16))) unsigned lds_all[kWaves * kBlk];
   __shared__ unsigned s_ctot[kEmitChunks];
   __shared__ unsigned long long red[kWaves];
   __shared__ unsigned redo[kWaves];
@@ -692,6 +686,7 @@ __global__ __launch_bounds__(kWG) void k_emit(EmitArgs a) {
   }
 
   unsigned or_main = 0;
+  const bool cap_ok = N <= a.out.n_cap;
   unsigned long long emitted = 0;   // outputs of this segment so far
   unsigned long long Lbase = A;     // global index of stage[0]
   unsigned *lds = lds_all + w * kBlk;
@@ -737,6 +732,45 @@ __global__ __launch_bounds__(kWG) void k_emit(EmitArgs a) {
       unsigned m = msk[j];
       unsigned long long g = O + emitted + cbase[j] + off[j];
       const unsigned long long idx0 = c * kBlk + 8ull * lane;
+      // Fast path: all of this lane's outputs land in one region (the owned, staged blocks;
+      // or the values/runs of an uncompressed or RLE output) below n_main.
+      const unsigned long long gend = g + __popc(m);
+      const bool fast = cap_ok && gend <= n_main_o &&
+                        (blocky ? (g >= A && gend <= B && gend - Lbase <= (unsigned long long)kStage) : true);
+      if (fast) {
+        unsigned vals[8];
+#pragma unroll
+        for (int i = 0; i < 8; i++) vals[i] = a.emit_values ? v[j][i] : (unsigned)(idx0 + i);
+        unsigned r = 0, orl = 0;
+        if (blocky) {
+          unsigned *st = stage + (unsigned)(g - Lbase);
+#pragma unroll
+          for (int i = 0; i < 8; i++)
+            if ((m >> i) & 1u) {
+              st[r++] = vals[i];
+              orl |= vals[i];
+            }
+        } else if (kind == UNCOMPR) {
+          unsigned *dst = a.out.payload + g;
+#pragma unroll
+          for (int i = 0; i < 8; i++)
+            if ((m >> i) & 1u) {
+              dst[r++] = vals[i];
+              orl |= vals[i];
+            }
+        } else {
+#pragma unroll
+          for (int i = 0; i < 8; i++)
+            if ((m >> i) & 1u) {
+              a.out.rvalues[g + r] = vals[i];
+              a.out.rstarts[g + r] = (unsigned)(g + r);
+              orl |= vals[i];
+              r++;
+            }
+        }
+        or_main |= orl;
+        m = 0;
+      }
       while (m) {
         const unsigned i = __ffs(m) - 1;
         m &= m - 1;
@@ -779,10 +813,15 @@ __global__ __launch_bounds__(kWG) void k_emit(EmitArgs a) {
         const unsigned long long nenc = nfull + (final_partial ? 1 : 0);
         for (unsigned long long j = w; j < nenc; j += kWaves) {
           unsigned x[8];
+          const unsigned long long l0 = j * kBlk + 8ull * lane;
+          if (l0 + 8 <= have) {  // two 16-byte reads: no bank conflicts between lanes
+            const uint4 *s4 = reinterpret_cast<const uint4 *>(stage + l0);
+            const uint4 p = s4[0], q = s4[1];
+            x[0] = p.x; x[1] = p.y; x[2] = p.z; x[3] = p.w;
+            x[4] = q.x; x[5] = q.y; x[6] = q.z; x[7] = q.w;
+          } else {
 #pragma unroll
-          for (int i = 0; i < 8; i++) {
-            const unsigned long long li = j * kBlk + 8ull * lane + i;
-            x[i] = (li < have) ? stage[li] : 0u;
+            for (int i = 0; i < 8; i++) x[i] = (l0 + i < have) ? stage[l0 + i] : 0u;
           }
           encode_out_block(o, (Lbase / kBlk) + j, x, lane, lds, or_main);
         }
@@ -807,7 +846,7 @@ __global__ __launch_bounds__(kWG) void k_emit(EmitArgs a) {
 // Compaction phase 3 (block formats): a block that started in an earlier segment is
 // packed from the staging array by the segment that holds its last element.
 __global__ __launch_bounds__(kWG) void k_emit_fix(EmitArgs a) {
-  __shared__ unsigned lds_all[kWaves * kBlk];
+  __shared__ __attribute__((aligned(16))) unsigned lds_all[kWaves * kBlk];
   __shared__ unsigned long long red[kWaves];
   __shared__ unsigned redo[kWaves];
   const unsigned lane = lane_id(), w = threadIdx.x >> 6, G = gridDim.x, seg = blockIdx.x;
@@ -841,7 +880,7 @@ __global__ __launch_bounds__(kWG) void k_emit_fix(EmitArgs a) {
 // ---------------------------------------------------------------------------------------------
 // Sum and group-sum.
 __global__ __launch_bounds__(kWG) void k_sum(ColView inv, unsigned long long *partials) {
-  __shared__ unsigned ring[kWaves * kRing * kBlk];
+  __shared__ __attribute__((aligned(16))) unsigned ring[kWaves * kRing * kBlk];
   __shared__ unsigned long long red[kWaves];
   const InCol in = load_in(inv);
   const unsigned lane = lane_id(), w = threadIdx.x >> 6, G = gridDim.x;
@@ -885,7 +924,7 @@ constexpr unsigned kMaxLdsGroups = 4096;
 __global__ __launch_bounds__(kWG) void k_group_sum(ColView gv, ColView vv, unsigned G_groups,
                                                    unsigned long long *partials) {
   __shared__ unsigned long long hist[kMaxLdsGroups];
-  __shared__ unsigned lds_all[2 * kWaves * kBlk];
+  __shared__ __attribute__((aligned(16))) unsigned lds_all[2 * kWaves * kBlk];
   const InCol ig = load_in(gv);
   const InCol iv = load_in(vv);
   const unsigned lane = lane_id(), w = threadIdx.x >> 6, G = gridDim.x;
@@ -981,7 +1020,7 @@ __global__ void k_fill_u64(unsigned long long *p, unsigned long long n, unsigned
 // (inside chunks here, across chunk ends in k_check_order).
 __global__ __launch_bounds__(kWG) void k_bitmap(ColView posv, unsigned long long domain, unsigned *bitmap,
                                                 unsigned *chunk_first, unsigned *chunk_last) {
-  __shared__ unsigned ring[kWaves * kRing * kBlk];
+  __shared__ __attribute__((aligned(16))) unsigned ring[kWaves * kRing * kBlk];
   const InCol in = load_in(posv);
   const unsigned lane = lane_id(), w = threadIdx.x >> 6, G = gridDim.x;
   const unsigned long long C = (in.n + kBlk - 1) / kBlk;
@@ -1000,13 +1039,7 @@ __global__ __launch_bounds__(kWG) void k_bitmap(ColView posv, unsigned long long
       }
       const unsigned long long last_idx = min(in.n, (c + 1) * kBlk) - 1;
       if (lane == 0) chunk_first[c] = v[0];
-      if (idx0 <= last_idx && last_idx < idx0 + 8) {
-        unsigned lv = v[0];
-#pragma unroll
-        for (int i = 1; i < 8; i++)
-          if (idx0 + i == last_idx) lv = v[i];
-        chunk_last[c] = lv;
-      }
+      if (idx0 <= last_idx && last_idx < idx0 + 8) chunk_last[c] = select8(v, (unsigned)(last_idx - idx0));
     }
     // combine bits that land in the same word before the atomic
     unsigned cur_word = 0xFFFFFFFFu, bits = 0;
