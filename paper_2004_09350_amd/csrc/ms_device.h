@@ -24,6 +24,15 @@ __device__ unsigned int g_ring[kRingSlots];  // self-resetting "last workgroup" 
 __device__ __forceinline__ void raise_err(unsigned code) { atomicCAS(&g_err, 0u, code); }
 
 __device__ __forceinline__ unsigned lane_id() { return __lane_id(); }
+// Values the whole wave shares, moved to scalar registers: branches on them become
+// scalar branches and their loads scalar work.
+__device__ __forceinline__ unsigned uni(unsigned x) { return __builtin_amdgcn_readfirstlane(x); }
+__device__ __forceinline__ unsigned long long uni(unsigned long long x) {
+  const unsigned lo = __builtin_amdgcn_readfirstlane((unsigned)x);
+  const unsigned hi = __builtin_amdgcn_readfirstlane((unsigned)(x >> 32));
+  return ((unsigned long long)hi << 32) | lo;
+}
+__device__ __forceinline__ unsigned wave_id() { return __builtin_amdgcn_readfirstlane(threadIdx.x >> 6); }
 __device__ __forceinline__ unsigned bw(unsigned x) { return x ? 32u - __clz(x) : 0u; }
 __device__ __forceinline__ unsigned lowmask(unsigned w) { return w >= 32 ? 0xFFFFFFFFu : ((1u << w) - 1u); }
 
@@ -224,9 +233,9 @@ struct InCol {
 __device__ __forceinline__ InCol load_in(const ColView &c) {
   InCol in;
   in.kind = c.kind;
-  in.n = c.hdr->n;
-  in.W = c.hdr->sbp_width;
-  in.runs = min(c.hdr->runs, c.n_cap);
+  in.n = uni(c.hdr->n);
+  in.W = uni(c.hdr->sbp_width);
+  in.runs = uni(min(c.hdr->runs, c.n_cap));
   in.payload_cap = c.payload_cap;
   in.widths = c.widths;
   in.offsets = c.offsets;
@@ -331,8 +340,8 @@ __device__ __forceinline__ void decode_chunk(const InCol &in, unsigned long long
     case DELTA_DYN_BP:
     case FOR_DYN_BP: {
       if (c < in.nb) {
-        unsigned W = in.widths[c];
-        unsigned long long off = in.offsets[c];
+        unsigned W = uni((unsigned)in.widths[c]);
+        unsigned long long off = uni((unsigned long long)in.offsets[c]);
         if (W > 32 || off + 16ull * W > in.payload_cap) {  // a corrupt directory never reads out of bounds
           raise_err(E_INVALID);
           W = 0;
@@ -340,13 +349,13 @@ __device__ __forceinline__ void decode_chunk(const InCol &in, unsigned long long
         }
         unpack8_rt(W, in.payload + off, lane, v);
         if (in.kind == FOR_DYN_BP) {
-          const unsigned ref = in.bases[c];
+          const unsigned ref = uni(in.bases[c]);
 #pragma unroll
           for (int i = 0; i < 8; i++) v[i] += ref;
         } else if (in.kind == DELTA_DYN_BP) {
 #pragma unroll
           for (int i = 1; i < 8; i++) v[i] += v[i - 1];
-          const unsigned excl = wave_excl_scan(v[7], lane) + in.bases[c];
+          const unsigned excl = wave_excl_scan(v[7], lane) + uni(in.bases[c]);
 #pragma unroll
           for (int i = 0; i < 8; i++) v[i] += excl;
         }
@@ -460,7 +469,7 @@ __device__ __forceinline__ Raw issue_chunk(const InCol &in, unsigned long long c
           off = 0;
         }
         r.W = W;
-        r.base = (in.kind == DYN_BP) ? 0u : in.bases[c];
+        r.base = (in.kind == DYN_BP) ? 0u : uni(in.bases[c]);
         blk = in.payload + off;
         r.mode = 0;
       }
@@ -554,8 +563,8 @@ __device__ __forceinline__ unsigned chunk_mode(const InCol &in, unsigned long lo
     case DELTA_DYN_BP:
     case FOR_DYN_BP:
       if (c < in.nb) {
-        W = in.widths[c];
-        off = in.offsets[c];
+        W = uni((unsigned)in.widths[c]);
+        off = uni((unsigned long long)in.offsets[c]);
         if (W > 32 || off + 16ull * W > in.payload_cap) {  // a corrupt directory never reads out of bounds
           W = 0;
           off = 0;
@@ -607,13 +616,13 @@ __device__ __forceinline__ void consume_chunk(const InCol &in, unsigned long lon
   }
   unpack8_rt(W, buf, lane, v);
   if (in.kind == FOR_DYN_BP) {
-    const unsigned ref = in.bases[c];
+    const unsigned ref = uni(in.bases[c]);
 #pragma unroll
     for (int i = 0; i < 8; i++) v[i] += ref;
   } else if (in.kind == DELTA_DYN_BP) {
 #pragma unroll
     for (int i = 1; i < 8; i++) v[i] += v[i - 1];
-    const unsigned excl = wave_excl_scan(v[7], lane) + in.bases[c];
+    const unsigned excl = wave_excl_scan(v[7], lane) + uni(in.bases[c]);
 #pragma unroll
     for (int i = 0; i < 8; i++) v[i] += excl;
   }

@@ -34,7 +34,7 @@ __device__ __forceinline__ void segment(unsigned long long C, unsigned s, unsign
 // Workgroup reductions (256 threads).
 __device__ __forceinline__ unsigned long long wg_add64(unsigned long long x, unsigned long long *sh) {
   x = wave_add64(x);
-  const unsigned w = threadIdx.x >> 6;
+  const unsigned w = wave_id();
   __syncthreads();
   if (lane_id() == 0) sh[w] = x;
   __syncthreads();
@@ -45,7 +45,7 @@ __device__ __forceinline__ unsigned long long wg_add64(unsigned long long x, uns
 }
 __device__ __forceinline__ unsigned wg_or(unsigned x, unsigned *sh) {
   x = wave_or(x);
-  const unsigned w = threadIdx.x >> 6;
+  const unsigned w = wave_id();
   __syncthreads();
   if (lane_id() == 0) sh[w] = x;
   __syncthreads();
@@ -247,7 +247,7 @@ __global__ __launch_bounds__(kWG) void k_narrow(FinishArgs a, unsigned *tmp) {
   unsigned long long n_main;
   unsigned Wf, Wt;
   if (!narrow_plan(a, n_main, Wf, Wt, red)) return;
-  const unsigned lane = lane_id(), w = threadIdx.x >> 6;
+  const unsigned lane = lane_id(), w = wave_id();
   unsigned *lds = lds_all + w * kBlk;
   const unsigned long long C = (n_main + kBlk - 1) / kBlk;
   for (unsigned long long c = (unsigned long long)blockIdx.x * kWaves + w; c < C;
@@ -278,7 +278,7 @@ __global__ __launch_bounds__(kWG) void k_colstats(ColView inv, unsigned *partial
   __shared__ __attribute__((aligned(16))) unsigned ring[kWaves * kRing * kBlk];
   __shared__ unsigned red[kWaves];
   const InCol in = load_in(inv);
-  const unsigned lane = lane_id(), w = threadIdx.x >> 6, G = gridDim.x;
+  const unsigned lane = lane_id(), w = wave_id(), G = gridDim.x;
   const unsigned long long C = (in.n + kBlk - 1) / kBlk;
   unsigned long long cb, ce;
   segment(C, blockIdx.x, G, cb, ce);
@@ -308,7 +308,7 @@ __global__ __launch_bounds__(kWG) void k_morph(ColView inv, ColView outv, unsign
   __shared__ __attribute__((aligned(16))) unsigned lds_all[kWaves * kBlk];
   __shared__ unsigned red[kWaves];
   const InCol in = load_in(inv);
-  const unsigned lane = lane_id(), w = threadIdx.x >> 6, G = gridDim.x;
+  const unsigned lane = lane_id(), w = wave_id(), G = gridDim.x;
   unsigned Wp = outv.width;
   if (outv.kind == STATIC_BP && auto_w) Wp = bw(inv.hdr->or_all);
   const OutCol o = make_out(outv, in.n, Wp);
@@ -333,7 +333,7 @@ __global__ __launch_bounds__(kWG) void k_morph(ColView inv, ColView outv, unsign
 __global__ __launch_bounds__(kWG) void k_decode(ColView inv, unsigned *__restrict__ out) {
   __shared__ __attribute__((aligned(16))) unsigned ring[kWaves * kRing * kBlk];
   const InCol in = load_in(inv);
-  const unsigned lane = lane_id(), w = threadIdx.x >> 6, G = gridDim.x;
+  const unsigned lane = lane_id(), w = wave_id(), G = gridDim.x;
   const unsigned long long C = (in.n + kBlk - 1) / kBlk;
   unsigned long long cb, ce;
   segment(C, blockIdx.x, G, cb, ce);
@@ -362,7 +362,7 @@ __global__ __launch_bounds__(kWG) void k_project(ColView posv, ColView datav, Co
   __shared__ unsigned red[kWaves];
   const InCol ip = load_in(posv);
   const InCol id = load_in(datav);
-  const unsigned lane = lane_id(), w = threadIdx.x >> 6, G = gridDim.x;
+  const unsigned lane = lane_id(), w = threadIdx.x >> 6, G = gridDim.x;  // w kept in a VGPR: SGPRs run short here
   unsigned Wp = outv.width;
   if (outv.kind == STATIC_BP && auto_w) Wp = bw(datav.hdr->or_all);
   const OutCol o = make_out(outv, ip.n, Wp);
@@ -421,7 +421,7 @@ __device__ __forceinline__ void rle_walk(const ChunkSrc &s, const ColView &outv,
   const InCol ia = load_in(s.a);
   InCol ib = ia;
   if (s.mode == 1) ib = load_in(s.b);
-  const unsigned lane = lane_id(), w = threadIdx.x >> 6, G = gridDim.x;
+  const unsigned lane = lane_id(), w = wave_id(), G = gridDim.x;
   const unsigned long long n = ia.n;
   const unsigned long long C = (n + kBlk - 1) / kBlk;
   unsigned long long cb, ce;
@@ -542,7 +542,7 @@ __global__ __launch_bounds__(kWG) void k_pred(PredArgs a) {
   __shared__ unsigned long long red[kWaves];
   __shared__ unsigned redo[kWaves];
   const InCol in = load_in(a.in);
-  const unsigned lane = lane_id(), w = threadIdx.x >> 6, G = gridDim.x;
+  const unsigned lane = lane_id(), w = wave_id(), G = gridDim.x;
   const unsigned long long C = (in.n + kBlk - 1) / kBlk;
   unsigned long long cb, ce;
   segment(C, blockIdx.x, G, cb, ce);
@@ -647,7 +647,7 @@ __global__ __launch_bounds__(kWG) void k_emit(EmitArgs a) {
   __shared__ unsigned long long red[kWaves];
   __shared__ unsigned redo[kWaves];
   const InCol in = load_in(a.in);
-  const unsigned lane = lane_id(), w = threadIdx.x >> 6, G = gridDim.x, seg = blockIdx.x;
+  const unsigned lane = lane_id(), w = wave_id(), G = gridDim.x, seg = blockIdx.x;
   const unsigned long long C = (in.n + kBlk - 1) / kBlk;
   unsigned long long cb, ce;
   segment(C, seg, G, cb, ce);
@@ -849,7 +849,7 @@ __global__ __launch_bounds__(kWG) void k_emit_fix(EmitArgs a) {
   __shared__ __attribute__((aligned(16))) unsigned lds_all[kWaves * kBlk];
   __shared__ unsigned long long red[kWaves];
   __shared__ unsigned redo[kWaves];
-  const unsigned lane = lane_id(), w = threadIdx.x >> 6, G = gridDim.x, seg = blockIdx.x;
+  const unsigned lane = lane_id(), w = wave_id(), G = gridDim.x, seg = blockIdx.x;
   unsigned long long O, N;
   unsigned orv;
   seg_offsets(a.seg_count, a.seg_or, seg, G, O, N, orv, red, redo);
@@ -883,7 +883,7 @@ __global__ __launch_bounds__(kWG) void k_sum(ColView inv, unsigned long long *pa
   __shared__ __attribute__((aligned(16))) unsigned ring[kWaves * kRing * kBlk];
   __shared__ unsigned long long red[kWaves];
   const InCol in = load_in(inv);
-  const unsigned lane = lane_id(), w = threadIdx.x >> 6, G = gridDim.x;
+  const unsigned lane = lane_id(), w = wave_id(), G = gridDim.x;
   unsigned long long s = 0;
   if (in.kind == RLE) {
     // sum over runs: value * run length (section 2.2)
@@ -927,7 +927,7 @@ __global__ __launch_bounds__(kWG) void k_group_sum(ColView gv, ColView vv, unsig
   __shared__ __attribute__((aligned(16))) unsigned lds_all[2 * kWaves * kBlk];
   const InCol ig = load_in(gv);
   const InCol iv = load_in(vv);
-  const unsigned lane = lane_id(), w = threadIdx.x >> 6, G = gridDim.x;
+  const unsigned lane = lane_id(), w = wave_id(), G = gridDim.x;
   if (ig.n != iv.n && blockIdx.x == 0 && threadIdx.x == 0) raise_err(E_LENGTH);
   const unsigned long long n = min(ig.n, iv.n);
   const bool use_lds = G_groups <= kMaxLdsGroups;
@@ -1022,7 +1022,7 @@ __global__ __launch_bounds__(kWG) void k_bitmap(ColView posv, unsigned long long
                                                 unsigned *chunk_first, unsigned *chunk_last) {
   __shared__ __attribute__((aligned(16))) unsigned ring[kWaves * kRing * kBlk];
   const InCol in = load_in(posv);
-  const unsigned lane = lane_id(), w = threadIdx.x >> 6, G = gridDim.x;
+  const unsigned lane = lane_id(), w = wave_id(), G = gridDim.x;
   const unsigned long long C = (in.n + kBlk - 1) / kBlk;
   unsigned long long cb, ce;
   segment(C, blockIdx.x, G, cb, ce);
@@ -1078,7 +1078,7 @@ __global__ void k_check_order(const unsigned *chunk_first, const unsigned *chunk
 __global__ __launch_bounds__(kWG) void k_shrink_payload(const unsigned *src, const unsigned *old_off,
                                                         const unsigned char *widths, const unsigned *new_off,
                                                         unsigned *dst, unsigned long long nb) {
-  const unsigned lane = lane_id(), w = threadIdx.x >> 6;
+  const unsigned lane = lane_id(), w = wave_id();
   for (unsigned long long k = (unsigned long long)blockIdx.x * kWaves + w; k < nb;
        k += (unsigned long long)gridDim.x * kWaves) {
     const unsigned words = 16u * widths[k];

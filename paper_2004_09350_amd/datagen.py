@@ -50,6 +50,22 @@ def stream(seed: int, start: int, count: int) -> np.ndarray:
         return mix64(key + idx * GAMMA)
 
 
+def stream_at(seed: int, idx) -> np.ndarray:
+    """x_i of the same stream at arbitrary indices i (for sampled checks of huge columns)."""
+    key = mix64(np.array([seed & 0xFFFFFFFFFFFFFFFF], dtype=np.uint64))[0]
+    i = np.asarray(idx, dtype=np.uint64)
+    with np.errstate(over="ignore"):
+        return mix64(key + (i + np.uint64(1)) * GAMMA)
+
+
+def uniform_range_at(seed: int, idx, lo: int, span: int) -> np.ndarray:
+    """Element idx of uniform_range(seed, n, lo, span), for any n > idx."""
+    x = stream_at(seed, idx) >> np.uint64(32)
+    with np.errstate(over="ignore"):
+        v = (x * np.uint64(span)) >> np.uint64(32)
+    return (v + np.uint64(lo)).astype(np.uint32)
+
+
 def uniform_bits(seed: int, n: int, b: int, start: int = 0) -> np.ndarray:
     if not 0 <= b <= 32:
         raise ValueError("bit width must be in [0, 32]")
