@@ -183,7 +183,7 @@ class Sweep:
                 ue = 4 * (2 * pinfo["n"]) + int(4 * 16 * frac * ((n + 15) // 16))
                 data = int(frac * fin)
                 alg = {"k_project": pinfo["footprint"] + oi["footprint"] + data,
-                       "k_rle_count": pinfo["footprint"] + data, "k_rle_emit": oi["footprint"]}
+                       "k_rle_count_proj": pinfo["footprint"] + data, "k_rle_emit_proj": oi["footprint"]}
             elif name == "sum":
                 ue = 4 * n + 8
                 alg = {"k_sum": fin}
@@ -409,7 +409,7 @@ def plan_account(M, plan, inputs, log=None):
             data = int(d["footprint"] * sec / nsec)
             ue_total += 8 * p["n"] + 64 * sec
             if s.out.kind == M.RLE:
-                add("k_rle_count", p["footprint"] + data); add("k_rle_emit", out["footprint"])
+                add("k_rle_count_proj", p["footprint"] + data); add("k_rle_emit_proj", out["footprint"])
             else:
                 add(f"k_project<{kout}>", p["footprint"] + out["footprint"] + data)
         elif op == M.OP_SUM:

@@ -406,13 +406,16 @@ __device__ __forceinline__ unsigned src_value(const ChunkSrc &s, const InCol &ia
 
 // Both RLE phases walk the segment's chunks in lockstep, kWaves at a time, so that the
 // value before a chunk (needed to see whether the chunk starts a new run) is the last
-// value of the neighbouring wave's chunk, passed through LDS.
-template <bool EMIT>
+// value of the neighbouring wave's chunk, passed through LDS.  The emit phase stages a
+// chunk's runs in LDS and writes them with coalesced stores.  MODE 0 decodes column a
+// (morph), MODE 1 gathers b at the positions in a (project).
+template <unsigned MODE, bool EMIT>
 __device__ __forceinline__ void rle_walk(const ChunkSrc &s, const ColView &outv, const unsigned *seg_count,
                                          unsigned *seg_out, unsigned *partials) {
   __shared__ __attribute__((aligned(16))) unsigned lds_all[kWaves * kBlk];
-  __shared__ __attribute__((aligned(16))) unsigned gblk[kWaves * kBlk];
-  __shared__ unsigned gstage[kWaves * kBlk];
+  __shared__ __attribute__((aligned(16))) unsigned gblk[MODE == 1 ? kWaves * kBlk : 1];
+  __shared__ unsigned gstage[MODE == 1 ? kWaves * kBlk : 1];
+  __shared__ unsigned rstage[EMIT ? 2 * kWaves * kBlk : 1];
   __shared__ unsigned long long red[kWaves];
   __shared__ unsigned s_chunk_runs[kWaves];
   __shared__ unsigned s_last[kWaves];
@@ -420,7 +423,7 @@ __device__ __forceinline__ void rle_walk(const ChunkSrc &s, const ColView &outv,
   __shared__ unsigned redu[kWaves];
   const InCol ia = load_in(s.a);
   InCol ib = ia;
-  if (s.mode == 1) ib = load_in(s.b);
+  if (MODE == 1) ib = load_in(s.b);
   const unsigned lane = lane_id(), w = wave_id(), G = gridDim.x;
   const unsigned long long n = ia.n;
   const unsigned long long C = (n + kBlk - 1) / kBlk;
@@ -446,6 +449,7 @@ __device__ __forceinline__ void rle_walk(const ChunkSrc &s, const ColView &outv,
   unsigned or_all = 0, cnt_all = 0;
   bool bad = false;
   unsigned *lds = lds_all + w * kBlk;
+  unsigned *rv = rstage + (EMIT ? 2 * w * kBlk : 0), *rs = rv + kBlk;
   Raw cur;
   if (cb + w < ce) cur = issue_chunk(ia, cb + w, lane);
   for (unsigned long long c0 = cb; c0 < ce; c0 += kWaves) {
@@ -455,7 +459,7 @@ __device__ __forceinline__ void rle_walk(const ChunkSrc &s, const ColView &outv,
     unsigned v[8] = {0, 0, 0, 0, 0, 0, 0, 0};
     if (c < ce) {
       finish_chunk(ia, cur, c, lane, lds, v);
-      if (s.mode == 1)
+      if (MODE == 1)
         gather8(ib, v, valid_mask(c * kBlk + 8ull * lane, n), bad, lane, gblk + w * kBlk, gstage + w * kBlk);
       if (lane == 63) s_last[w] = v[7];
     }
@@ -467,10 +471,11 @@ __device__ __forceinline__ void rle_walk(const ChunkSrc &s, const ColView &outv,
       const unsigned long long idx0 = c * kBlk + 8ull * lane;
       unsigned prev = __shfl_up(v[7], 1);
       if (lane == 0) prev = before_chunk;
+      const unsigned valid = valid_mask(idx0, n);
 #pragma unroll
       for (int i = 0; i < 8; i++) {
         const unsigned pv = i ? v[i - 1] : prev;
-        if (idx0 + i < n) {
+        if ((valid >> i) & 1u) {
           or_all |= v[i];
           if (idx0 + i == 0 || v[i] != pv) flags |= 1u << i;
         }
@@ -488,20 +493,26 @@ __device__ __forceinline__ void rle_walk(const ChunkSrc &s, const ColView &outv,
       unsigned long long all = base;
       for (unsigned j = 0; j < kWaves; j++) all += s_chunk_runs[j];
       if (c < ce) {
-        unsigned long long r = my + off;
-        const unsigned long long idx0 = c * kBlk + 8ull * lane;
+        const unsigned idx0 = (unsigned)(c * kBlk) + 8u * lane;
+        unsigned q = off;
 #pragma unroll
         for (int i = 0; i < 8; i++) {
           if (flags & (1u << i)) {
-            if (r < outv.n_cap) {
-              outv.rvalues[r] = v[i];
-              outv.rstarts[r] = (unsigned)(idx0 + i);
-            } else {
-              raise_err(E_INVALID);
-            }
-            r++;
+            rv[q] = v[i];
+            rs[q] = idx0 + i;
+            q++;
           }
         }
+        wave_sync();
+        if (my + chunk_total <= outv.n_cap) {
+          for (unsigned t = lane; t < chunk_total; t += 64) {  // consecutive lanes, consecutive runs
+            outv.rvalues[my + t] = rv[t];
+            outv.rstarts[my + t] = rs[t];
+          }
+        } else if (chunk_total > 0) {
+          raise_err(E_INVALID);
+        }
+        wave_sync();
       }
       base = all;
     }
@@ -523,12 +534,18 @@ __device__ __forceinline__ void rle_walk(const ChunkSrc &s, const ColView &outv,
 }
 
 __global__ __launch_bounds__(kWG) void k_rle_count(ChunkSrc s, unsigned *seg_count) {
-  rle_walk<false>(s, s.a, nullptr, seg_count, nullptr);
+  rle_walk<0, false>(s, s.a, nullptr, seg_count, nullptr);
 }
-
 __global__ __launch_bounds__(kWG) void k_rle_emit(ChunkSrc s, ColView outv, const unsigned *seg_count,
                                                   unsigned *partials) {
-  rle_walk<true>(s, outv, seg_count, nullptr, partials);
+  rle_walk<0, true>(s, outv, seg_count, nullptr, partials);
+}
+__global__ __launch_bounds__(kWG) void k_rle_count_proj(ChunkSrc s, unsigned *seg_count) {
+  rle_walk<1, false>(s, s.a, nullptr, seg_count, nullptr);
+}
+__global__ __launch_bounds__(kWG) void k_rle_emit_proj(ChunkSrc s, ColView outv, const unsigned *seg_count,
+                                                       unsigned *partials) {
+  rle_walk<1, true>(s, outv, seg_count, nullptr, partials);
 }
 
 // ---------------------------------------------------------------------------------------------
@@ -1229,8 +1246,13 @@ hipError_t launch_rle(unsigned mode, const ColView &a, const ColView &b, const C
   src.mode = mode;
   src.a = a;
   src.b = b;
-  MS_LAUNCH(k_rle_count, G, kWG, s, src, seg_count);
-  MS_LAUNCH(k_rle_emit, G, kWG, s, src, out, seg_count, partials);
+  if (mode == 0) {
+    MS_LAUNCH(k_rle_count, G, kWG, s, src, seg_count);
+    MS_LAUNCH(k_rle_emit, G, kWG, s, src, out, seg_count, partials);
+  } else {
+    MS_LAUNCH(k_rle_count_proj, G, kWG, s, src, seg_count);
+    MS_LAUNCH(k_rle_emit_proj, G, kWG, s, src, out, seg_count, partials);
+  }
   return hipGetLastError();
 }
 hipError_t launch_project(const ColView &pos, const ColView &data, const ColView &out, unsigned auto_w, unsigned G,
