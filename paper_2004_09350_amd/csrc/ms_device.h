@@ -8,6 +8,7 @@
 // ORs its window into a zeroed per-wave LDS block, then the wave writes the
 // block out with 16-byte stores.
 #pragma once
+#include <type_traits>
 #include <hip/hip_runtime.h>
 
 #include "ms_internal.h"
@@ -42,21 +43,54 @@ __device__ __forceinline__ void wave_sync() {
   __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
 }
 
-__device__ __forceinline__ unsigned wave_or(unsigned x) {
-#pragma unroll
-  for (int d = 32; d >= 1; d >>= 1) x |= __shfl_xor(x, d);
-  return x;
+// Cross-lane operations through DPP (data-parallel primitives inside the VALU: no LDS
+// round trip).  An inclusive scan runs as four row shifts (1, 2, 4, 8 lanes inside each
+// row of 16; lanes whose source lies outside the row keep the operation's identity), then
+// the totals of rows 0..2, read into scalar registers, are folded into the later rows.
+template <int CTRL, int ROW_MASK>
+__device__ __forceinline__ unsigned dpp(unsigned ident, unsigned x) {
+  return (unsigned)__builtin_amdgcn_update_dpp((int)ident, (int)x, CTRL, ROW_MASK, 0xF, false);
 }
-__device__ __forceinline__ unsigned wave_min(unsigned x) {
-#pragma unroll
-  for (int d = 32; d >= 1; d >>= 1) x = min(x, (unsigned)__shfl_xor(x, d));
-  return x;
+template <class Op>
+__device__ __forceinline__ unsigned wave_incl_scan(unsigned x, unsigned ident, Op op, unsigned &total) {
+  x = op(x, dpp<0x111, 0xF>(ident, x));  // row_shr:1
+  x = op(x, dpp<0x112, 0xF>(ident, x));  // row_shr:2
+  x = op(x, dpp<0x114, 0xF>(ident, x));  // row_shr:4
+  x = op(x, dpp<0x118, 0xF>(ident, x));  // row_shr:8
+  const unsigned t0 = __builtin_amdgcn_readlane(x, 15), t1 = __builtin_amdgcn_readlane(x, 31);
+  const unsigned t2 = __builtin_amdgcn_readlane(x, 47), t3 = __builtin_amdgcn_readlane(x, 63);
+  const unsigned p1 = t0, p2 = op(t0, t1), p3 = op(p2, t2);
+  total = op(p3, t3);
+  const unsigned row = __lane_id() >> 4;
+  return op(x, row == 0 ? ident : row == 1 ? p1 : row == 2 ? p2 : p3);
 }
-__device__ __forceinline__ unsigned wave_add(unsigned x) {
-#pragma unroll
-  for (int d = 32; d >= 1; d >>= 1) x += __shfl_xor(x, d);
-  return x;
+template <class Op>
+__device__ __forceinline__ unsigned wave_incl_scan(unsigned x, unsigned ident, Op op) {
+  unsigned total;
+  return wave_incl_scan(x, ident, op, total);
 }
+struct OpAdd {
+  __device__ unsigned operator()(unsigned a, unsigned b) const { return a + b; }
+};
+struct OpOr {
+  __device__ unsigned operator()(unsigned a, unsigned b) const { return a | b; }
+};
+struct OpMin {
+  __device__ unsigned operator()(unsigned a, unsigned b) const { return a < b ? a : b; }
+};
+// Reductions, as wave-uniform values.
+template <class Op>
+__device__ __forceinline__ unsigned wave_reduce(unsigned x, unsigned ident, Op op) {
+  x = op(x, dpp<0x111, 0xF>(ident, x));  // row_shr:1
+  x = op(x, dpp<0x112, 0xF>(ident, x));  // row_shr:2
+  x = op(x, dpp<0x114, 0xF>(ident, x));  // row_shr:4
+  x = op(x, dpp<0x118, 0xF>(ident, x));  // row_shr:8: lane 15 of each row holds the row's total
+  return op(op(__builtin_amdgcn_readlane(x, 15), __builtin_amdgcn_readlane(x, 31)),
+            op(__builtin_amdgcn_readlane(x, 47), __builtin_amdgcn_readlane(x, 63)));
+}
+__device__ __forceinline__ unsigned wave_or(unsigned x) { return wave_reduce(x, 0u, OpOr()); }
+__device__ __forceinline__ unsigned wave_min(unsigned x) { return wave_reduce(x, 0xFFFFFFFFu, OpMin()); }
+__device__ __forceinline__ unsigned wave_add(unsigned x) { return wave_reduce(x, 0u, OpAdd()); }
 __device__ __forceinline__ unsigned long long wave_add64(unsigned long long x) {
 #pragma unroll
   for (int d = 32; d >= 1; d >>= 1) x += __shfl_xor(x, d);
@@ -64,14 +98,21 @@ __device__ __forceinline__ unsigned long long wave_add64(unsigned long long x) {
 }
 // Exclusive prefix sum over the 64 lanes (wrapping uint32 arithmetic).
 __device__ __forceinline__ unsigned wave_excl_scan(unsigned x, unsigned lane) {
-  unsigned incl = x;
-#pragma unroll
-  for (int d = 1; d < 64; d <<= 1) {
-    unsigned y = __shfl_up(incl, d);
-    if (lane >= (unsigned)d) incl += y;
-  }
-  return incl - x;
+  (void)lane;
+  return wave_incl_scan(x, 0u, OpAdd()) - x;
 }
+// The value of the previous lane (lane 0 gets 0): a row shift, and the last lane of the
+// previous row for the first lane of rows 1..3.
+__device__ __forceinline__ unsigned lane_prev(unsigned x) {
+  const unsigned y = dpp<0x111, 0xF>(0u, x);  // row_shr:1
+  const unsigned l = __lane_id();
+  const unsigned e15 = __builtin_amdgcn_readlane(x, 15), e31 = __builtin_amdgcn_readlane(x, 31);
+  const unsigned e47 = __builtin_amdgcn_readlane(x, 47);
+  return l == 16 ? e15 : l == 32 ? e31 : l == 48 ? e47 : y;
+}
+// The value of lane 63 / lane 0, wave-uniform.
+__device__ __forceinline__ unsigned lane_last(unsigned x) { return __builtin_amdgcn_readlane(x, 63); }
+__device__ __forceinline__ unsigned lane_first(unsigned x) { return __builtin_amdgcn_readlane(x, 0); }
 
 // ---------------------------------------------------------------------------------------------
 // Unpack: lane's 8 values of a block packed at width W (block 64-byte aligned).
@@ -515,119 +556,6 @@ __device__ __forceinline__ void finish_chunk(const InCol &in, const Raw &r, unsi
   }
 }
 
-// ---------------------------------------------------------------------------------------------
-// DMA-pipelined chunk stream.  Each wave keeps kRing chunks in flight in a ring of
-// 512-word LDS buffers, filled by direct global->LDS loads (16 bytes per lane, no
-// VGPRs).  Every chunk costs exactly two such loads (a chunk that needs fewer, or
-// takes the direct path, repeats a load of a valid address), so the wait before
-// chunk j is "vmcnt <= 2 * (chunks issued after j)".  Loads return in order, so
-// other loads or stores issued in between only make that wait stricter.
-constexpr int kRing = 4;
-
-typedef __attribute__((address_space(1))) void gvoid_t;
-typedef __attribute__((address_space(3))) void lvoid_t;
-
-__device__ __forceinline__ void dma16(const void *gsrc, unsigned *lds_dst) {
-  __builtin_amdgcn_global_load_lds((gvoid_t *)gsrc, (lvoid_t *)lds_dst, 16, 0, 0);
-}
-
-// s_waitcnt vmcnt(k) leaving the other counters untouched (gfx9 encoding).
-__device__ __forceinline__ void wait_vm(unsigned k) {
-  switch (k) {
-    case 0: __builtin_amdgcn_s_waitcnt(0x0F70); break;
-    case 1: case 2: __builtin_amdgcn_s_waitcnt(0x0F72); break;
-    case 3: case 4: __builtin_amdgcn_s_waitcnt(0x0F74); break;
-    case 5: case 6: __builtin_amdgcn_s_waitcnt(0x0F76); break;
-    default: __builtin_amdgcn_s_waitcnt(0x0F70); break;
-  }
-}
-
-__device__ __forceinline__ void compiler_fence() { asm volatile("" ::: "memory"); }
-
-// How chunk c is read: 0 packed block via LDS, 1 uncompressed via LDS, 2 direct path.
-__device__ __forceinline__ unsigned chunk_mode(const InCol &in, unsigned long long c, unsigned &W,
-                                               unsigned long long &off) {
-  const unsigned long long c0 = c * kBlk;
-  W = 0;
-  off = 0;
-  switch (in.kind) {
-    case UNCOMPR: return (c0 + kBlk <= in.n) ? 1u : 2u;
-    case STATIC_BP:
-      if (c0 + kBlk <= in.n_main && in.W <= 32) {
-        W = in.W;
-        off = c * 16ull * in.W;
-        return 0u;
-      }
-      return 2u;
-    case DYN_BP:
-    case DELTA_DYN_BP:
-    case FOR_DYN_BP:
-      if (c < in.nb) {
-        W = uni((unsigned)in.widths[c]);
-        off = uni((unsigned long long)in.offsets[c]);
-        if (W > 32 || off + 16ull * W > in.payload_cap) {  // a corrupt directory never reads out of bounds
-          W = 0;
-          off = 0;
-        }
-        return 0u;
-      }
-      return 2u;
-    default: return 2u;
-  }
-}
-
-__device__ __forceinline__ void issue_dma(const InCol &in, unsigned long long c, unsigned lane, unsigned *buf,
-                                          const void *dummy) {
-  unsigned W;
-  unsigned long long off;
-  const unsigned mode = chunk_mode(in, c, W, off);
-  const uint4 *a0 = reinterpret_cast<const uint4 *>(dummy), *a1 = a0;
-  if (mode == 1) {
-    const uint4 *p4 = reinterpret_cast<const uint4 *>(in.payload + c * kBlk);
-    a0 = p4 + lane;
-    a1 = p4 + 64 + lane;
-  } else if (mode == 0 && W > 0) {
-    const uint4 *b4 = reinterpret_cast<const uint4 *>(in.payload + off);
-    const unsigned nq = 4u * W;
-    a0 = (lane < nq) ? b4 + lane : b4;
-    a1 = (lane + 64 < nq) ? b4 + 64 + lane : b4;
-  }
-  compiler_fence();
-  dma16(a0, buf);
-  dma16(a1, buf + 256);
-  compiler_fence();
-}
-
-__device__ __forceinline__ void consume_chunk(const InCol &in, unsigned long long c, unsigned lane,
-                                              const unsigned *buf, unsigned (&v)[8], unsigned long long &rle_hint) {
-  unsigned W;
-  unsigned long long off;
-  const unsigned mode = chunk_mode(in, c, W, off);
-  if (mode == 1) {
-    const uint4 *b4 = reinterpret_cast<const uint4 *>(buf) + 2 * lane;
-    const uint4 a = b4[0], b = b4[1];
-    v[0] = a.x; v[1] = a.y; v[2] = a.z; v[3] = a.w;
-    v[4] = b.x; v[5] = b.y; v[6] = b.z; v[7] = b.w;
-    return;
-  }
-  if (mode == 2) {
-    decode_chunk(in, c, lane, v, rle_hint);
-    return;
-  }
-  unpack8_rt(W, buf, lane, v);
-  if (in.kind == FOR_DYN_BP) {
-    const unsigned ref = uni(in.bases[c]);
-#pragma unroll
-    for (int i = 0; i < 8; i++) v[i] += ref;
-  } else if (in.kind == DELTA_DYN_BP) {
-#pragma unroll
-    for (int i = 1; i < 8; i++) v[i] += v[i - 1];
-    const unsigned excl = wave_excl_scan(v[7], lane) + uni(in.bases[c]);
-#pragma unroll
-    for (int i = 0; i < 8; i++) v[i] += excl;
-  }
-}
-
 // v[k] for a lane-varying k in 0..7, as a chain of selects (an indexed read of the
 // register array would go through scratch memory).
 __device__ __forceinline__ unsigned select8(const unsigned (&v)[8], unsigned k) {
@@ -638,6 +566,105 @@ __device__ __forceinline__ unsigned select8(const unsigned (&v)[8], unsigned k) 
     asm volatile("" : "+v"(x));
   }
   return x;
+}
+
+constexpr int kRing = 4;  // the kernels' per-wave LDS buffer holds kRing * 512 words
+
+// ---------------------------------------------------------------------------------------------
+// Direct window loads.  A packed 512-value block (uncompressed = width 32) is read by
+// each lane straight into registers: its 8 values are W bytes at byte lane * W, a window
+// of at most 9 words.  Loads of kPre chunks are in flight per wave; every width has its
+// own load and unpack code, picked by a scalar branch per chunk.
+constexpr int kPre = 4;
+constexpr int kWin = 9;
+struct Win {
+  unsigned x[kWin];
+};
+
+template <int W>
+__device__ __forceinline__ void win_issue(const unsigned *__restrict__ blk, unsigned lane, Win &r) {
+  if constexpr (W == 0) {
+    return;
+  } else if constexpr (W % 16 == 0) {  // 16-byte aligned window of W/4 words
+    const uint4 *q = reinterpret_cast<const uint4 *>(blk + lane * (W / 4));
+#pragma unroll
+    for (int k = 0; k < W / 16; k++) {
+      const uint4 a = q[k];
+      r.x[4 * k] = a.x; r.x[4 * k + 1] = a.y; r.x[4 * k + 2] = a.z; r.x[4 * k + 3] = a.w;
+    }
+  } else if constexpr (W % 8 == 0) {  // 8-byte aligned window of W/4 words
+    const uint2 *q = reinterpret_cast<const uint2 *>(blk + lane * (W / 4));
+#pragma unroll
+    for (int k = 0; k < W / 8; k++) {
+      const uint2 a = q[k];
+      r.x[2 * k] = a.x; r.x[2 * k + 1] = a.y;
+    }
+  } else if constexpr (W % 4 == 0) {
+    const unsigned *q = blk + lane * (W / 4);
+#pragma unroll
+    for (int k = 0; k < W / 4; k++) r.x[k] = q[k];
+  } else {  // window at byte lane * W: (W + 3) / 4 words and one more for the shift
+    const unsigned *q = blk + ((lane * W) >> 2);
+#pragma unroll
+    for (int k = 0; k <= (W + 3) / 4; k++) r.x[k] = q[k];
+  }
+}
+
+template <int W>
+__device__ __forceinline__ void win_unpack(const Win &r, unsigned lane, unsigned (&v)[8]) {
+  if constexpr (W == 0) {
+#pragma unroll
+    for (int i = 0; i < 8; i++) v[i] = 0;
+  } else if constexpr (W == 32) {
+#pragma unroll
+    for (int i = 0; i < 8; i++) v[i] = r.x[i];
+  } else if constexpr (W % 4 == 0) {
+    extract8<W>(r.x, v);
+  } else {
+    constexpr int NW = (W + 3) / 4;
+    const unsigned sh = ((lane * W) & 3u) * 8u;
+    unsigned w[NW];
+#pragma unroll
+    for (int k = 0; k < NW; k++) w[k] = __builtin_amdgcn_alignbit(r.x[k + 1], r.x[k], sh);
+    extract8<W>(w, v);
+  }
+}
+
+// Fixed-count window loads (the same loads for every width, so that the compiler can
+// count them and wait only for the chunk it consumes): 9 words from word (lane*W)/4 of a
+// packed block, or a lane's 8 words of an uncompressed chunk.
+__device__ __forceinline__ void win_issue9(const unsigned *__restrict__ blk, unsigned W, unsigned lane, Win &r) {
+  const unsigned *q = blk + ((lane * W) >> 2);
+#pragma unroll
+  for (int k = 0; k < kWin; k++) r.x[k] = q[k];
+}
+__device__ __forceinline__ void win_issue_unc(const unsigned *__restrict__ blk, unsigned lane, Win &r) {
+  const uint4 *q = reinterpret_cast<const uint4 *>(blk + 8u * lane);
+  const uint4 a = q[0], b = q[1];
+  r.x[0] = a.x; r.x[1] = a.y; r.x[2] = a.z; r.x[3] = a.w;
+  r.x[4] = b.x; r.x[5] = b.y; r.x[6] = b.z; r.x[7] = b.w;
+}
+
+__device__ __forceinline__ void win_issue_rt(unsigned W, const unsigned *__restrict__ blk, unsigned lane, Win &r) {
+  switch (W) {
+#define MS_ISSUE_CASE(w) \
+  case w: win_issue<w>(blk, lane, r); break;
+    MS_WIDTH_CASES(MS_ISSUE_CASE)
+#undef MS_ISSUE_CASE
+    default: break;
+  }
+}
+
+__device__ __forceinline__ void win_unpack_rt(unsigned W, const Win &r, unsigned lane, unsigned (&v)[8]) {
+  switch (W) {
+#define MS_WUNPACK_CASE(w) \
+  case w: win_unpack<w>(r, lane, v); break;
+    MS_WIDTH_CASES(MS_WUNPACK_CASE)
+#undef MS_WUNPACK_CASE
+    default:
+#pragma unroll
+      for (int i = 0; i < 8; i++) v[i] = 0;
+  }
 }
 
 // RLE input walked run by run.  Wave w takes a contiguous quarter of the chunks
@@ -728,7 +755,7 @@ __device__ __forceinline__ void rle_stream(const InCol &in, unsigned long long c
       for (int i = 0; i < 8; i++) v[i] = 0u;
     }
     // the run holding c1, the first value of the next chunk
-    const unsigned jl = __shfl(j, 63);
+    const unsigned jl = lane_last(j);
     const unsigned nxt = (jl + 1 < nst) ? S[(r + jl + 1) & kRunMask] : 0xFFFFFFFFu;
     wave_sync();
     est = jl + 1;
@@ -748,35 +775,156 @@ __device__ __forceinline__ void rle_stream(const InCol &in, unsigned long long c
   }
 }
 
-// Walk the wave's chunks cb + w + kWaves*j < ce with kRing chunks in flight.
-// ring: the wave's kRing * 512 LDS words; dummy: any valid 16-byte global address.
+// The chunks c = cb + w + kWaves * j < ce of an UNCOMPR (UNC) or packed column: full
+// blocks stream through direct window loads, kPre chunks ahead, with the block
+// directory of the next group of chunks loaded one group earlier (lane s holds chunk
+// s's entry); the remaining chunks take the direct path.
+template <bool UNC, class Body>
+__device__ __forceinline__ void stream_blocks(const InCol &in, unsigned long long cb, unsigned long long ce,
+                                              unsigned w, unsigned lane, Body &&body) {
+  const unsigned long long first = cb + w;
+  if (first >= ce) return;
+  const unsigned long long nj = (ce - first + kWaves - 1) / kWaves;
+  const bool dyn = !UNC && (in.kind == DYN_BP || in.kind == DELTA_DYN_BP || in.kind == FOR_DYN_BP);
+  unsigned long long cmain;  // chunks [0, cmain) are full packed blocks
+  unsigned Wfix = 32;
+  if (UNC) {
+    cmain = in.n / kBlk;
+  } else if (in.kind == STATIC_BP) {
+    cmain = (in.W <= 32) ? in.n_main / kBlk : 0ull;
+    Wfix = in.W;
+  } else {
+    cmain = in.nb;
+  }
+  const unsigned long long njm = (first < cmain) ? min(nj, (cmain - first + kWaves - 1) / kWaves) : 0ull;
+  if (njm > 0) {
+    // directory of group g (chunks 4g .. 4g+3 of this wave) in lanes 0..3
+    auto dir_load = [&](unsigned long long g, unsigned &dw, unsigned &doff, unsigned &dbase) {
+      const unsigned long long j = kPre * g + lane;
+      dw = 0;
+      doff = 0;
+      dbase = 0;
+      if (dyn && lane < (unsigned)kPre && j < njm) {
+        const unsigned long long c = first + kWaves * j;
+        dw = in.widths[c];
+        doff = in.offsets[c];
+        dbase = in.bases[c];
+      }
+    };
+    // width and payload offset of chunk j, whose directory entry is in lane s of (dw, doff)
+    auto locate = [&](unsigned long long j, unsigned s, unsigned dw, unsigned doff, unsigned &W,
+                      unsigned long long &off) {
+      const unsigned long long c = first + kWaves * j;
+      if (dyn) {
+        W = __builtin_amdgcn_readlane(dw, s);
+        off = __builtin_amdgcn_readlane(doff, s);
+        if (W > 32 || off + 16ull * W > in.payload_cap) {  // a corrupt directory never reads out of bounds
+          raise_err(E_INVALID);
+          W = 0;
+          off = 0;
+        }
+      } else {
+        W = Wfix;
+        off = c * 16ull * Wfix;
+      }
+    };
+    Win win[kPre];
+    unsigned dwA, doA, dbA, dwB, doB, dbB;
+    dir_load(0, dwA, doA, dbA);
+    dir_load(1, dwB, doB, dbB);
+    auto prime = [&](auto S) {
+      constexpr int s = decltype(S)::value;
+      if ((unsigned long long)s < njm) {
+        unsigned W;
+        unsigned long long off;
+        locate(s, s, dwA, doA, W, off);
+        if (UNC)
+          win_issue_unc(in.payload + off, lane, win[s]);
+        else
+          win_issue9(in.payload + off, W, lane, win[s]);
+      }
+    };
+    prime(std::integral_constant<int, 0>{});
+    prime(std::integral_constant<int, 1>{});
+    prime(std::integral_constant<int, 2>{});
+    prime(std::integral_constant<int, 3>{});
+    for (unsigned long long g = 0; kPre * g < njm; g++) {
+      unsigned dwC, doC, dbC;
+      dir_load(g + 2, dwC, doC, dbC);
+      // one chunk per slot; the slot index is a compile-time constant so that the
+      // windows stay in registers
+      auto slot = [&](auto S) {
+        constexpr int s = decltype(S)::value;
+        const unsigned long long j = kPre * g + s;
+        if (j < njm) {
+          const unsigned long long c = first + kWaves * j;
+          unsigned W;
+          unsigned long long off;
+          locate(j, s, dwA, doA, W, off);
+          unsigned v[8];
+          if (UNC) {
+#pragma unroll
+            for (int i = 0; i < 8; i++) v[i] = win[s].x[i];
+          } else {
+            win_unpack_rt(W, win[s], lane, v);
+          }
+          if (in.kind == FOR_DYN_BP) {
+            const unsigned ref = __builtin_amdgcn_readlane(dbA, s);
+#pragma unroll
+            for (int i = 0; i < 8; i++) v[i] += ref;
+          } else if (in.kind == DELTA_DYN_BP) {
+#pragma unroll
+            for (int i = 1; i < 8; i++) v[i] += v[i - 1];
+            const unsigned excl = wave_excl_scan(v[7], lane) + __builtin_amdgcn_readlane(dbA, s);
+#pragma unroll
+            for (int i = 0; i < 8; i++) v[i] += excl;
+          }
+          if (j + kPre < njm) {
+            unsigned Wn;
+            unsigned long long offn;
+            locate(j + kPre, s, dwB, doB, Wn, offn);
+            if (UNC)
+              win_issue_unc(in.payload + offn, lane, win[s]);
+            else
+              win_issue9(in.payload + offn, Wn, lane, win[s]);
+          }
+          body(c, v);
+        }
+      };
+      static_assert(kPre == 4, "four slots below");
+      slot(std::integral_constant<int, 0>{});
+      slot(std::integral_constant<int, 1>{});
+      slot(std::integral_constant<int, 2>{});
+      slot(std::integral_constant<int, 3>{});
+      dwA = dwB; doA = doB; dbA = dbB;
+      dwB = dwC; doB = doC; dbB = dbC;
+    }
+  }
+  unsigned long long rle_hint = 0;
+  for (unsigned long long j = njm; j < nj; j++) {
+    const unsigned long long c = first + kWaves * j;
+    unsigned v[8];
+    decode_chunk(in, c, lane, v, rle_hint);
+    body(c, v);
+  }
+}
+
+// Walk the wave's chunks c = cb + w + kWaves * j < ce.  Full packed blocks (the main
+// part of UNCOMPR, STATIC_BP and the DynBP family) stream through direct window loads,
+// kPre chunks ahead, with the block directory of the next group of chunks loaded one
+// group earlier (lane s holds chunk s's entry); the remaining chunks take the direct
+// path.  RLE columns are walked run by run.  ring: the wave's kRing * 512 LDS words.
 template <class Body>
 __device__ __forceinline__ void stream_chunks(const InCol &in, unsigned long long cb, unsigned long long ce,
                                               unsigned w, unsigned lane, unsigned *ring, const void *dummy,
                                               Body &&body) {
-  if (in.kind == RLE) {
+  (void)dummy;
+  if (in.kind == RLE)
     rle_stream(in, cb, ce, w, lane, ring, body);
-    return;
-  }
-  const unsigned long long first = cb + w;
-  if (first >= ce) return;
-  const unsigned long long nj = (ce - first + kWaves - 1) / kWaves;
-  const unsigned long long pre = min(nj, (unsigned long long)kRing);
-  for (unsigned long long j = 0; j < pre; j++) issue_dma(in, first + kWaves * j, lane, ring + kBlk * j, dummy);
-  unsigned long long rle_hint = 0;
-  for (unsigned long long j = 0; j < nj; j++) {
-    const unsigned long long ahead = min(nj - 1 - j, (unsigned long long)kRing - 1);
-    wait_vm(2u * (unsigned)ahead);
-    compiler_fence();
-    unsigned *buf = ring + kBlk * (j % kRing);
-    const unsigned long long c = first + kWaves * j;
-    unsigned v[8];
-    consume_chunk(in, c, lane, buf, v, rle_hint);
-    body(c, v);
-    compiler_fence();
-    if (j + kRing < nj) issue_dma(in, first + kWaves * (j + kRing), lane, buf, dummy);
-  }
-  wait_vm(0);
+  else if (in.kind == UNCOMPR)
+    stream_blocks<true>(in, cb, ce, w, lane, body);
+  else
+    stream_blocks<false>(in, cb, ce, w, lane, body);
 }
 
 // Walk chunks cb + w, cb + w + kWaves, ... < ce with one chunk of look-ahead;

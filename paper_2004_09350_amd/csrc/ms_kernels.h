@@ -39,7 +39,8 @@ struct EmitArgs {
   const unsigned *seg_count;
   const unsigned *seg_or;
   const unsigned *chunk_first, *chunk_last;
-  unsigned *stage_g;          // global staging for blocks shared by several segments
+  unsigned *stage_g;          // global staging for blocks shared by several waves
+  unsigned *wave_count;       // outputs of each wave (kWaves per workgroup), for the fix phase
   unsigned *partials;
 };
 

@@ -91,8 +91,8 @@ __device__ __forceinline__ void encode_dyn_block(const OutCol &o, unsigned long 
   unsigned r[8];
   unsigned base = 0;
   if (o.c.kind == DELTA_DYN_BP) {
-    const unsigned prev = __shfl_up(v[7], 1);
-    base = __shfl(v[0], 0);
+    const unsigned prev = lane_prev(v[7]);
+    base = lane_first(v[0]);
     r[0] = lane ? v[0] - prev : 0u;
 #pragma unroll
     for (int i = 1; i < 8; i++) r[i] = v[i] - v[i - 1];
@@ -469,7 +469,7 @@ __device__ __forceinline__ void rle_walk(const ChunkSrc &s, const ColView &outv,
     unsigned flags = 0;
     if (c < ce) {
       const unsigned long long idx0 = c * kBlk + 8ull * lane;
-      unsigned prev = __shfl_up(v[7], 1);
+      unsigned prev = lane_prev(v[7]);
       if (lane == 0) prev = before_chunk;
       const unsigned valid = valid_mask(idx0, n);
 #pragma unroll
@@ -485,7 +485,7 @@ __device__ __forceinline__ void rle_walk(const ChunkSrc &s, const ColView &outv,
     cnt_all += cnt;
     if (EMIT) {
       const unsigned off = wave_excl_scan(cnt, lane);
-      const unsigned chunk_total = __shfl(off + cnt, 63);
+      const unsigned chunk_total = lane_last(off + cnt);
       if (lane == 0) s_chunk_runs[w] = chunk_total;
       __syncthreads();
       unsigned long long my = base;
@@ -595,7 +595,7 @@ __global__ __launch_bounds__(kWG) void k_pred(PredArgs a) {
       for (int i = 0; i < 8; i++)
         if (mask & (1u << i)) orv |= v[i];
       // strictly increasing inside the chunk; chunk ends are checked by the emit phase
-      const unsigned prev = __shfl_up(v[7], 1);
+      const unsigned prev = lane_prev(v[7]);
 #pragma unroll
       for (int i = 0; i < 8; i++) {
         const unsigned pv = i ? v[i - 1] : prev;
@@ -619,8 +619,6 @@ __global__ __launch_bounds__(kWG) void k_pred(PredArgs a) {
 
 // ---------------------------------------------------------------------------------------------
 // Compaction phase 2: emit.
-constexpr int kEmitChunks = 8;                 // chunks per emit tile (2 per wave)
-constexpr int kStage = kEmitChunks * kBlk + kBlk;
 
 // Output blocks of a compaction: 512-blocks over [0, Nb), Nb = n_main for the DynBP
 // family (the rest is remainder) and N for static BP (the last block may be partial).
@@ -657,10 +655,42 @@ __device__ __forceinline__ unsigned emit_width(const EmitArgs &a, unsigned orv) 
   return (a.out.kind == STATIC_BP && a.auto_w) ? bw(orv) : a.out.width;
 }
 
+// Output range of wave w of workgroup seg: [Ow, Ew), from the workgroup's offset O and
+// the per-wave counts.
+__device__ __forceinline__ void wave_range(const unsigned *cnt4, unsigned w, unsigned long long O,
+                                           unsigned long long &Ow, unsigned long long &Ew) {
+  unsigned long long before = 0;
+  for (unsigned j = 0; j < w; j++) before += cnt4[j];
+  Ow = O + before;
+  Ew = Ow + cnt4[w];
+}
+
+// Blocks owned by the output range [Ow, Ew): those lying entirely inside it and below Nb
+// are packed by the wave from LDS; the other block elements go to the global stage.
+__device__ __forceinline__ void owned_blocks(unsigned long long Ow, unsigned long long Ew, unsigned long long Nb,
+                                             unsigned long long &A, unsigned long long &B) {
+  const unsigned long long Eb = min(Ew, Nb);
+  const unsigned long long kA = (Ow + kBlk - 1) / kBlk;
+  const unsigned long long kB1 = (Eb == Nb && Nb > 0) ? (Nb + kBlk - 1) / kBlk : Eb / kBlk;
+  if (Ow >= Nb || kA >= kB1) {
+    A = B = (Ow < Nb) ? Ow : Nb;
+  } else {
+    A = kA * kBlk;
+    B = blk_end(kB1 - 1, Nb);
+  }
+}
+
+// Compaction phase 2.  Each wave emits a contiguous quarter of its workgroup's chunks on
+// its own: it counts its outputs from the bitmask, learns its output offset through
+// LDS, then streams its chunks, appending outputs of owned blocks to a two-block ring
+// in its LDS and packing each block as soon as it is complete.  No workgroup barrier
+// inside the loop.
+constexpr unsigned kEmitRing = 2 * kBlk;
+
 __global__ __launch_bounds__(kWG) void k_emit(EmitArgs a) {
-  __shared__ __attribute__((aligned(16))) unsigned stage[kStage];
+  __shared__ __attribute__((aligned(16))) unsigned ring_all[kWaves * kEmitRing];
   __shared__ __attribute__((aligned(16))) unsigned lds_all[kWaves * kBlk];
-  __shared__ unsigned s_ctot[kEmitChunks];
+  __shared__ unsigned s_wcnt[kWaves];
   __shared__ unsigned long long red[kWaves];
   __shared__ unsigned redo[kWaves];
   const InCol in = load_in(a.in);
@@ -683,174 +713,135 @@ __global__ __launch_bounds__(kWG) void k_emit(EmitArgs a) {
     a.out.hdr->runs = (kind == RLE) ? N : 0ull;
     a.out.hdr->sbp_width = (kind == STATIC_BP) ? Wp : 0u;
   }
-  const unsigned long long E = O + a.seg_count[seg];   // this segment's outputs are [O, E)
-  // Owned blocks lie entirely inside [O, E) and below Nb; all other block elements are staged.
-  unsigned long long A = 0, B = 0;
-  if (blocky) {
-    const unsigned long long Eb = min(E, Nb);
-    const unsigned long long kA = (O + kBlk - 1) / kBlk;
-    const unsigned long long kB1 = (Eb == Nb && Nb > 0) ? (Nb + kBlk - 1) / kBlk : Eb / kBlk;
-    if (O >= Nb || kA >= kB1) {
-      A = B = (O < Nb) ? O : Nb;
-    } else {
-      A = kA * kBlk;
-      B = blk_end(kB1 - 1, Nb);
-    }
-  }
   if (a.check_sorted) {
     for (unsigned long long c = cb + threadIdx.x; c < ce; c += kWG)
       if (c > 0 && a.chunk_first[c] <= a.chunk_last[c - 1]) raise_err(E_NOT_SORTED);
   }
+  // this wave's chunks and its output count
+  const unsigned long long nseg = ce - cb;
+  const unsigned long long cw0 = cb + nseg * w / kWaves, cw1 = cb + nseg * (w + 1) / kWaves;
+  unsigned cnt = 0;
+#pragma unroll 4
+  for (unsigned long long c = cw0; c < cw1; c++) cnt += __popc((unsigned)a.bitmask[c * 64 + lane]);
+  cnt = wave_add(cnt);
+  if (lane == 0) {
+    s_wcnt[w] = cnt;
+    a.wave_count[(unsigned long long)kWaves * seg + w] = cnt;
+  }
+  __syncthreads();
+  unsigned long long Ow, Ew;
+  wave_range(s_wcnt, w, O, Ow, Ew);
+  unsigned long long A = 0, B = 0;
+  if (blocky) owned_blocks(Ow, Ew, Nb, A, B);
 
   unsigned or_main = 0;
   const bool cap_ok = N <= a.out.n_cap;
-  unsigned long long emitted = 0;   // outputs of this segment so far
-  unsigned long long Lbase = A;     // global index of stage[0]
-  unsigned *lds = lds_all + w * kBlk;
   const unsigned long long n_main_o = o.n_main;
-
-  // bitmask bytes of the next tile are loaded while the current one is emitted
-  unsigned nmsk[2];
+  unsigned *ring = ring_all + w * kEmitRing;
+  unsigned *lds = lds_all + w * kBlk;
+  unsigned long long g_done = A;   // owned outputs below g_done are packed
+  unsigned long long g = Ow;       // next output index of this wave
+  // bitmask bytes four chunks ahead
+  unsigned q0 = (cw0 < cw1) ? a.bitmask[cw0 * 64 + lane] : 0u;
+  unsigned q1 = (cw0 + 1 < cw1) ? a.bitmask[(cw0 + 1) * 64 + lane] : 0u;
+  unsigned q2 = (cw0 + 2 < cw1) ? a.bitmask[(cw0 + 2) * 64 + lane] : 0u;
+  unsigned q3 = (cw0 + 3 < cw1) ? a.bitmask[(cw0 + 3) * 64 + lane] : 0u;
+  for (unsigned long long c = cw0; c < cw1; c++) {
+    unsigned m = q0;
+    q0 = q1;
+    q1 = q2;
+    q2 = q3;
+    q3 = (c + 4 < cw1) ? a.bitmask[(c + 4) * 64 + lane] : 0u;
+    unsigned v[8];
+    if (a.emit_values) decode_chunk(in, c, lane, v);
+    const unsigned cntl = __popc(m);
+    const unsigned off = wave_excl_scan(cntl, lane);
+    const unsigned tot = lane_last(off + cntl);
+    const unsigned long long idx0 = c * kBlk + 8ull * lane;
+    unsigned long long gl = g + off;   // this lane's first output
+    const unsigned long long gend = gl + cntl;
+    const bool fast = cap_ok && gend <= n_main_o && (blocky ? (gl >= A && gend <= B) : true);
+    if (fast) {
+      unsigned vals[8];
 #pragma unroll
-  for (int j = 0; j < 2; j++) {
-    const unsigned long long c = cb + 2 * w + j;
-    nmsk[j] = (c < ce) ? a.bitmask[c * 64 + lane] : 0u;
-  }
-  for (unsigned long long t0 = cb; t0 < ce; t0 += kEmitChunks) {
-    unsigned v[2][8];
-    unsigned msk[2], off[2];
+      for (int i = 0; i < 8; i++) vals[i] = a.emit_values ? v[i] : (unsigned)(idx0 + i);
+      unsigned r = 0, orl = 0;
+      if (blocky) {
+        const unsigned base = (unsigned)(gl - A);
 #pragma unroll
-    for (int j = 0; j < 2; j++) {
-      msk[j] = nmsk[j];
-      const unsigned long long cn = t0 + kEmitChunks + 2 * w + j;
-      nmsk[j] = (cn < ce) ? a.bitmask[cn * 64 + lane] : 0u;
-    }
-#pragma unroll
-    for (int j = 0; j < 2; j++) {
-      const unsigned lc = 2 * w + j;
-      const unsigned long long c = t0 + lc;
-      if (c < ce) {
-        if (a.emit_values) decode_chunk(in, c, lane, v[j]);
-      }
-      const unsigned cntl = __popc(msk[j]);
-      off[j] = wave_excl_scan(cntl, lane);
-      if (lane == 63) s_ctot[lc] = off[j] + cntl;
-    }
-    __syncthreads();
-    unsigned long long tile_total = 0, cbase[2] = {0, 0};
-    for (unsigned lc = 0; lc < kEmitChunks; lc++) {
-      if (lc == 2 * w) cbase[0] = tile_total;
-      if (lc == 2 * w + 1) cbase[1] = tile_total;
-      tile_total += s_ctot[lc];
-    }
-#pragma unroll
-    for (int j = 0; j < 2; j++) {
-      const unsigned long long c = t0 + 2 * w + j;
-      unsigned m = msk[j];
-      unsigned long long g = O + emitted + cbase[j] + off[j];
-      const unsigned long long idx0 = c * kBlk + 8ull * lane;
-      // Fast path: all of this lane's outputs land in one region (the owned, staged blocks;
-      // or the values/runs of an uncompressed or RLE output) below n_main.
-      const unsigned long long gend = g + __popc(m);
-      const bool fast = cap_ok && gend <= n_main_o &&
-                        (blocky ? (g >= A && gend <= B && gend - Lbase <= (unsigned long long)kStage) : true);
-      if (fast) {
-        unsigned vals[8];
-#pragma unroll
-        for (int i = 0; i < 8; i++) vals[i] = a.emit_values ? v[j][i] : (unsigned)(idx0 + i);
-        unsigned r = 0, orl = 0;
-        if (blocky) {
-          unsigned *st = stage + (unsigned)(g - Lbase);
-#pragma unroll
-          for (int i = 0; i < 8; i++)
-            if ((m >> i) & 1u) {
-              st[r++] = vals[i];
-              orl |= vals[i];
-            }
-        } else if (kind == UNCOMPR) {
-          unsigned *dst = a.out.payload + g;
-#pragma unroll
-          for (int i = 0; i < 8; i++)
-            if ((m >> i) & 1u) {
-              dst[r++] = vals[i];
-              orl |= vals[i];
-            }
-        } else {
-#pragma unroll
-          for (int i = 0; i < 8; i++)
-            if ((m >> i) & 1u) {
-              a.out.rvalues[g + r] = vals[i];
-              a.out.rstarts[g + r] = (unsigned)(g + r);
-              orl |= vals[i];
-              r++;
-            }
-        }
-        or_main |= orl;
-        m = 0;
-      }
-      while (m) {
-        const unsigned i = __ffs(m) - 1;
-        m &= m - 1;
-        unsigned val = (unsigned)(idx0 + i);
-        if (a.emit_values) {
-#pragma unroll
-          for (int q = 0; q < 8; q++)
-            if (q == (int)i) val = v[j][q];
-        }
-        if (g < n_main_o) or_main |= val;
-        if (g >= a.out.n_cap) {
-          raise_err(E_INVALID);
-        } else if (kind == UNCOMPR) {
-          a.out.payload[g] = val;
-        } else if (kind == RLE) {
-          a.out.rvalues[g] = val;
-          a.out.rstarts[g] = (unsigned)g;
-        } else if (g >= Nb) {
-          a.out.rem[g - Nb] = val;             // DynBP-family remainder
-        } else if (g < A || g >= B) {
-          a.stage_g[g] = val;                  // block shared with a neighbouring segment
-        } else {
-          const unsigned long long li = g - Lbase;
-          if (li < (unsigned long long)kStage)
-            stage[li] = val;
-          else
-            raise_err(E_INVALID);
-        }
-        g++;
-      }
-    }
-    __syncthreads();
-    emitted += tile_total;
-    if (blocky && B > A) {
-      const unsigned long long have_end = min(O + emitted, B);
-      if (have_end > Lbase) {
-        const unsigned long long have = have_end - Lbase;
-        const unsigned long long nfull = have / kBlk;
-        const bool final_partial = (have_end == B) && (have % kBlk != 0);  // last block of the output
-        const unsigned long long nenc = nfull + (final_partial ? 1 : 0);
-        for (unsigned long long j = w; j < nenc; j += kWaves) {
-          unsigned x[8];
-          const unsigned long long l0 = j * kBlk + 8ull * lane;
-          if (l0 + 8 <= have) {  // two 16-byte reads: no bank conflicts between lanes
-            const uint4 *s4 = reinterpret_cast<const uint4 *>(stage + l0);
-            const uint4 p = s4[0], q = s4[1];
-            x[0] = p.x; x[1] = p.y; x[2] = p.z; x[3] = p.w;
-            x[4] = q.x; x[5] = q.y; x[6] = q.z; x[7] = q.w;
-          } else {
-#pragma unroll
-            for (int i = 0; i < 8; i++) x[i] = (l0 + i < have) ? stage[l0 + i] : 0u;
+        for (int i = 0; i < 8; i++)
+          if ((m >> i) & 1u) {
+            ring[(base + r) & (kEmitRing - 1)] = vals[i];
+            orl |= vals[i];
+            r++;
           }
-          encode_out_block(o, (Lbase / kBlk) + j, x, lane, lds, or_main);
-        }
-        __syncthreads();
-        const unsigned long long keep = final_partial ? 0 : have - nfull * kBlk;
-        if (nfull > 0) {
-          for (unsigned long long i = threadIdx.x; i < keep; i += kWG) stage[i] = stage[nfull * kBlk + i];
-        }
-        __syncthreads();
-        Lbase += nenc * kBlk;
-        if (final_partial) Lbase = B;
+      } else if (kind == UNCOMPR) {
+        unsigned *dst = a.out.payload + gl;
+#pragma unroll
+        for (int i = 0; i < 8; i++)
+          if ((m >> i) & 1u) {
+            dst[r++] = vals[i];
+            orl |= vals[i];
+          }
+      } else {
+#pragma unroll
+        for (int i = 0; i < 8; i++)
+          if ((m >> i) & 1u) {
+            a.out.rvalues[gl + r] = vals[i];
+            a.out.rstarts[gl + r] = (unsigned)(gl + r);
+            orl |= vals[i];
+            r++;
+          }
       }
+      or_main |= orl;
+      m = 0;
+    }
+    while (m) {
+      const unsigned i = __ffs(m) - 1;
+      m &= m - 1;
+      const unsigned val = a.emit_values ? select8(v, i) : (unsigned)(idx0 + i);
+      if (gl < n_main_o) or_main |= val;
+      if (gl >= a.out.n_cap) {
+        raise_err(E_INVALID);
+      } else if (kind == UNCOMPR) {
+        a.out.payload[gl] = val;
+      } else if (kind == RLE) {
+        a.out.rvalues[gl] = val;
+        a.out.rstarts[gl] = (unsigned)gl;
+      } else if (gl >= Nb) {
+        a.out.rem[gl - Nb] = val;             // DynBP-family remainder
+      } else if (gl < A || gl >= B) {
+        a.stage_g[gl] = val;                  // block shared with a neighbouring wave
+      } else {
+        ring[(unsigned)(gl - A) & (kEmitRing - 1)] = val;
+      }
+      gl++;
+    }
+    g += tot;
+    if (blocky && B > A) {
+      wave_sync();
+      // pack every owned block that is now complete (the last block of the output may be partial)
+      const unsigned long long have_end = min(g, B);
+      while (g_done < have_end) {
+        const unsigned long long bend = blk_end(g_done / kBlk, Nb);
+        if (bend > have_end) break;
+        const unsigned len = (unsigned)(bend - g_done);
+        const unsigned *src = ring + ((unsigned)(g_done - A) & (kEmitRing - 1));
+        unsigned x[8];
+        const unsigned l0 = 8u * lane;
+        if (l0 + 8 <= len) {  // two 16-byte reads: no bank conflicts between lanes
+          const uint4 *s4 = reinterpret_cast<const uint4 *>(src + l0);
+          const uint4 p = s4[0], q = s4[1];
+          x[0] = p.x; x[1] = p.y; x[2] = p.z; x[3] = p.w;
+          x[4] = q.x; x[5] = q.y; x[6] = q.z; x[7] = q.w;
+        } else {
+#pragma unroll
+          for (int i = 0; i < 8; i++) x[i] = (l0 + i < len) ? src[l0 + i] : 0u;
+        }
+        encode_out_block(o, g_done / kBlk, x, lane, lds, or_main);
+        g_done = bend;
+      }
+      wave_sync();
     }
   }
   or_main = wg_or(or_main, redo);
@@ -860,8 +851,8 @@ __global__ __launch_bounds__(kWG) void k_emit(EmitArgs a) {
   }
 }
 
-// Compaction phase 3 (block formats): a block that started in an earlier segment is
-// packed from the staging array by the segment that holds its last element.
+// Compaction phase 3 (block formats): a block that started before a wave's output range
+// is packed from the global stage by the wave whose range holds its last element.
 __global__ __launch_bounds__(kWG) void k_emit_fix(EmitArgs a) {
   __shared__ __attribute__((aligned(16))) unsigned lds_all[kWaves * kBlk];
   __shared__ unsigned long long red[kWaves];
@@ -870,28 +861,27 @@ __global__ __launch_bounds__(kWG) void k_emit_fix(EmitArgs a) {
   unsigned long long O, N;
   unsigned orv;
   seg_offsets(a.seg_count, a.seg_or, seg, G, O, N, orv, red, redo);
-  const unsigned long long E = O + a.seg_count[seg];
   const unsigned Wp = emit_width(a, orv);
   const OutCol o = make_out(a.out, N, Wp);
   const unsigned long long Nb = (a.out.kind == STATIC_BP) ? N : o.n_main;
-  const unsigned long long Eb = min(E, Nb);
-  if (Eb <= O) return;  // no block element in this segment
-  // Only the block holding the segment's first output can have started in an earlier
-  // segment; it is packed here when it also ends inside this segment.
-  const unsigned long long k = O / kBlk;
+  unsigned long long Ow, Ew;
+  wave_range(a.wave_count + (unsigned long long)kWaves * seg, w, O, Ow, Ew);
+  const unsigned long long Eb = min(Ew, Nb);
+  if (Eb <= Ow) return;  // no block element in this wave's range
+  // Only the block holding the range's first output can have started before it; it is
+  // packed here when it also ends inside the range.
+  const unsigned long long k = Ow / kBlk;
   const unsigned long long end = blk_end(k, Nb);
-  if (k * kBlk == O || end > Eb) return;
-  if (w == 0) {
-    const unsigned long long len = end - k * kBlk;
-    unsigned x[8];
+  if (k * kBlk == Ow || end > Eb) return;
+  const unsigned long long len = end - k * kBlk;
+  unsigned x[8];
 #pragma unroll
-    for (int i = 0; i < 8; i++) {
-      const unsigned long long li = 8ull * lane + i;
-      x[i] = (li < len) ? a.stage_g[k * kBlk + li] : 0u;
-    }
-    unsigned om = 0;
-    encode_out_block(o, k, x, lane, lds_all, om);
+  for (int i = 0; i < 8; i++) {
+    const unsigned long long li = 8ull * lane + i;
+    x[i] = (li < len) ? a.stage_g[k * kBlk + li] : 0u;
   }
+  unsigned om = 0;
+  encode_out_block(o, k, x, lane, lds_all + w * kBlk, om);
 }
 
 // ---------------------------------------------------------------------------------------------
@@ -1048,7 +1038,7 @@ __global__ __launch_bounds__(kWG) void k_bitmap(ColView posv, unsigned long long
     const unsigned long long idx0 = c * kBlk + 8ull * lane;
     const unsigned valid = valid_mask(idx0, in.n);
     if (chunk_first) {
-      const unsigned prev = __shfl_up(v[7], 1);
+      const unsigned prev = lane_prev(v[7]);
 #pragma unroll
       for (int i = 0; i < 8; i++) {
         const unsigned pv = i ? v[i - 1] : prev;
