@@ -183,6 +183,7 @@ class Sweep:
                 ue = 4 * (2 * pinfo["n"]) + int(4 * 16 * frac * ((n + 15) // 16))
                 data = int(frac * fin)
                 alg = {"k_project": pinfo["footprint"] + oi["footprint"] + data,
+                       "k_project_rle": pinfo["footprint"] + oi["footprint"] + data,
                        "k_rle_count_proj": pinfo["footprint"] + data, "k_rle_emit_proj": oi["footprint"]}
             elif name == "sum":
                 ue = 4 * n + 8
@@ -411,7 +412,8 @@ def plan_account(M, plan, inputs, log=None):
             if s.out.kind == M.RLE:
                 add("k_rle_count_proj", p["footprint"] + data); add("k_rle_emit_proj", out["footprint"])
             else:
-                add(f"k_project<{kout}>", p["footprint"] + out["footprint"] + data)
+                kname = "k_project_rle" if d["kind"] == M.RLE else "k_project"
+                add(f"{kname}<{kout}>", p["footprint"] + out["footprint"] + data)
         elif op == M.OP_SUM:
             a = inf(s.a)
             ue_total += 4 * a["n"] + 8

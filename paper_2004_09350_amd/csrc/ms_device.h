@@ -1065,14 +1065,84 @@ __device__ __forceinline__ void gather8_blocks(const InCol &d, unsigned (&v)[8],
 }
 
 // blk, stage: the wave's two 512-word LDS buffers (used for DELTA and RLE data only).
+// Gather from an RLE column.  When the wave's positions ascend (select outputs do), the
+// runs spanning them are staged window by window in LDS (512 runs, 511 of them
+// resolvable, per window; S: starts, V: values) and every position is found by binary
+// search there; each window starts at the run of the smallest pending position.  Other
+// position orders search each position on its own.
+__device__ __forceinline__ void gather8_rle(const InCol &d, unsigned (&v)[8], unsigned valid, bool &bad,
+                                            unsigned lane, unsigned *S, unsigned *V) {
+  unsigned pend = 0;
+#pragma unroll
+  for (int i = 0; i < 8; i++) {
+    if ((valid >> i) & 1u) {
+      if (v[i] < d.n)
+        pend |= 1u << i;
+      else
+        bad = true;
+    }
+  }
+  bool ok = true;
+#pragma unroll
+  for (int i = 1; i < 8; i++)
+    if ((valid >> i) & 1u) ok = ok && v[i - 1] <= v[i];
+  const unsigned pl = lane_prev(v[7]);
+  if (lane > 0 && (valid & 1u)) ok = ok && pl <= v[0];
+  if (__ballot(!ok) != 0ull || d.runs == 0) {
+#pragma unroll
+    for (int i = 0; i < 8; i++) v[i] = ((pend >> i) & 1u) ? value_at(d, v[i]) : 0u;
+    return;
+  }
+  unsigned res[8];
+#pragma unroll
+  for (int i = 0; i < 8; i++) res[i] = 0;
+  unsigned long long r = 0;
+  bool first = true;
+  while (__ballot(pend != 0) != 0ull) {
+    unsigned mine = 0xFFFFFFFFu;
+#pragma unroll
+    for (int i = 0; i < 8; i++)
+      if ((pend >> i) & 1u) mine = min(mine, v[i]);
+    const unsigned pmin = wave_min(mine);
+    r = rle_find_wave(d, pmin, lane, first ? 0ull : r);
+    first = false;
+#pragma unroll
+    for (int k = 0; k < 8; k++) {
+      const unsigned long long q = r + 64ull * k + lane;
+      S[64 * k + lane] = (q < d.runs) ? d.rstarts[q] : 0xFFFFFFFFu;
+      V[64 * k + lane] = (q < d.runs) ? d.rvalues[q] : 0u;
+    }
+    wave_sync();
+    const unsigned s_end = S[511];  // positions below the start of the last staged run resolve here
+#pragma unroll
+    for (int i = 0; i < 8; i++) {
+      if (((pend >> i) & 1u) && v[i] < s_end) {
+        unsigned lo = 0;  // last staged run starting at or before v[i] (S[0] <= v[i] < S[511])
+#pragma unroll
+        for (unsigned step = 256; step > 0; step >>= 1)
+          if (lo + step < 511u && S[lo + step] <= v[i]) lo += step;
+        res[i] = V[lo];
+        pend &= ~(1u << i);
+      }
+    }
+    wave_sync();
+    r += 511;
+  }
+#pragma unroll
+  for (int i = 0; i < 8; i++) v[i] = res[i];
+}
+
+template <bool WITH_RLE = true>
 __device__ __forceinline__ void gather8(const InCol &d, unsigned (&v)[8], unsigned valid, bool &bad, unsigned lane,
                                         unsigned *blk, unsigned *stage) {
   switch (d.kind) {
     case UNCOMPR: gather8_kind<UNCOMPR>(d, v, valid, bad); break;
     case STATIC_BP: gather8_kind<STATIC_BP>(d, v, valid, bad); break;
     case DYN_BP: gather8_kind<DYN_BP>(d, v, valid, bad); break;
-    case DELTA_DYN_BP:
-    case RLE: gather8_blocks(d, v, valid, bad, lane, blk, stage); break;
+    case DELTA_DYN_BP: gather8_blocks(d, v, valid, bad, lane, blk, stage); break;
+    case RLE:
+      if constexpr (WITH_RLE) gather8_rle(d, v, valid, bad, lane, blk, stage);
+      break;
     case FOR_DYN_BP: gather8_kind<FOR_DYN_BP>(d, v, valid, bad); break;
     default: break;
   }

@@ -353,9 +353,12 @@ __global__ __launch_bounds__(kWG) void k_decode(ColView inv, unsigned *__restric
 
 // ---------------------------------------------------------------------------------------------
 // Project: out_j = data[pos_j].
-template <unsigned OK>
-__global__ __launch_bounds__(kWG) void k_project(ColView posv, ColView datav, ColView outv, unsigned auto_w,
-                                                 unsigned *partials) {
+// Project: gather the data column at the positions streamed from posv and encode the
+// values into the output format.  RLE data columns have their own kernel (their gather
+// stages runs in LDS and needs its own registers).
+template <unsigned OK, bool DRLE>
+__device__ __forceinline__ void project_body(const ColView &posv, const ColView &datav, const ColView &outv,
+                                             unsigned auto_w, unsigned *partials) {
   __shared__ __attribute__((aligned(16))) unsigned ring[kWaves * kRing * kBlk];
   __shared__ __attribute__((aligned(16))) unsigned gblk[kWaves * kBlk];
   __shared__ __attribute__((aligned(16))) unsigned lds_all[kWaves * kBlk];
@@ -377,7 +380,11 @@ __global__ __launch_bounds__(kWG) void k_project(ColView posv, ColView datav, Co
     unsigned v[8];
 #pragma unroll
     for (int i = 0; i < 8; i++) v[i] = pv[i];
-    gather8(id, v, valid_mask(c * kBlk + 8ull * lane, ip.n), bad, lane, gblk + w * kBlk, lds);
+    const unsigned valid = valid_mask(c * kBlk + 8ull * lane, ip.n);
+    if constexpr (DRLE)
+      gather8_rle(id, v, valid, bad, lane, gblk + w * kBlk, lds);
+    else
+      gather8<false>(id, v, valid, bad, lane, gblk + w * kBlk, lds);
     write_chunk_known<OK>(o, c, v, lane, lds, or_all, or_main);
   });
   if (bad) raise_err(E_RANGE);
@@ -387,6 +394,17 @@ __global__ __launch_bounds__(kWG) void k_project(ColView posv, ColView datav, Co
     partials[2 * blockIdx.x] = or_all;
     partials[2 * blockIdx.x + 1] = or_main;
   }
+}
+
+template <unsigned OK>
+__global__ __launch_bounds__(kWG, 3) void k_project(ColView posv, ColView datav, ColView outv, unsigned auto_w,
+                                                 unsigned *partials) {
+  project_body<OK, false>(posv, datav, outv, auto_w, partials);
+}
+template <unsigned OK>
+__global__ __launch_bounds__(kWG) void k_project_rle(ColView posv, ColView datav, ColView outv, unsigned auto_w,
+                                                     unsigned *partials) {
+  project_body<OK, true>(posv, datav, outv, auto_w, partials);
 }
 
 // ---------------------------------------------------------------------------------------------
@@ -1247,9 +1265,15 @@ hipError_t launch_rle(unsigned mode, const ColView &a, const ColView &b, const C
 }
 hipError_t launch_project(const ColView &pos, const ColView &data, const ColView &out, unsigned auto_w, unsigned G,
                           unsigned *partials, void *s) {
-#define MS_L(K) MS_LAUNCH(k_project<K>, G, kWG, s, pos, data, out, auto_w, partials)
-  MS_BY_OUT_KIND(out.kind, MS_L)
+  if (data.kind == RLE) {
+#define MS_L(K) MS_LAUNCH(k_project_rle<K>, G, kWG, s, pos, data, out, auto_w, partials)
+    MS_BY_OUT_KIND(out.kind, MS_L)
 #undef MS_L
+  } else {
+#define MS_L(K) MS_LAUNCH(k_project<K>, G, kWG, s, pos, data, out, auto_w, partials)
+    MS_BY_OUT_KIND(out.kind, MS_L)
+#undef MS_L
+  }
   return hipGetLastError();
 }
 hipError_t launch_pred(const PredArgs &a, unsigned G, void *s) {

@@ -37,7 +37,7 @@ KIND_NAMES = ("UNCOMPR", "STATIC_BP", "DYN_BP", "DELTA_DYN_BP", "FOR_DYN_BP", "R
 def canonical(name: str) -> str:
     """Kernel names as the library's launch timer reports them (k_morph<DYN_BP>, k_pred<0>)."""
     n = short(name)
-    m = re.match(r"(k_morph|k_project)<(\d+)>", n)
+    m = re.match(r"(k_morph|k_project|k_project_rle)<(\d+)>", n)
     if m:
         return f"{m.group(1)}<{KIND_NAMES[int(m.group(2))]}>"
     return n
