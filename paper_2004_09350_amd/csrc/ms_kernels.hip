@@ -754,97 +754,100 @@ __global__ __launch_bounds__(kWG) void k_emit(EmitArgs a) {
 
   unsigned or_main = 0;
   const bool cap_ok = N <= a.out.n_cap;
-  const unsigned long long n_main_o = o.n_main;
+  // Output indices are below 2^32 (columns hold fewer than 2^32 values): 32-bit from here.
+  const unsigned n_main_o = (unsigned)o.n_main, A32 = (unsigned)A, B32 = (unsigned)B, Nb32 = (unsigned)Nb;
+  const unsigned cap32 = (unsigned)min(a.out.n_cap, 0xFFFFFFFFull);
   unsigned *ring = ring_all + w * kEmitRing;
   unsigned *lds = lds_all + w * kBlk;
-  unsigned long long g_done = A;   // owned outputs below g_done are packed
-  unsigned long long g = Ow;       // next output index of this wave
+  unsigned g_done = A32;          // owned outputs below g_done are packed
+  unsigned g = (unsigned)Ow;      // next output index of this wave
+  const unsigned char *bm = a.bitmask + lane;
   // bitmask bytes four chunks ahead
-  unsigned q0 = (cw0 < cw1) ? a.bitmask[cw0 * 64 + lane] : 0u;
-  unsigned q1 = (cw0 + 1 < cw1) ? a.bitmask[(cw0 + 1) * 64 + lane] : 0u;
-  unsigned q2 = (cw0 + 2 < cw1) ? a.bitmask[(cw0 + 2) * 64 + lane] : 0u;
-  unsigned q3 = (cw0 + 3 < cw1) ? a.bitmask[(cw0 + 3) * 64 + lane] : 0u;
+  unsigned q0 = (cw0 < cw1) ? bm[cw0 * 64] : 0u;
+  unsigned q1 = (cw0 + 1 < cw1) ? bm[(cw0 + 1) * 64] : 0u;
+  unsigned q2 = (cw0 + 2 < cw1) ? bm[(cw0 + 2) * 64] : 0u;
+  unsigned q3 = (cw0 + 3 < cw1) ? bm[(cw0 + 3) * 64] : 0u;
   for (unsigned long long c = cw0; c < cw1; c++) {
     unsigned m = q0;
     q0 = q1;
     q1 = q2;
     q2 = q3;
-    q3 = (c + 4 < cw1) ? a.bitmask[(c + 4) * 64 + lane] : 0u;
+    q3 = (c + 4 < cw1) ? bm[(c + 4) * 64] : 0u;
     unsigned v[8];
     if (a.emit_values) decode_chunk(in, c, lane, v);
     const unsigned cntl = __popc(m);
     const unsigned off = wave_excl_scan(cntl, lane);
     const unsigned tot = lane_last(off + cntl);
-    const unsigned long long idx0 = c * kBlk + 8ull * lane;
-    unsigned long long gl = g + off;   // this lane's first output
-    const unsigned long long gend = gl + cntl;
-    const bool fast = cap_ok && gend <= n_main_o && (blocky ? (gl >= A && gend <= B) : true);
-    if (fast) {
-      unsigned vals[8];
-#pragma unroll
-      for (int i = 0; i < 8; i++) vals[i] = a.emit_values ? v[i] : (unsigned)(idx0 + i);
-      unsigned r = 0, orl = 0;
-      if (blocky) {
-        const unsigned base = (unsigned)(gl - A);
-#pragma unroll
-        for (int i = 0; i < 8; i++)
-          if ((m >> i) & 1u) {
-            ring[(base + r) & (kEmitRing - 1)] = vals[i];
-            orl |= vals[i];
-            r++;
-          }
-      } else if (kind == UNCOMPR) {
-        unsigned *dst = a.out.payload + gl;
-#pragma unroll
-        for (int i = 0; i < 8; i++)
-          if ((m >> i) & 1u) {
-            dst[r++] = vals[i];
-            orl |= vals[i];
-          }
-      } else {
-#pragma unroll
-        for (int i = 0; i < 8; i++)
-          if ((m >> i) & 1u) {
-            a.out.rvalues[gl + r] = vals[i];
-            a.out.rstarts[gl + r] = (unsigned)(gl + r);
-            orl |= vals[i];
-            r++;
-          }
+    const unsigned idx0 = (unsigned)(c * kBlk) + 8u * lane;
+    unsigned gl = g + off;   // this lane's first output
+    const unsigned gend = gl + cntl;
+    if (blocky) {
+      if (cap_ok && gend <= n_main_o && gl >= A32 && gend <= B32) {
+        // owned, staged block elements: append to the ring
+        unsigned k = gl - A32, orl = 0;
+        while (m) {
+          const unsigned i = __ffs(m) - 1;
+          m &= m - 1;
+          const unsigned val = a.emit_values ? select8(v, i) : idx0 + i;
+          ring[k & (kEmitRing - 1)] = val;
+          orl |= val;
+          k++;
+        }
+        or_main |= orl;
       }
-      or_main |= orl;
-      m = 0;
+    } else if (cap_ok && tot > 0) {
+      // uncompressed and RLE outputs: stage the chunk's outputs, then coalesced stores
+      unsigned k = off, orl = 0;
+      while (m) {
+        const unsigned i = __ffs(m) - 1;
+        m &= m - 1;
+        const unsigned val = a.emit_values ? select8(v, i) : idx0 + i;
+        lds[k++] = val;
+        orl |= val;
+      }
+      or_main |= orl;  // n_main = N for these kinds
+      wave_sync();
+      if (kind == UNCOMPR) {
+        for (unsigned t = lane; t < tot; t += 64) a.out.payload[g + t] = lds[t];
+      } else {
+        for (unsigned t = lane; t < tot; t += 64) {
+          a.out.rvalues[g + t] = lds[t];
+          a.out.rstarts[g + t] = g + t;
+        }
+      }
+      wave_sync();
     }
-    while (m) {
+    while (m) {  // elements outside the fast paths
       const unsigned i = __ffs(m) - 1;
       m &= m - 1;
-      const unsigned val = a.emit_values ? select8(v, i) : (unsigned)(idx0 + i);
+      const unsigned val = a.emit_values ? select8(v, i) : idx0 + i;
       if (gl < n_main_o) or_main |= val;
-      if (gl >= a.out.n_cap) {
+      if (gl >= cap32) {
         raise_err(E_INVALID);
       } else if (kind == UNCOMPR) {
         a.out.payload[gl] = val;
       } else if (kind == RLE) {
         a.out.rvalues[gl] = val;
-        a.out.rstarts[gl] = (unsigned)gl;
-      } else if (gl >= Nb) {
-        a.out.rem[gl - Nb] = val;             // DynBP-family remainder
-      } else if (gl < A || gl >= B) {
+        a.out.rstarts[gl] = gl;
+      } else if (gl >= Nb32) {
+        a.out.rem[gl - Nb32] = val;           // DynBP-family remainder
+      } else if (gl < A32 || gl >= B32) {
         a.stage_g[gl] = val;                  // block shared with a neighbouring wave
       } else {
-        ring[(unsigned)(gl - A) & (kEmitRing - 1)] = val;
+        ring[(gl - A32) & (kEmitRing - 1)] = val;
       }
       gl++;
     }
     g += tot;
-    if (blocky && B > A) {
+    if (blocky && B32 > A32) {
       wave_sync();
       // pack every owned block that is now complete (the last block of the output may be partial)
-      const unsigned long long have_end = min(g, B);
+      const unsigned have_end = min(g, B32);
       while (g_done < have_end) {
-        const unsigned long long bend = blk_end(g_done / kBlk, Nb);
+        const unsigned bend = (unsigned)blk_end(g_done / kBlk, Nb);
         if (bend > have_end) break;
-        const unsigned len = (unsigned)(bend - g_done);
-        const unsigned *src = ring + ((unsigned)(g_done - A) & (kEmitRing - 1));
+        const unsigned len = bend - g_done;
+        const unsigned *src = ring + ((g_done - A32) & (kEmitRing - 1));
         unsigned x[8];
         const unsigned l0 = 8u * lane;
         if (l0 + 8 <= len) {  // two 16-byte reads: no bank conflicts between lanes
