@@ -292,7 +292,7 @@ ms_status compaction(const ms_column *in, const PredArgs &pa_in, bool emit_value
   ea.chunk_first = pa.chunk_first;
   ea.chunk_last = pa.chunk_last;
   ea.stage_g = blocky ? sc.get<unsigned>(n_cap + 1) : nullptr;
-  ea.wave_count = sc.get<unsigned>((uint64_t)kWaves * G);
+  ea.wave_count = sc.get<unsigned>(2ull * kWaves * G);
   ea.partials = sc.get<unsigned>(2 * G);
   unsigned *narrow_tmp = (fmt.kind == MS_STATIC_BP && auto_w) ? sc.get<unsigned>(n_cap + kPayloadSlackWords) : nullptr;
   if (!sc.ok) {

@@ -40,7 +40,7 @@ struct EmitArgs {
   const unsigned *seg_or;
   const unsigned *chunk_first, *chunk_last;
   unsigned *stage_g;          // global staging for blocks shared by several waves
-  unsigned *wave_count;       // outputs of each wave (kWaves per workgroup), for the fix phase
+  unsigned *wave_count;       // (first output, count) of each wave (kWaves per workgroup), for the fix phase
   unsigned *partials;
 };
 

@@ -742,13 +742,14 @@ __global__ __launch_bounds__(kWG) void k_emit(EmitArgs a) {
 #pragma unroll 4
   for (unsigned long long c = cw0; c < cw1; c++) cnt += __popc((unsigned)a.bitmask[c * 64 + lane]);
   cnt = wave_add(cnt);
-  if (lane == 0) {
-    s_wcnt[w] = cnt;
-    a.wave_count[(unsigned long long)kWaves * seg + w] = cnt;
-  }
+  if (lane == 0) s_wcnt[w] = cnt;
   __syncthreads();
   unsigned long long Ow, Ew;
   wave_range(s_wcnt, w, O, Ow, Ew);
+  if (lane == 0) {  // the fix phase reads each wave's output range from here
+    a.wave_count[2ull * (kWaves * seg + w)] = (unsigned)Ow;
+    a.wave_count[2ull * (kWaves * seg + w) + 1] = cnt;
+  }
   unsigned long long A = 0, B = 0;
   if (blocky) owned_blocks(Ow, Ew, Nb, A, B);
 
@@ -876,17 +877,14 @@ __global__ __launch_bounds__(kWG) void k_emit(EmitArgs a) {
 // is packed from the global stage by the wave whose range holds its last element.
 __global__ __launch_bounds__(kWG) void k_emit_fix(EmitArgs a) {
   __shared__ __attribute__((aligned(16))) unsigned lds_all[kWaves * kBlk];
-  __shared__ unsigned long long red[kWaves];
-  __shared__ unsigned redo[kWaves];
-  const unsigned lane = lane_id(), w = wave_id(), G = gridDim.x, seg = blockIdx.x;
-  unsigned long long O, N;
-  unsigned orv;
-  seg_offsets(a.seg_count, a.seg_or, seg, G, O, N, orv, red, redo);
-  const unsigned Wp = emit_width(a, orv);
+  const unsigned lane = lane_id(), w = wave_id(), seg = blockIdx.x;
+  // the emit phase recorded the output count and width in the header, and each wave's range
+  const unsigned long long N = a.out.hdr->n;
+  const unsigned Wp = (a.out.kind == STATIC_BP) ? a.out.hdr->sbp_width : a.out.width;
   const OutCol o = make_out(a.out, N, Wp);
   const unsigned long long Nb = (a.out.kind == STATIC_BP) ? N : o.n_main;
-  unsigned long long Ow, Ew;
-  wave_range(a.wave_count + (unsigned long long)kWaves * seg, w, O, Ow, Ew);
+  const unsigned long long Ow = a.wave_count[2ull * (kWaves * seg + w)];
+  const unsigned long long Ew = Ow + a.wave_count[2ull * (kWaves * seg + w) + 1];
   const unsigned long long Eb = min(Ew, Nb);
   if (Eb <= Ow) return;  // no block element in this wave's range
   // Only the block holding the range's first output can have started before it; it is
