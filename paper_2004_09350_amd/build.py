@@ -4,6 +4,7 @@ from __future__ import annotations
 import os
 import subprocess
 import sys
+from concurrent.futures import ThreadPoolExecutor
 
 HERE = os.path.dirname(os.path.abspath(__file__))
 CSRC = os.path.join(HERE, "csrc")
@@ -13,24 +14,37 @@ ARCH = os.environ.get("MS_OFFLOAD_ARCH", "gfx950")
 COMMON = ["-O3", "-std=c++17", "-fPIC", f"--offload-arch={ARCH}",
           "-Xclang", "-target-feature", "-Xclang", "-packed-fp32-ops", "-Wno-unused-command-line-argument"]
 
+# (source, extra flags): morph and project are compiled once per output kind
+# (MS_OK = UNCOMPR 0 .. FOR_DYN_BP 4) so that the instantiations build in parallel.
+_PER_KIND = [(src, [f"-DMS_OK={k}"]) for src in ("ms_project.hip", "ms_morph.hip") for k in range(5)]
 LIBS = {
-    "libmorphgpu.so": ["ms_kernels.hip", "ms_api.hip", "ms_plan.hip"],
-    "libmsgen.so": ["datagen.hip"],
+    "libmorphgpu.so": _PER_KIND + [("ms_kernels.hip", []), ("ms_api.hip", []), ("ms_plan.hip", [])],
+    "libmsgen.so": [("datagen.hip", [])],
 }
+JOBS = max(1, min(16, int(os.environ.get("MAX_JOBS", os.cpu_count() or 1))))
+
+
+def _object(src: str, flags) -> str:
+    tag = "".join("." + f[2:].replace("=", "").lower() for f in flags)
+    return os.path.join(CSRC, "_build", os.path.basename(src) + tag + ".o")
 
 
 def build_lib(name: str, verbose: bool = True) -> str:
     out = os.path.join(HERE, name)
-    srcs = [os.path.join(CSRC, s) for s in LIBS[name]]
-    objs = []
-    for s in srcs:
-        o = os.path.join(CSRC, "_build", os.path.basename(s) + ".o")
+    jobs = []
+    for src, flags in LIBS[name]:
+        o = _object(src, flags)
         os.makedirs(os.path.dirname(o), exist_ok=True)
-        cmd = [HIPCC, *COMMON, "-c", s, "-o", o]
+        jobs.append([HIPCC, *COMMON, *flags, "-c", os.path.join(CSRC, src), "-o", o])
+
+    def run(cmd):
         if verbose:
             print(" ".join(cmd), flush=True)
         subprocess.check_call(cmd)
-        objs.append(o)
+        return cmd[-1]
+
+    with ThreadPoolExecutor(max_workers=JOBS) as ex:
+        objs = list(ex.map(run, jobs))
     tmp = out + ".tmp"
     cmd = [HIPCC, f"--offload-arch={ARCH}", "-shared", "-fPIC", "-o", tmp, *objs]
     if verbose:

@@ -337,6 +337,8 @@ ms_status ms_init(ms_alloc_fn alloc, ms_free_fn free_fn, void *ctx) {
   e = hipGetDeviceProperties(&prop, dev);
   if (e != hipSuccess) return hip_fail(e, "hipGetDeviceProperties");
   g_cus = prop.multiProcessorCount > 0 ? prop.multiProcessorCount : 256;
+  e = init_err_word();
+  if (e != hipSuccess) return hip_fail(e, "device error word");
   g_alloc = alloc;
   g_free = free_fn;
   g_ctx = ctx;
@@ -696,9 +698,13 @@ ms_status ms_bitmap_from_positions(const ms_column *pos, uint64_t domain, uint32
   if (domain > (1ull << 32)) return fail(MS_ERR_INVALID_ARG, "domain exceeds 2^32");
   const uint64_t words = (domain + 31) / 32;
   if (words && !dev_bitmap) return fail(MS_ERR_INVALID_ARG, "bitmap is NULL");
-  hipError_t e = launch_fill_u32(dev_bitmap, words, 0u, stream);
   const uint64_t n_cap = pos->n_host != kUnknown ? pos->n_host : pos->n_cap;
-  if (e == hipSuccess) e = launch_bitmap(pos->v, domain, dev_bitmap, grid_for(chunks_of(n_cap)), stream);
+  Scratch sc(stream);
+  unsigned *ends = sc.get<unsigned>(4 * chunks_of(n_cap) + 4);
+  if (!sc.ok) return fail(MS_ERR_OOM, "scratch allocation failed");
+  hipError_t e = launch_fill_u32(dev_bitmap, words, 0u, stream);
+  if (e == hipSuccess)
+    e = launch_bitmap(pos->v, domain, dev_bitmap, ends, nullptr, nullptr, grid_for(chunks_of(n_cap)), stream);
   return e == hipSuccess ? MS_OK : hip_fail(e, "kernel launch");
 }
 
@@ -738,12 +744,11 @@ ms_status ms_intersect(const ms_column *a, const ms_column *b, uint64_t domain, 
   const uint64_t ncb = std::max(ca, cb);
   const uint64_t Cb = chunks_of(ncb);
   unsigned *first = sc.get<unsigned>(Cb + 1), *last = sc.get<unsigned>(Cb + 1);
+  unsigned *ends = sc.get<unsigned>(4 * Cb + 4);
   if (!sc.ok) return fail(MS_ERR_OOM, "scratch allocation failed");
   {
     hipError_t e = launch_fill_u32(bm, words, 0u, stream);
-    if (e == hipSuccess)
-      e = launch_bitmap_checked(build->v, domain, bm, first, last, grid_for(Cb), stream);
-    if (e == hipSuccess) e = launch_check_order(first, last, build->v, stream);
+    if (e == hipSuccess) e = launch_bitmap(build->v, domain, bm, ends, first, last, grid_for(Cb), stream);
     if (e != hipSuccess) return hip_fail(e, "kernel launch");
   }
   PredArgs pa;

@@ -19,10 +19,14 @@ namespace ms {
   X(0) X(1) X(2) X(3) X(4) X(5) X(6) X(7) X(8) X(9) X(10) X(11) X(12) X(13) X(14) X(15) X(16) X(17) X(18) X(19) \
   X(20) X(21) X(22) X(23) X(24) X(25) X(26) X(27) X(28) X(29) X(30) X(31) X(32)
 
-__device__ unsigned int g_err;               // first data-dependent error since the last sync
-__device__ unsigned int g_ring[kRingSlots];  // self-resetting "last workgroup" counters
+// Address of the library's device error word (the first data-dependent error since the
+// last sync).  Every translation unit has its own copy of this pointer; all of them are
+// set to the same word when the library is initialised.
+namespace {
+__constant__ unsigned *g_err_word;
+}
 
-__device__ __forceinline__ void raise_err(unsigned code) { atomicCAS(&g_err, 0u, code); }
+__device__ __forceinline__ void raise_err(unsigned code) { atomicCAS(g_err_word, 0u, code); }
 
 __device__ __forceinline__ unsigned lane_id() { return __lane_id(); }
 // Values the whole wave shares, moved to scalar registers: branches on them become
@@ -775,22 +779,25 @@ __device__ __forceinline__ void rle_stream(const InCol &in, unsigned long long c
   }
 }
 
-// The chunks c = cb + w + kWaves * j < ce of an UNCOMPR (UNC) or packed column: full
-// blocks stream through direct window loads, kPre chunks ahead, with the block
-// directory of the next group of chunks loaded one group earlier (lane s holds chunk
-// s's entry); the remaining chunks take the direct path.
-template <bool UNC, class Body>
+// The chunks c = cb + w + kWaves * j < ce of an uncompressed (MODE 0), static BP
+// (MODE 1) or DynBP-family (MODE 2) column: full blocks stream through direct window
+// loads, kPre chunks ahead, with the block directory of the next group of chunks loaded
+// one group earlier (lane s holds chunk s's entry); the remaining chunks take the direct
+// path.  In the steady-state loop every load is issued on every path, so that the
+// compiler's wait counts let the kPre windows stay in flight: only the first group
+// needs the window it consumes.
+template <int MODE, class Body>
 __device__ __forceinline__ void stream_blocks(const InCol &in, unsigned long long cb, unsigned long long ce,
                                               unsigned w, unsigned lane, Body &&body) {
+  constexpr bool UNC = MODE == 0, DYN = MODE == 2;
   const unsigned long long first = cb + w;
   if (first >= ce) return;
   const unsigned long long nj = (ce - first + kWaves - 1) / kWaves;
-  const bool dyn = !UNC && (in.kind == DYN_BP || in.kind == DELTA_DYN_BP || in.kind == FOR_DYN_BP);
   unsigned long long cmain;  // chunks [0, cmain) are full packed blocks
   unsigned Wfix = 32;
   if (UNC) {
     cmain = in.n / kBlk;
-  } else if (in.kind == STATIC_BP) {
+  } else if (!DYN) {
     cmain = (in.W <= 32) ? in.n_main / kBlk : 0ull;
     Wfix = in.W;
   } else {
@@ -798,24 +805,24 @@ __device__ __forceinline__ void stream_blocks(const InCol &in, unsigned long lon
   }
   const unsigned long long njm = (first < cmain) ? min(nj, (cmain - first + kWaves - 1) / kWaves) : 0ull;
   if (njm > 0) {
-    // directory of group g (chunks 4g .. 4g+3 of this wave) in lanes 0..3
+    // directory of group g (chunks kPre*g .. kPre*g+3 of this wave) in lanes 0..3; every
+    // lane loads (lane & 3)'s entry, clamped to the wave's last full block
     auto dir_load = [&](unsigned long long g, unsigned &dw, unsigned &doff, unsigned &dbase) {
-      const unsigned long long j = kPre * g + lane;
-      dw = 0;
-      doff = 0;
-      dbase = 0;
-      if (dyn && lane < (unsigned)kPre && j < njm) {
+      if (DYN) {
+        const unsigned long long j = min(kPre * g + (lane & (unsigned)(kPre - 1)), njm - 1);
         const unsigned long long c = first + kWaves * j;
         dw = in.widths[c];
         doff = in.offsets[c];
         dbase = in.bases[c];
+      } else {
+        dw = doff = dbase = 0;
       }
     };
     // width and payload offset of chunk j, whose directory entry is in lane s of (dw, doff)
     auto locate = [&](unsigned long long j, unsigned s, unsigned dw, unsigned doff, unsigned &W,
                       unsigned long long &off) {
       const unsigned long long c = first + kWaves * j;
-      if (dyn) {
+      if (DYN) {
         W = __builtin_amdgcn_readlane(dw, s);
         off = __builtin_amdgcn_readlane(doff, s);
         if (W > 32 || off + 16ull * W > in.payload_cap) {  // a corrupt directory never reads out of bounds
@@ -832,64 +839,69 @@ __device__ __forceinline__ void stream_blocks(const InCol &in, unsigned long lon
     unsigned dwA, doA, dbA, dwB, doB, dbB;
     dir_load(0, dwA, doA, dbA);
     dir_load(1, dwB, doB, dbB);
+    auto issue = [&](const unsigned *blk, unsigned W, Win &r) {
+      if (UNC)
+        win_issue_unc(blk, lane, r);
+      else
+        win_issue9(blk, W, lane, r);
+    };
+    // the first windows are loaded on every path (slots past the wave's last full block
+    // load that block again and are never consumed), so that the wait counts inside the
+    // steady-state loop do not have to allow for a path with fewer loads in flight
     auto prime = [&](auto S) {
       constexpr int s = decltype(S)::value;
-      if ((unsigned long long)s < njm) {
-        unsigned W;
-        unsigned long long off;
-        locate(s, s, dwA, doA, W, off);
-        if (UNC)
-          win_issue_unc(in.payload + off, lane, win[s]);
-        else
-          win_issue9(in.payload + off, W, lane, win[s]);
-      }
+      const unsigned long long js = min((unsigned long long)s, njm - 1);
+      unsigned W;
+      unsigned long long off;
+      locate(js, (unsigned)js, dwA, doA, W, off);
+      issue(in.payload + off, W, win[s]);
     };
     prime(std::integral_constant<int, 0>{});
     prime(std::integral_constant<int, 1>{});
     prime(std::integral_constant<int, 2>{});
     prime(std::integral_constant<int, 3>{});
-    for (unsigned long long g = 0; kPre * g < njm; g++) {
+    // group g: one chunk per slot (the slot index is a compile-time constant so that the
+    // windows stay in registers).  CHECK false: every slot and its reload exist.
+    auto group = [&](unsigned long long g, auto CK) {
+      constexpr bool check = decltype(CK)::value;
       unsigned dwC, doC, dbC;
       dir_load(g + 2, dwC, doC, dbC);
-      // one chunk per slot; the slot index is a compile-time constant so that the
-      // windows stay in registers
       auto slot = [&](auto S) {
         constexpr int s = decltype(S)::value;
         const unsigned long long j = kPre * g + s;
-        if (j < njm) {
-          const unsigned long long c = first + kWaves * j;
-          unsigned W;
-          unsigned long long off;
-          locate(j, s, dwA, doA, W, off);
-          unsigned v[8];
-          if (UNC) {
+        if (check && j >= njm) return;
+        const unsigned long long c = first + kWaves * j;
+        unsigned W;
+        unsigned long long off;
+        locate(j, s, dwA, doA, W, off);
+        unsigned v[8];
+        if (UNC) {
 #pragma unroll
-            for (int i = 0; i < 8; i++) v[i] = win[s].x[i];
-          } else {
-            win_unpack_rt(W, win[s], lane, v);
-          }
-          if (in.kind == FOR_DYN_BP) {
-            const unsigned ref = __builtin_amdgcn_readlane(dbA, s);
-#pragma unroll
-            for (int i = 0; i < 8; i++) v[i] += ref;
-          } else if (in.kind == DELTA_DYN_BP) {
-#pragma unroll
-            for (int i = 1; i < 8; i++) v[i] += v[i - 1];
-            const unsigned excl = wave_excl_scan(v[7], lane) + __builtin_amdgcn_readlane(dbA, s);
-#pragma unroll
-            for (int i = 0; i < 8; i++) v[i] += excl;
-          }
-          if (j + kPre < njm) {
-            unsigned Wn;
-            unsigned long long offn;
-            locate(j + kPre, s, dwB, doB, Wn, offn);
-            if (UNC)
-              win_issue_unc(in.payload + offn, lane, win[s]);
-            else
-              win_issue9(in.payload + offn, Wn, lane, win[s]);
-          }
-          body(c, v);
+          for (int i = 0; i < 8; i++) v[i] = win[s].x[i];
+        } else {
+          win_unpack_rt(W, win[s], lane, v);
         }
+        if (DYN && in.kind == FOR_DYN_BP) {
+          const unsigned ref = __builtin_amdgcn_readlane(dbA, s);
+#pragma unroll
+          for (int i = 0; i < 8; i++) v[i] += ref;
+        } else if (DYN && in.kind == DELTA_DYN_BP) {
+#pragma unroll
+          for (int i = 1; i < 8; i++) v[i] += v[i - 1];
+          const unsigned excl = wave_excl_scan(v[7], lane) + __builtin_amdgcn_readlane(dbA, s);
+#pragma unroll
+          for (int i = 0; i < 8; i++) v[i] += excl;
+        }
+        if (!check || j + kPre < njm) {
+          unsigned Wn;
+          unsigned long long offn;
+          locate(j + kPre, s, dwB, doB, Wn, offn);
+          issue(in.payload + offn, Wn, win[s]);
+        }
+        // keep the reload ahead of the body: the scheduler would otherwise sink the
+        // loads of all four slots to the end of the group
+        __builtin_amdgcn_sched_barrier(0);
+        body(c, v);
       };
       static_assert(kPre == 4, "four slots below");
       slot(std::integral_constant<int, 0>{});
@@ -898,7 +910,12 @@ __device__ __forceinline__ void stream_blocks(const InCol &in, unsigned long lon
       slot(std::integral_constant<int, 3>{});
       dwA = dwB; doA = doB; dbA = dbB;
       dwB = dwC; doB = doC; dbB = dbC;
-    }
+    };
+    // groups g with kPre * (g + 2) <= njm have all four slots and all four reloads
+    const unsigned long long g_steady = njm / kPre >= 2 ? njm / kPre - 1 : 0ull;
+    unsigned long long g = 0;
+    for (; g < g_steady; g++) group(g, std::false_type{});
+    for (; kPre * g < njm; g++) group(g, std::true_type{});
   }
   unsigned long long rle_hint = 0;
   for (unsigned long long j = njm; j < nj; j++) {
@@ -922,9 +939,11 @@ __device__ __forceinline__ void stream_chunks(const InCol &in, unsigned long lon
   if (in.kind == RLE)
     rle_stream(in, cb, ce, w, lane, ring, body);
   else if (in.kind == UNCOMPR)
-    stream_blocks<true>(in, cb, ce, w, lane, body);
+    stream_blocks<0>(in, cb, ce, w, lane, body);
+  else if (in.kind == STATIC_BP)
+    stream_blocks<1>(in, cb, ce, w, lane, body);
   else
-    stream_blocks<false>(in, cb, ce, w, lane, body);
+    stream_blocks<2>(in, cb, ce, w, lane, body);
 }
 
 // Walk chunks cb + w, cb + w + kWaves, ... < ce with one chunk of look-ahead;

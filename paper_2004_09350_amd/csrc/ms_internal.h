@@ -19,7 +19,6 @@ constexpr int kSbpGroup = 32;       // static BP block size
 constexpr int kWG = 256;            // threads per workgroup
 constexpr int kWaves = kWG / 64;
 constexpr uint64_t kPayloadSlackWords = 1024;  // lane windows may read past a section's last word
-constexpr int kRingSlots = 4096;    // self-resetting "last workgroup" counters
 
 struct ColHdr {
   unsigned long long n;        // element count

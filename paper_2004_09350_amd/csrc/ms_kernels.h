@@ -44,6 +44,7 @@ struct EmitArgs {
   unsigned *partials;
 };
 
+hipError_t init_err_word();  // once, at library initialisation (the current device)
 unsigned read_and_clear_err(void *stream);
 void prof_enable(bool on);
 size_t prof_count();
@@ -55,6 +56,13 @@ hipError_t launch_finish(const FinishArgs &a, void *s);
 hipError_t launch_narrow(const FinishArgs &a, unsigned *tmp, unsigned G, void *s);
 hipError_t launch_set_hdr(ColHdr *h, unsigned long long n, unsigned long long runs, unsigned width, unsigned or_all,
                           unsigned or_main, unsigned sorted, void *s);
+// One translation unit per output kind holds each of these.
+template <unsigned OK>
+hipError_t launch_morph_ok(const ColView &in, const ColView &out, unsigned auto_w, unsigned G, unsigned *partials,
+                           void *s);
+template <unsigned OK>
+hipError_t launch_project_ok(const ColView &pos, const ColView &data, const ColView &out, unsigned auto_w, unsigned G,
+                             unsigned *partials, void *s);
 hipError_t launch_morph(const ColView &in, const ColView &out, unsigned auto_w, unsigned G, unsigned *partials,
                         void *s);
 hipError_t launch_decode(const ColView &in, unsigned *out, unsigned G, void *s);
@@ -70,10 +78,10 @@ hipError_t launch_group_sum(const ColView &g, const ColView &v, unsigned groups,
                             unsigned long long *partials, void *s);
 hipError_t launch_fill_u32(unsigned *p, unsigned long long n, unsigned v, void *s);
 hipError_t launch_fill_u64(unsigned long long *p, unsigned long long n, unsigned long long v, void *s);
-hipError_t launch_bitmap(const ColView &pos, unsigned long long domain, unsigned *bitmap, unsigned G, void *s);
-hipError_t launch_bitmap_checked(const ColView &pos, unsigned long long domain, unsigned *bitmap, unsigned *first,
-                                 unsigned *last, unsigned G, void *s);
-hipError_t launch_check_order(const unsigned *first, const unsigned *last, const ColView &pos, void *s);
+// Bitmap of a position list (fill it with zeros first).  ends: 4 words per chunk of the
+// list.  first/last (one word per chunk, or both NULL): check that the list increases.
+hipError_t launch_bitmap(const ColView &pos, unsigned long long domain, unsigned *bitmap, unsigned *ends,
+                         unsigned *first, unsigned *last, unsigned G, void *s);
 hipError_t launch_shrink_payload(const unsigned *src, const unsigned *old_off, const unsigned char *widths,
                                  const unsigned *new_off, unsigned *dst, unsigned long long nb, void *s);
 

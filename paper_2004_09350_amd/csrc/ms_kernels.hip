@@ -19,173 +19,10 @@
 #include <mutex>
 #include <vector>
 
-#include "ms_device.h"
-#include "ms_kernels.h"
+#include "ms_kcommon.h"
+#include "ms_launch.h"
 
 namespace ms {
-
-// Segment s of G over C chunks.
-__device__ __forceinline__ void segment(unsigned long long C, unsigned s, unsigned G, unsigned long long &cb,
-                                        unsigned long long &ce) {
-  cb = C * s / G;
-  ce = C * (s + 1) / G;
-}
-
-// Workgroup reductions (256 threads).
-__device__ __forceinline__ unsigned long long wg_add64(unsigned long long x, unsigned long long *sh) {
-  x = wave_add64(x);
-  const unsigned w = wave_id();
-  __syncthreads();
-  if (lane_id() == 0) sh[w] = x;
-  __syncthreads();
-  unsigned long long t = 0;
-  for (int i = 0; i < kWaves; i++) t += sh[i];
-  __syncthreads();
-  return t;
-}
-__device__ __forceinline__ unsigned wg_or(unsigned x, unsigned *sh) {
-  x = wave_or(x);
-  const unsigned w = wave_id();
-  __syncthreads();
-  if (lane_id() == 0) sh[w] = x;
-  __syncthreads();
-  unsigned t = 0;
-  for (int i = 0; i < kWaves; i++) t |= sh[i];
-  __syncthreads();
-  return t;
-}
-
-__device__ __forceinline__ unsigned valid_mask(unsigned long long idx0, unsigned long long n) {
-  return idx0 >= n ? 0u : (idx0 + 8 <= n ? 0xFFu : ((1u << (unsigned)(n - idx0)) - 1u));
-}
-
-// ---------------------------------------------------------------------------------------------
-// Output side.
-struct OutCol {
-  ColView c;
-  unsigned W;                       // static BP packing width (provisional for auto)
-  unsigned long long n;             // output element count
-  unsigned long long n_main;        // compressed main part
-  unsigned long long nb;            // full 512-blocks of the DynBP family
-};
-
-__device__ __forceinline__ OutCol make_out(const ColView &c, unsigned long long n, unsigned W) {
-  OutCol o;
-  o.c = c;
-  o.W = W;
-  o.n = n;
-  if (c.kind == STATIC_BP)
-    o.n_main = n & ~31ull;
-  else if (c.kind == DYN_BP || c.kind == DELTA_DYN_BP || c.kind == FOR_DYN_BP)
-    o.n_main = n & ~511ull;
-  else
-    o.n_main = n;
-  o.nb = o.n_main >> 9;
-  return o;
-}
-
-// Encode output block k (a full 512-block of a DynBP-family column) from the wave's
-// registers into its 512-word payload slot.
-__device__ __forceinline__ void encode_dyn_block(const OutCol &o, unsigned long long k, const unsigned (&v)[8],
-                                                 unsigned lane, unsigned *lds) {
-  unsigned r[8];
-  unsigned base = 0;
-  if (o.c.kind == DELTA_DYN_BP) {
-    const unsigned prev = lane_prev(v[7]);
-    base = lane_first(v[0]);
-    r[0] = lane ? v[0] - prev : 0u;
-#pragma unroll
-    for (int i = 1; i < 8; i++) r[i] = v[i] - v[i - 1];
-  } else if (o.c.kind == FOR_DYN_BP) {
-    unsigned m = v[0];
-#pragma unroll
-    for (int i = 1; i < 8; i++) m = min(m, v[i]);
-    base = wave_min(m);
-#pragma unroll
-    for (int i = 0; i < 8; i++) r[i] = v[i] - base;
-  } else {
-#pragma unroll
-    for (int i = 0; i < 8; i++) r[i] = v[i];
-  }
-  unsigned orr = 0;
-#pragma unroll
-  for (int i = 0; i < 8; i++) orr |= r[i];
-  const unsigned W = bw(wave_or(orr));
-  const unsigned long long off = k * (unsigned long long)kBlk;
-  if (lane == 0) {
-    o.c.widths[k] = (unsigned char)W;
-    o.c.offsets[k] = (unsigned)off;
-    o.c.bases[k] = base;
-  }
-  pack_block(W, r, lane, lds, o.c.payload + off);
-}
-
-// Encode output chunk c of a static BP column; values of the main part are packed at
-// o.W, values past n_main go to the remainder.
-__device__ __forceinline__ void encode_sbp_chunk(const OutCol &o, unsigned long long c, const unsigned (&v)[8],
-                                                 unsigned lane, unsigned *lds, unsigned &or_main) {
-  const unsigned long long idx0 = c * kBlk + 8ull * lane;
-  const bool in_main = idx0 + 8 <= o.n_main;
-  unsigned r[8];
-  unsigned orr = 0;
-#pragma unroll
-  for (int i = 0; i < 8; i++) {
-    r[i] = in_main ? v[i] : 0u;
-    orr |= r[i];
-  }
-  or_main |= orr;
-  if (o.W < 32 && (orr >> o.W) != 0) raise_err(E_TOO_WIDE);
-  if (c * kBlk < o.n_main) {
-#pragma unroll
-    for (int i = 0; i < 8; i++) r[i] &= lowmask(o.W);
-    pack_block(o.W, r, lane, lds, o.c.payload + c * 16ull * o.W);
-  }
-  if (!in_main) {
-#pragma unroll
-    for (int i = 0; i < 8; i++)
-      if (idx0 + i < o.n && idx0 + i >= o.n_main) o.c.rem[idx0 + i - o.n_main] = v[i];
-  }
-}
-
-// Write output chunk c of a count-known operator (output index = chunk position).
-// Handles UNCOMPR, STATIC_BP and the DynBP family (RLE outputs take the two-phase path).
-template <unsigned OK>
-__device__ __forceinline__ void write_chunk_known(const OutCol &o, unsigned long long c, const unsigned (&v)[8],
-                                                  unsigned lane, unsigned *lds, unsigned &or_all,
-                                                  unsigned &or_main) {
-  const unsigned long long idx0 = c * kBlk + 8ull * lane;
-#pragma unroll
-  for (int i = 0; i < 8; i++)
-    if (idx0 + i < o.n) or_all |= v[i];
-  switch (OK) {
-    case UNCOMPR: {
-      if (idx0 + 8 <= o.n) {
-        uint4 *p = reinterpret_cast<uint4 *>(o.c.payload + idx0);
-        p[0] = make_uint4(v[0], v[1], v[2], v[3]);
-        p[1] = make_uint4(v[4], v[5], v[6], v[7]);
-      } else {
-#pragma unroll
-        for (int i = 0; i < 8; i++)
-          if (idx0 + i < o.n) o.c.payload[idx0 + i] = v[i];
-      }
-      break;
-    }
-    case STATIC_BP: encode_sbp_chunk(o, c, v, lane, lds, or_main); break;
-    case DYN_BP:
-    case DELTA_DYN_BP:
-    case FOR_DYN_BP: {
-      if (c < o.nb) {
-        encode_dyn_block(o, c, v, lane, lds);
-      } else {
-#pragma unroll
-        for (int i = 0; i < 8; i++)
-          if (idx0 + i < o.n) o.c.rem[idx0 + i - o.n_main] = v[i];
-      }
-      break;
-    }
-    default: break;
-  }
-}
 
 // ---------------------------------------------------------------------------------------------
 // Finish: one workgroup after a column-producing kernel.  Reduces the per-workgroup
@@ -300,35 +137,6 @@ __global__ __launch_bounds__(kWG) void k_colstats(ColView inv, unsigned *partial
   }
 }
 
-// ---------------------------------------------------------------------------------------------
-// Morph (and encode): out = encode_fmt(decode(in)), count known.
-template <unsigned OK>
-__global__ __launch_bounds__(kWG) void k_morph(ColView inv, ColView outv, unsigned auto_w, unsigned *partials) {
-  __shared__ __attribute__((aligned(16))) unsigned ring[kWaves * kRing * kBlk];
-  __shared__ __attribute__((aligned(16))) unsigned lds_all[kWaves * kBlk];
-  __shared__ unsigned red[kWaves];
-  const InCol in = load_in(inv);
-  const unsigned lane = lane_id(), w = wave_id(), G = gridDim.x;
-  unsigned Wp = outv.width;
-  if (outv.kind == STATIC_BP && auto_w) Wp = bw(inv.hdr->or_all);
-  const OutCol o = make_out(outv, in.n, Wp);
-  if (blockIdx.x == 0 && threadIdx.x == 0) outv.hdr->sbp_width = Wp;
-  const unsigned long long C = (in.n + kBlk - 1) / kBlk;
-  unsigned long long cb, ce;
-  segment(C, blockIdx.x, G, cb, ce);
-  unsigned or_all = 0, or_main = 0;
-  unsigned *lds = lds_all + w * kBlk;
-  stream_chunks(in, cb, ce, w, lane, ring + w * kRing * kBlk, inv.hdr, [&](unsigned long long c, const unsigned (&v)[8]) {
-    write_chunk_known<OK>(o, c, v, lane, lds, or_all, or_main);
-  });
-  or_all = wg_or(or_all, red);
-  or_main = wg_or(or_main, red);
-  if (threadIdx.x == 0) {
-    partials[2 * blockIdx.x] = or_all;
-    partials[2 * blockIdx.x + 1] = or_main;
-  }
-}
-
 // Decode into a plain device array.
 __global__ __launch_bounds__(kWG) void k_decode(ColView inv, unsigned *__restrict__ out) {
   __shared__ __attribute__((aligned(16))) unsigned ring[kWaves * kRing * kBlk];
@@ -349,62 +157,6 @@ __global__ __launch_bounds__(kWG) void k_decode(ColView inv, unsigned *__restric
         if (idx0 + i < in.n) out[idx0 + i] = v[i];
     }
   });
-}
-
-// ---------------------------------------------------------------------------------------------
-// Project: out_j = data[pos_j].
-// Project: gather the data column at the positions streamed from posv and encode the
-// values into the output format.  RLE data columns have their own kernel (their gather
-// stages runs in LDS and needs its own registers).
-template <unsigned OK, bool DRLE>
-__device__ __forceinline__ void project_body(const ColView &posv, const ColView &datav, const ColView &outv,
-                                             unsigned auto_w, unsigned *partials) {
-  __shared__ __attribute__((aligned(16))) unsigned ring[kWaves * kRing * kBlk];
-  __shared__ __attribute__((aligned(16))) unsigned gblk[kWaves * kBlk];
-  __shared__ __attribute__((aligned(16))) unsigned lds_all[kWaves * kBlk];
-  __shared__ unsigned red[kWaves];
-  const InCol ip = load_in(posv);
-  const InCol id = load_in(datav);
-  const unsigned lane = lane_id(), w = threadIdx.x >> 6, G = gridDim.x;  // w kept in a VGPR: SGPRs run short here
-  unsigned Wp = outv.width;
-  if (outv.kind == STATIC_BP && auto_w) Wp = bw(datav.hdr->or_all);
-  const OutCol o = make_out(outv, ip.n, Wp);
-  if (blockIdx.x == 0 && threadIdx.x == 0) outv.hdr->sbp_width = Wp;
-  const unsigned long long C = (ip.n + kBlk - 1) / kBlk;
-  unsigned long long cb, ce;
-  segment(C, blockIdx.x, G, cb, ce);
-  unsigned or_all = 0, or_main = 0;
-  unsigned *lds = lds_all + w * kBlk;
-  bool bad = false;
-  stream_chunks(ip, cb, ce, w, lane, ring + w * kRing * kBlk, posv.hdr, [&](unsigned long long c, const unsigned (&pv)[8]) {
-    unsigned v[8];
-#pragma unroll
-    for (int i = 0; i < 8; i++) v[i] = pv[i];
-    const unsigned valid = valid_mask(c * kBlk + 8ull * lane, ip.n);
-    if constexpr (DRLE)
-      gather8_rle(id, v, valid, bad, lane, gblk + w * kBlk, lds);
-    else
-      gather8<false>(id, v, valid, bad, lane, gblk + w * kBlk, lds);
-    write_chunk_known<OK>(o, c, v, lane, lds, or_all, or_main);
-  });
-  if (bad) raise_err(E_RANGE);
-  or_all = wg_or(or_all, red);
-  or_main = wg_or(or_main, red);
-  if (threadIdx.x == 0) {
-    partials[2 * blockIdx.x] = or_all;
-    partials[2 * blockIdx.x + 1] = or_main;
-  }
-}
-
-template <unsigned OK>
-__global__ __launch_bounds__(kWG, 3) void k_project(ColView posv, ColView datav, ColView outv, unsigned auto_w,
-                                                 unsigned *partials) {
-  project_body<OK, false>(posv, datav, outv, auto_w, partials);
-}
-template <unsigned OK>
-__global__ __launch_bounds__(kWG) void k_project_rle(ColView posv, ColView datav, ColView outv, unsigned auto_w,
-                                                     unsigned *partials) {
-  project_body<OK, true>(posv, datav, outv, auto_w, partials);
 }
 
 // ---------------------------------------------------------------------------------------------
@@ -590,6 +342,14 @@ __global__ __launch_bounds__(kWG) void k_pred(PredArgs a) {
   const unsigned *bitmap = a.bitmap;
   unsigned char *bitmask = a.bitmask;
   unsigned *chunk_first = a.chunk_first, *chunk_last = a.chunk_last;
+  // A semi-join bitmap that fits the workgroup's LDS (its ring, which only RLE input
+  // uses) is probed there instead of through the caches.
+  const bool lds_bm = mode == 1 && in.kind != RLE && domain <= 32ull * kWaves * kRing * kBlk;
+  if (lds_bm) {
+    const unsigned nw = (unsigned)((domain + 31) / 32);
+    for (unsigned t = threadIdx.x; t < nw; t += kWG) ring[t] = bitmap[t];
+    __syncthreads();
+  }
   stream_chunks(in, cb, ce, w, lane, ring + w * kRing * kBlk, a.in.hdr, [&](unsigned long long c, const unsigned (&v)[8]) {
     const unsigned long long idx0 = c * kBlk + 8ull * lane;
     const unsigned valid = valid_mask(idx0, in.n);
@@ -598,6 +358,12 @@ __global__ __launch_bounds__(kWG) void k_pred(PredArgs a) {
 #pragma unroll
       for (int i = 0; i < 8; i++)
         if (((v[i] - lo) <= span) != neg) mask |= 1u << i;
+    } else if (mode == 1 && lds_bm) {
+#pragma unroll
+      for (int i = 0; i < 8; i++) {
+        const unsigned x = v[i];
+        if ((unsigned long long)x < domain && ((ring[x >> 5] >> (x & 31)) & 1u)) mask |= 1u << i;
+      }
     } else {
 #pragma unroll
       for (int i = 0; i < 8; i++) {
@@ -738,9 +504,15 @@ __global__ __launch_bounds__(kWG) void k_emit(EmitArgs a) {
   // this wave's chunks and its output count
   const unsigned long long nseg = ce - cb;
   const unsigned long long cw0 = cb + nseg * w / kWaves, cw1 = cb + nseg * (w + 1) / kWaves;
+  // The bitmask is a bitmap in row order (byte b covers rows 8b .. 8b+7), so lane l's
+  // eight bytes at chunk c cover rows 512c + 64l .. +63: eight chunks per wave load.
+  const unsigned long long *bm64 = reinterpret_cast<const unsigned long long *>(a.bitmask);
   unsigned cnt = 0;
-#pragma unroll 4
-  for (unsigned long long c = cw0; c < cw1; c++) cnt += __popc((unsigned)a.bitmask[c * 64 + lane]);
+  {
+    unsigned long long c = cw0;
+    for (; c + 8 <= cw1; c += 8) cnt += __popcll(bm64[c * 8 + lane]);
+    for (; c < cw1; c++) cnt += __popc((unsigned)a.bitmask[c * 64 + lane]);
+  }
   cnt = wave_add(cnt);
   if (lane == 0) s_wcnt[w] = cnt;
   __syncthreads();
@@ -762,34 +534,24 @@ __global__ __launch_bounds__(kWG) void k_emit(EmitArgs a) {
   unsigned *lds = lds_all + w * kBlk;
   unsigned g_done = A32;          // owned outputs below g_done are packed
   unsigned g = (unsigned)Ow;      // next output index of this wave
-  const unsigned char *bm = a.bitmask + lane;
-  // bitmask bytes four chunks ahead
-  unsigned q0 = (cw0 < cw1) ? bm[cw0 * 64] : 0u;
-  unsigned q1 = (cw0 + 1 < cw1) ? bm[(cw0 + 1) * 64] : 0u;
-  unsigned q2 = (cw0 + 2 < cw1) ? bm[(cw0 + 2) * 64] : 0u;
-  unsigned q3 = (cw0 + 3 < cw1) ? bm[(cw0 + 3) * 64] : 0u;
-  for (unsigned long long c = cw0; c < cw1; c++) {
-    unsigned m = q0;
-    q0 = q1;
-    q1 = q2;
-    q2 = q3;
-    q3 = (c + 4 < cw1) ? bm[(c + 4) * 64] : 0u;
-    unsigned v[8];
-    if (a.emit_values) decode_chunk(in, c, lane, v);
-    const unsigned cntl = __popc(m);
+
+  // Emit one unit: lane bits m (bit i = value i, which is pos0 + i, or v[i] when the
+  // chunk's values are emitted) in row order across the lanes; at most 512 outputs.
+  auto emit_unit = [&](unsigned long long m, unsigned pos0, const unsigned (&v)[8], bool vals) {
+    auto value = [&](unsigned i) { return vals ? select8(v, i) : pos0 + i; };
+    const unsigned cntl = __popcll(m);
     const unsigned off = wave_excl_scan(cntl, lane);
     const unsigned tot = lane_last(off + cntl);
-    const unsigned idx0 = (unsigned)(c * kBlk) + 8u * lane;
-    unsigned gl = g + off;   // this lane's first output
+    unsigned gl = g + off;  // this lane's first output
     const unsigned gend = gl + cntl;
     if (blocky) {
       if (cap_ok && gend <= n_main_o && gl >= A32 && gend <= B32) {
         // owned, staged block elements: append to the ring
         unsigned k = gl - A32, orl = 0;
         while (m) {
-          const unsigned i = __ffs(m) - 1;
+          const unsigned i = __ffsll(m) - 1;
           m &= m - 1;
-          const unsigned val = a.emit_values ? select8(v, i) : idx0 + i;
+          const unsigned val = value(i);
           ring[k & (kEmitRing - 1)] = val;
           orl |= val;
           k++;
@@ -797,12 +559,12 @@ __global__ __launch_bounds__(kWG) void k_emit(EmitArgs a) {
         or_main |= orl;
       }
     } else if (cap_ok && tot > 0) {
-      // uncompressed and RLE outputs: stage the chunk's outputs, then coalesced stores
+      // uncompressed and RLE outputs: stage the unit's outputs, then coalesced stores
       unsigned k = off, orl = 0;
       while (m) {
-        const unsigned i = __ffs(m) - 1;
+        const unsigned i = __ffsll(m) - 1;
         m &= m - 1;
-        const unsigned val = a.emit_values ? select8(v, i) : idx0 + i;
+        const unsigned val = value(i);
         lds[k++] = val;
         orl |= val;
       }
@@ -819,9 +581,9 @@ __global__ __launch_bounds__(kWG) void k_emit(EmitArgs a) {
       wave_sync();
     }
     while (m) {  // elements outside the fast paths
-      const unsigned i = __ffs(m) - 1;
+      const unsigned i = __ffsll(m) - 1;
       m &= m - 1;
-      const unsigned val = a.emit_values ? select8(v, i) : idx0 + i;
+      const unsigned val = value(i);
       if (gl < n_main_o) or_main |= val;
       if (gl >= cap32) {
         raise_err(E_INVALID);
@@ -864,6 +626,52 @@ __global__ __launch_bounds__(kWG) void k_emit(EmitArgs a) {
         g_done = bend;
       }
       wave_sync();
+    }
+  };
+
+  const unsigned char *bm = a.bitmask + lane;
+  const unsigned novals[8] = {0, 0, 0, 0, 0, 0, 0, 0};
+  if (!a.emit_values) {
+    // positions: eight chunks at a time while they hold at most one block of outputs,
+    // else chunk by chunk
+    unsigned long long c = cw0;
+    unsigned long long mnext = (c + 8 <= cw1) ? bm64[c * 8 + lane] : 0ull;
+    for (; c + 8 <= cw1; c += 8) {
+      const unsigned long long m = mnext;
+      mnext = (c + 16 <= cw1) ? bm64[(c + 8) * 8 + lane] : 0ull;
+      const unsigned pc = __popcll(m);
+      const unsigned t_lo = wave_add(lane < 32 ? pc : 0u), t_hi = wave_add(lane < 32 ? 0u : pc);
+      if (t_lo + t_hi == 0) continue;
+      const unsigned pos0 = (unsigned)(c * kBlk) + 64u * lane;
+      if (t_lo + t_hi <= kBlk) {
+        emit_unit(m, pos0, novals, false);
+        continue;
+      }
+      // denser: the two halves of four chunks (lanes 0..31, 32..63), each alone if it
+      // holds at most a block of outputs, else chunk by chunk with one byte per lane
+      // (byte lane & 7 of lane 8k + lane / 8's word)
+      for (unsigned h = 0; h < 2; h++) {
+        const unsigned th = h ? t_hi : t_lo;
+        if (th == 0) continue;
+        if (th <= kBlk) {
+          emit_unit((lane >> 5) == h ? m : 0ull, pos0, novals, false);
+          continue;
+        }
+        for (unsigned k = 4 * h; k < 4 * h + 4; k++) {
+          const int src = (int)(8u * k + (lane >> 3));
+          const unsigned lo = __shfl((unsigned)m, src), hi = __shfl((unsigned)(m >> 32), src);
+          const unsigned sh = 8u * (lane & 7u);
+          const unsigned mb = (unsigned)(((((unsigned long long)hi) << 32) | lo) >> sh) & 0xFFu;
+          emit_unit(mb, (unsigned)((c + k) * kBlk) + 8u * lane, novals, false);
+        }
+      }
+    }
+    for (; c < cw1; c++) emit_unit(bm[c * 64], (unsigned)(c * kBlk) + 8u * lane, novals, false);
+  } else {
+    for (unsigned long long c = cw0; c < cw1; c++) {
+      unsigned v[8];
+      decode_chunk(in, c, lane, v);
+      emit_unit(bm[c * 64], (unsigned)(c * kBlk) + 8u * lane, v, true);
     }
   }
   or_main = wg_or(or_main, redo);
@@ -1004,17 +812,21 @@ __global__ __launch_bounds__(kWG) void k_group_sum(ColView gv, ColView vv, unsig
   }
 }
 
-__global__ void k_group_sum_finish(const unsigned long long *partials, unsigned G, unsigned G_groups, unsigned lds,
-                                   unsigned long long *out) {
-  const unsigned q = blockIdx.x * blockDim.x + threadIdx.x;
-  if (q >= G_groups) return;
-  if (!lds) {
-    out[q] = partials[q];
+// One workgroup per group: the sum of that group's per-workgroup partials (LDS
+// histograms), else a copy of the global sums.
+__global__ __launch_bounds__(kWG) void k_group_sum_finish(const unsigned long long *partials, unsigned G,
+                                                          unsigned G_groups, unsigned lds, unsigned long long *out) {
+  __shared__ unsigned long long red[kWaves];
+  const unsigned q = blockIdx.x;
+  if (!lds) {  // the partials are the sums themselves: one group per thread
+    const unsigned long long i = (unsigned long long)blockIdx.x * kWG + threadIdx.x;
+    if (i < G_groups) out[i] = partials[i];
     return;
   }
   unsigned long long t = 0;
-  for (unsigned b = 0; b < G; b++) t += partials[(unsigned long long)b * G_groups + q];
-  out[q] = t;
+  for (unsigned b = threadIdx.x; b < G; b += kWG) t += partials[(unsigned long long)b * G_groups + q];
+  t = wg_add64(t, red);
+  if (threadIdx.x == 0) out[q] = t;
 }
 
 __global__ void k_set_hdr(ColHdr *h, unsigned long long n, unsigned long long runs, unsigned width,
@@ -1043,9 +855,9 @@ __global__ void k_fill_u64(unsigned long long *p, unsigned long long n, unsigned
 
 // Bitmap from positions: bit p of the (zeroed) bitmap for every position p.  With
 // chunk_first/chunk_last set it also checks that the positions strictly increase
-// (inside chunks here, across chunk ends in k_check_order).
+// (inside chunks here, across chunk ends in k_bitmap_ends).
 __global__ __launch_bounds__(kWG) void k_bitmap(ColView posv, unsigned long long domain, unsigned *bitmap,
-                                                unsigned *chunk_first, unsigned *chunk_last) {
+                                                unsigned *chunk_first, unsigned *chunk_last, unsigned *ends) {
   __shared__ __attribute__((aligned(16))) unsigned ring[kWaves * kRing * kBlk];
   const InCol in = load_in(posv);
   const unsigned lane = lane_id(), w = wave_id(), G = gridDim.x;
@@ -1053,6 +865,8 @@ __global__ __launch_bounds__(kWG) void k_bitmap(ColView posv, unsigned long long
   unsigned long long cb, ce;
   segment(C, blockIdx.x, G, cb, ce);
   bool bad_range = false, bad_order = false;
+  // strictly increasing: recorded by the producer, or checked here (a failed check is an error)
+  const bool increasing = uni(posv.hdr->sorted) != 0 || chunk_first != nullptr;
   stream_chunks(in, cb, ce, w, lane, ring + w * kRing * kBlk, posv.hdr, [&](unsigned long long c, const unsigned (&v)[8]) {
     const unsigned long long idx0 = c * kBlk + 8ull * lane;
     const unsigned valid = valid_mask(idx0, in.n);
@@ -1067,37 +881,86 @@ __global__ __launch_bounds__(kWG) void k_bitmap(ColView posv, unsigned long long
       if (lane == 0) chunk_first[c] = v[0];
       if (idx0 <= last_idx && last_idx < idx0 + 8) chunk_last[c] = select8(v, (unsigned)(last_idx - idx0));
     }
-    // combine bits that land in the same word before the atomic
-    unsigned cur_word = 0xFFFFFFFFu, bits = 0;
+    // A sorted list's chunk covers the bitmap words [w0, w1]: no other chunk has a
+    // position inside (w0, w1), so when the span is short the words are assembled in
+    // LDS (the wave's ring, unused outside RLE input) and stored plainly.  The two end
+    // words, which neighbouring chunks may share, go to ends[4c .. 4c+3] as (word, bits)
+    // pairs that k_bitmap_ends ORs in, keeping atomics out of this kernel.
+    const unsigned nv = (unsigned)min((unsigned long long)kBlk, in.n - c * kBlk);  // valid values in the chunk
+    const unsigned last_lane = (nv - 1) >> 3;
+    const unsigned p_first = lane_first(v[0]);
+    const unsigned p_last = __builtin_amdgcn_readlane(select8(v, (nv - 1) & 7u), last_lane);
+    const unsigned w0 = p_first >> 5, w1 = p_last >> 5;
+    const bool staged = increasing && in.kind != RLE && p_first <= p_last && (unsigned long long)p_last < domain &&
+                        w1 - w0 < (unsigned)(kRing * kBlk);
+    if (staged) {
+      unsigned *st = ring + w * kRing * kBlk;
+      const unsigned span = w1 - w0 + 1;
+      for (unsigned t = lane; t < span; t += 64) st[t] = 0u;
+      wave_sync();
 #pragma unroll
-    for (int i = 0; i < 8; i++) {
-      if ((valid >> i) & 1u) {
+      for (int i = 0; i < 8; i++) {
         const unsigned p = v[i];
-        if ((unsigned long long)p >= domain) {
+        if (((valid >> i) & 1u) && p >= p_first && p <= p_last && (unsigned long long)p < domain)
+          atomicOr(&st[(p >> 5) - w0], 1u << (p & 31));
+        else if (((valid >> i) & 1u) && (unsigned long long)p >= domain)
           bad_range = true;
-        } else {
-          const unsigned wd = p >> 5;
-          if (wd != cur_word) {
-            if (bits) atomicOr(&bitmap[cur_word], bits);
-            cur_word = wd;
-            bits = 0;
+      }
+      wave_sync();
+      for (unsigned t = lane; t < span; t += 64) {
+        const unsigned x = st[t];
+        if (t == 0) {
+          ends[4 * c] = w0;
+          ends[4 * c + 1] = x;
+        }
+        if (t == span - 1) {
+          ends[4 * c + 2] = w1;
+          ends[4 * c + 3] = span > 1 ? x : 0u;
+        }
+        if (t > 0 && t < span - 1) bitmap[w0 + t] = x;
+      }
+      wave_sync();
+    } else {
+      // combine bits that land in the same word before the atomic
+      unsigned cur_word = 0xFFFFFFFFu, bits = 0;
+#pragma unroll
+      for (int i = 0; i < 8; i++) {
+        if ((valid >> i) & 1u) {
+          const unsigned p = v[i];
+          if ((unsigned long long)p >= domain) {
+            bad_range = true;
+          } else {
+            const unsigned wd = p >> 5;
+            if (wd != cur_word) {
+              if (bits) atomicOr(&bitmap[cur_word], bits);
+              cur_word = wd;
+              bits = 0;
+            }
+            bits |= 1u << (p & 31);
           }
-          bits |= 1u << (p & 31);
         }
       }
+      if (bits) atomicOr(&bitmap[cur_word], bits);
+      if (lane < 4) ends[4 * c + lane] = 0u;  // nothing left for k_bitmap_ends
     }
-    if (bits) atomicOr(&bitmap[cur_word], bits);
   });
   if (bad_range) raise_err(E_RANGE);
   if (bad_order) raise_err(E_NOT_SORTED);
 }
 
-__global__ void k_check_order(const unsigned *chunk_first, const unsigned *chunk_last, ColView posv) {
+// The end words of every chunk of k_bitmap (and, for a list that must increase, the
+// order across chunk boundaries).
+__global__ void k_bitmap_ends(const unsigned *ends, const unsigned *chunk_first, const unsigned *chunk_last,
+                              unsigned *bitmap, ColView posv) {
   const unsigned long long n = posv.hdr->n;
   const unsigned long long C = (n + kBlk - 1) / kBlk;
-  for (unsigned long long c = 1 + (unsigned long long)blockIdx.x * blockDim.x + threadIdx.x; c < C;
-       c += (unsigned long long)gridDim.x * blockDim.x)
-    if (chunk_first[c] <= chunk_last[c - 1]) raise_err(E_NOT_SORTED);
+  for (unsigned long long c = (unsigned long long)blockIdx.x * blockDim.x + threadIdx.x; c < C;
+       c += (unsigned long long)gridDim.x * blockDim.x) {
+    if (chunk_first && c > 0 && chunk_first[c] <= chunk_last[c - 1]) raise_err(E_NOT_SORTED);
+    const uint4 e = reinterpret_cast<const uint4 *>(ends)[c];
+    if (e.y) atomicOr(&bitmap[e.x], e.y);
+    if (e.w) atomicOr(&bitmap[e.z], e.w);
+  }
 }
 
 // Canonical copy of a DynBP-family payload: block k moves from old_off[k] to new_off[k].
@@ -1140,25 +1003,40 @@ hipEvent_t ev_get() {
   return e;
 }
 
-struct ProfScope {
-  ProfRec r{nullptr, nullptr, nullptr};
-  hipStream_t s;
-  ProfScope(const char *name, void *stream) : s(reinterpret_cast<hipStream_t>(stream)) {
-    if (!g_prof_on || t_prof_suspended) return;
-    std::lock_guard<std::mutex> g(g_prof_mu);
-    r.name = name;
-    r.a = ev_get();
-    r.b = ev_get();
-    if (r.a) (void)hipEventRecord(r.a, s);
-  }
-  ~ProfScope() {
-    if (!r.name) return;
-    if (r.b) (void)hipEventRecord(r.b, s);
-    std::lock_guard<std::mutex> g(g_prof_mu);
-    g_prof.push_back(r);
-  }
-};
+std::vector<ErrWordSetter> &err_word_setters() {
+  static std::vector<ErrWordSetter> r;
+  return r;
+}
+unsigned *g_err_dev = nullptr;
 }  // namespace
+
+int prof_begin(const char *name, void *stream) {
+  if (!g_prof_on || t_prof_suspended) return -1;
+  std::lock_guard<std::mutex> g(g_prof_mu);
+  ProfRec r{name, ev_get(), ev_get()};
+  if (r.a) (void)hipEventRecord(r.a, S(stream));
+  g_prof.push_back(r);
+  return (int)g_prof.size() - 1;
+}
+void prof_end(int rec, void *stream) {
+  std::lock_guard<std::mutex> g(g_prof_mu);
+  if (rec >= 0 && (size_t)rec < g_prof.size() && g_prof[rec].b) (void)hipEventRecord(g_prof[rec].b, S(stream));
+}
+
+// Registration runs in static initialisers of the kernel units, before any call.
+void register_err_word_setter(ErrWordSetter f) { err_word_setters().push_back(f); }
+
+hipError_t init_err_word() {
+  if (!g_err_dev) {
+    hipError_t e = hipMalloc(&g_err_dev, sizeof(unsigned));
+    if (e != hipSuccess) return e;
+    e = hipMemset(g_err_dev, 0, sizeof(unsigned));
+    if (e != hipSuccess) return e;
+  }
+  for (ErrWordSetter f : err_word_setters())
+    if (!f(g_err_dev)) return hipErrorInvalidSymbol;
+  return hipDeviceSynchronize();
+}
 
 void prof_enable(bool on) { g_prof_on = on; }
 void prof_suspend(bool on) { t_prof_suspended = on; }
@@ -1186,22 +1064,16 @@ void prof_reset() {
 
 // ---------------------------------------------------------------------------------------------
 // Host-side launchers.
-static hipStream_t S(void *s) { return reinterpret_cast<hipStream_t>(s); }
 
 unsigned read_and_clear_err(void *stream) {
-  unsigned e = 0, z = 0;
-  if (hipMemcpyFromSymbolAsync(&e, HIP_SYMBOL(g_err), sizeof(e), 0, hipMemcpyDeviceToHost, S(stream)) != hipSuccess ||
-      hipMemcpyToSymbolAsync(HIP_SYMBOL(g_err), &z, sizeof(z), 0, hipMemcpyHostToDevice, S(stream)) != hipSuccess ||
+  unsigned e = 0;
+  if (!g_err_dev || hipMemcpyAsync(&e, g_err_dev, sizeof(e), hipMemcpyDeviceToHost, S(stream)) != hipSuccess ||
+      hipMemsetAsync(g_err_dev, 0, sizeof(unsigned), S(stream)) != hipSuccess ||
       hipStreamSynchronize(S(stream)) != hipSuccess)
     return E_INVALID;
   return e;
 }
 
-#define MS_LAUNCH(kern, grid, block, stream, ...)                                 \
-  do {                                                                            \
-    ProfScope ps_(#kern, stream);                                                 \
-    hipLaunchKernelGGL(kern, dim3(grid), dim3(block), 0, S(stream), __VA_ARGS__); \
-  } while (0)
 
 hipError_t launch_set_hdr(ColHdr *h, unsigned long long n, unsigned long long runs, unsigned width, unsigned or_all,
                           unsigned or_main, unsigned sorted, void *s) {
@@ -1240,10 +1112,9 @@ hipError_t launch_colstats(const ColView &in, unsigned G, unsigned *partials, vo
 
 hipError_t launch_morph(const ColView &in, const ColView &out, unsigned auto_w, unsigned G, unsigned *partials,
                         void *s) {
-#define MS_L(K) MS_LAUNCH(k_morph<K>, G, kWG, s, in, out, auto_w, partials)
+#define MS_L(K) return launch_morph_ok<K>(in, out, auto_w, G, partials, s)
   MS_BY_OUT_KIND(out.kind, MS_L)
 #undef MS_L
-  return hipGetLastError();
 }
 hipError_t launch_decode(const ColView &in, unsigned *out, unsigned G, void *s) {
   MS_LAUNCH(k_decode, G, kWG, s, in, out);
@@ -1266,16 +1137,9 @@ hipError_t launch_rle(unsigned mode, const ColView &a, const ColView &b, const C
 }
 hipError_t launch_project(const ColView &pos, const ColView &data, const ColView &out, unsigned auto_w, unsigned G,
                           unsigned *partials, void *s) {
-  if (data.kind == RLE) {
-#define MS_L(K) MS_LAUNCH(k_project_rle<K>, G, kWG, s, pos, data, out, auto_w, partials)
-    MS_BY_OUT_KIND(out.kind, MS_L)
+#define MS_L(K) return launch_project_ok<K>(pos, data, out, auto_w, G, partials, s)
+  MS_BY_OUT_KIND(out.kind, MS_L)
 #undef MS_L
-  } else {
-#define MS_L(K) MS_LAUNCH(k_project<K>, G, kWG, s, pos, data, out, auto_w, partials)
-    MS_BY_OUT_KIND(out.kind, MS_L)
-#undef MS_L
-  }
-  return hipGetLastError();
 }
 hipError_t launch_pred(const PredArgs &a, unsigned G, void *s) {
   if (a.mode == 0)
@@ -1302,7 +1166,7 @@ hipError_t launch_group_sum(const ColView &g, const ColView &v, unsigned groups,
                             unsigned long long *partials, void *s) {
   MS_LAUNCH(k_group_sum, G, kWG, s, g, v, groups, partials);
   const unsigned lds = groups <= kMaxLdsGroups ? 1u : 0u;
-  MS_LAUNCH(k_group_sum_finish, (groups + 255) / 256, 256, s, partials, G, groups, lds, out);
+  if (groups > 0) MS_LAUNCH(k_group_sum_finish, lds ? groups : (groups + kWG - 1) / kWG, kWG, s, partials, G, groups, lds, out);
   return hipGetLastError();
 }
 hipError_t launch_fill_u32(unsigned *p, unsigned long long n, unsigned v, void *s) {
@@ -1317,17 +1181,10 @@ hipError_t launch_fill_u64(unsigned long long *p, unsigned long long n, unsigned
   MS_LAUNCH(k_fill_u64, blocks, 256, s, p, n, v);
   return hipGetLastError();
 }
-hipError_t launch_bitmap(const ColView &pos, unsigned long long domain, unsigned *bitmap, unsigned G, void *s) {
-  MS_LAUNCH(k_bitmap, G, kWG, s, pos, domain, bitmap, (unsigned *)nullptr, (unsigned *)nullptr);
-  return hipGetLastError();
-}
-hipError_t launch_bitmap_checked(const ColView &pos, unsigned long long domain, unsigned *bitmap, unsigned *first,
-                                 unsigned *last, unsigned G, void *s) {
-  MS_LAUNCH(k_bitmap, G, kWG, s, pos, domain, bitmap, first, last);
-  return hipGetLastError();
-}
-hipError_t launch_check_order(const unsigned *first, const unsigned *last, const ColView &pos, void *s) {
-  MS_LAUNCH(k_check_order, 256, 256, s, first, last, pos);
+hipError_t launch_bitmap(const ColView &pos, unsigned long long domain, unsigned *bitmap, unsigned *ends,
+                         unsigned *first, unsigned *last, unsigned G, void *s) {
+  MS_LAUNCH(k_bitmap, G, kWG, s, pos, domain, bitmap, first, last, ends);
+  MS_LAUNCH(k_bitmap_ends, 512, 256, s, ends, first, last, bitmap, pos);
   return hipGetLastError();
 }
 hipError_t launch_shrink_payload(const unsigned *src, const unsigned *old_off, const unsigned char *widths,

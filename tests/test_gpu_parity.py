@@ -180,6 +180,25 @@ def test_semijoin_and_bitmap(M):
     del rng
 
 
+@pytest.mark.parametrize("D", [2_500, 200_000, 262_144])
+def test_semijoin_small_domains(M, D):
+    """Bitmaps built from select outputs (recorded as increasing), domains that fit the
+    probe's LDS, and keys in and out of the domain."""
+    dim = datagen.uniform_range(61, D, 0, 100)
+    s = O.select(dim, O.LT, 13)
+    keys = datagen.uniform_range(62, 2_000_003, 0, D + D // 50)
+    bm_want = O.bitmap_from_positions(s, D)
+    want = O.semijoin(keys, bm_want, D)
+    sc = M.select(M.encode(dim, fmt_of(M, O.STATIC_BP)), M.LT, 13, 0, fmt_of(M, O.DELTA_DYN_BP))
+    bm = M.bitmap_from_positions(sc, D)
+    np.testing.assert_array_equal(M.u32(bm)[: bm_want.size], bm_want)
+    for kk in (O.STATIC_BP, O.UNCOMPR, O.DYN_BP, O.RLE):
+        kc = M.encode(keys, fmt_of(M, kk))
+        for kout in (O.UNCOMPR, O.DELTA_DYN_BP, O.RLE):
+            assert_column(M.semijoin(kc, bm, D, fmt_of(M, kout)), want, kout)
+    M.sync()
+
+
 def test_intersect(M):
     rng = np.random.default_rng(6)
     N = 2_000_000
