@@ -414,7 +414,7 @@ ms_status ms_morph(const ms_column *in, ms_format fmt, void *stream, ms_column *
   if (st != MS_OK) return st;
   Scratch sc(stream);
   unsigned *partials = sc.get<unsigned>(2 * G);
-  unsigned *seg = (fmt.kind == MS_RLE) ? sc.get<unsigned>(G) : nullptr;
+  unsigned *seg = (fmt.kind == MS_RLE) ? sc.get<unsigned>(kWaves * G) : nullptr;  // runs per wave
   unsigned *narrow_tmp = (fmt.kind == MS_STATIC_BP && auto_w) ? sc.get<unsigned>(n_cap + kPayloadSlackWords) : nullptr;
   if (!sc.ok) {
     free_column(*out);
@@ -774,7 +774,7 @@ ms_status ms_project(const ms_column *data, const ms_column *pos, ms_format fmt,
   if (st != MS_OK) return st;
   Scratch sc(stream);
   unsigned *partials = sc.get<unsigned>(2 * G);
-  unsigned *seg = (fmt.kind == MS_RLE) ? sc.get<unsigned>(G) : nullptr;
+  unsigned *seg = (fmt.kind == MS_RLE) ? sc.get<unsigned>(kWaves * G) : nullptr;  // runs per wave
   unsigned *narrow_tmp = (fmt.kind == MS_STATIC_BP && auto_w) ? sc.get<unsigned>(n_cap + kPayloadSlackWords) : nullptr;
   if (!sc.ok) {
     free_column(*out);

@@ -671,8 +671,7 @@ __device__ __forceinline__ void win_unpack_rt(unsigned W, const Win &r, unsigned
   }
 }
 
-// RLE input walked run by run.  Wave w takes a contiguous quarter of the chunks
-// [cb, ce).  The runs [r, whi) it needs are staged in a ring of kRunCap (start, value)
+// RLE input walked run by run over the chunks [c_begin, c_end).  The runs [r, whi) it needs are staged in a ring of kRunCap (start, value)
 // pairs in its LDS (run q in slot q mod kRunCap); each lane finds its 8 values there.
 // While a chunk's body runs, the runs the next chunks will need are already being
 // loaded (coalesced) into registers, so sparse and dense runs both stream without a
@@ -684,10 +683,8 @@ static_assert(2 * kRunCap <= kRing * kBlk, "run staging fits the wave's ring buf
 static_assert((kRunCap & kRunMask) == 0, "ring size is a power of two");
 
 template <class Body>
-__device__ __forceinline__ void rle_stream(const InCol &in, unsigned long long cb, unsigned long long ce, unsigned w,
+__device__ __forceinline__ void rle_stream(const InCol &in, unsigned long long c_begin, unsigned long long c_end,
                                            unsigned lane, unsigned *lds, Body &&body) {
-  const unsigned long long nseg = ce - cb;
-  const unsigned long long c_begin = cb + nseg * w / kWaves, c_end = cb + nseg * (w + 1) / kWaves;
   if (c_begin >= c_end) return;
   unsigned *S = lds, *V = lds + kRunCap;
   unsigned long long r = (in.runs > 0) ? rle_find_wave(in, c_begin * kBlk, lane, 0) : 0ull;
@@ -779,20 +776,18 @@ __device__ __forceinline__ void rle_stream(const InCol &in, unsigned long long c
   }
 }
 
-// The chunks c = cb + w + kWaves * j < ce of an uncompressed (MODE 0), static BP
+// The chunks c = first + STRIDE * j, j < nj, of an uncompressed (MODE 0), static BP
 // (MODE 1) or DynBP-family (MODE 2) column: full blocks stream through direct window
 // loads, kPre chunks ahead, with the block directory of the next group of chunks loaded
 // one group earlier (lane s holds chunk s's entry); the remaining chunks take the direct
 // path.  In the steady-state loop every load is issued on every path, so that the
 // compiler's wait counts let the kPre windows stay in flight: only the first group
 // needs the window it consumes.
-template <int MODE, class Body>
-__device__ __forceinline__ void stream_blocks(const InCol &in, unsigned long long cb, unsigned long long ce,
-                                              unsigned w, unsigned lane, Body &&body) {
+template <int MODE, int STRIDE, class Body>
+__device__ __forceinline__ void stream_blocks(const InCol &in, unsigned long long first, unsigned long long nj,
+                                              unsigned lane, Body &&body) {
   constexpr bool UNC = MODE == 0, DYN = MODE == 2;
-  const unsigned long long first = cb + w;
-  if (first >= ce) return;
-  const unsigned long long nj = (ce - first + kWaves - 1) / kWaves;
+  if (nj == 0) return;
   unsigned long long cmain;  // chunks [0, cmain) are full packed blocks
   unsigned Wfix = 32;
   if (UNC) {
@@ -803,14 +798,14 @@ __device__ __forceinline__ void stream_blocks(const InCol &in, unsigned long lon
   } else {
     cmain = in.nb;
   }
-  const unsigned long long njm = (first < cmain) ? min(nj, (cmain - first + kWaves - 1) / kWaves) : 0ull;
+  const unsigned long long njm = (first < cmain) ? min(nj, (cmain - first + STRIDE - 1) / STRIDE) : 0ull;
   if (njm > 0) {
     // directory of group g (chunks kPre*g .. kPre*g+3 of this wave) in lanes 0..3; every
     // lane loads (lane & 3)'s entry, clamped to the wave's last full block
     auto dir_load = [&](unsigned long long g, unsigned &dw, unsigned &doff, unsigned &dbase) {
       if (DYN) {
         const unsigned long long j = min(kPre * g + (lane & (unsigned)(kPre - 1)), njm - 1);
-        const unsigned long long c = first + kWaves * j;
+        const unsigned long long c = first + STRIDE * j;
         dw = in.widths[c];
         doff = in.offsets[c];
         dbase = in.bases[c];
@@ -821,7 +816,7 @@ __device__ __forceinline__ void stream_blocks(const InCol &in, unsigned long lon
     // width and payload offset of chunk j, whose directory entry is in lane s of (dw, doff)
     auto locate = [&](unsigned long long j, unsigned s, unsigned dw, unsigned doff, unsigned &W,
                       unsigned long long &off) {
-      const unsigned long long c = first + kWaves * j;
+      const unsigned long long c = first + STRIDE * j;
       if (DYN) {
         W = __builtin_amdgcn_readlane(dw, s);
         off = __builtin_amdgcn_readlane(doff, s);
@@ -861,47 +856,53 @@ __device__ __forceinline__ void stream_blocks(const InCol &in, unsigned long lon
     prime(std::integral_constant<int, 2>{});
     prime(std::integral_constant<int, 3>{});
     // group g: one chunk per slot (the slot index is a compile-time constant so that the
-    // windows stay in registers).  CHECK false: every slot and its reload exist.
-    auto group = [&](unsigned long long g, auto CK) {
-      constexpr bool check = decltype(CK)::value;
+    // windows stay in registers).  Every slot reloads its window on every path (past the
+    // wave's last full block it loads that block again, never consumed), so the wait
+    // before a window counts the other slots' loads as still in flight.
+    for (unsigned long long g = 0; kPre * g < njm; g++) {
       unsigned dwC, doC, dbC;
       dir_load(g + 2, dwC, doC, dbC);
       auto slot = [&](auto S) {
         constexpr int s = decltype(S)::value;
         const unsigned long long j = kPre * g + s;
-        if (check && j >= njm) return;
-        const unsigned long long c = first + kWaves * j;
-        unsigned W;
-        unsigned long long off;
-        locate(j, s, dwA, doA, W, off);
-        unsigned v[8];
-        if (UNC) {
+        if (j < njm) {
+          const unsigned long long c = first + STRIDE * j;
+          unsigned W;
+          unsigned long long off;
+          locate(j, s, dwA, doA, W, off);
+          unsigned v[8];
+          if (UNC) {
 #pragma unroll
-          for (int i = 0; i < 8; i++) v[i] = win[s].x[i];
-        } else {
-          win_unpack_rt(W, win[s], lane, v);
-        }
-        if (DYN && in.kind == FOR_DYN_BP) {
-          const unsigned ref = __builtin_amdgcn_readlane(dbA, s);
+            for (int i = 0; i < 8; i++) v[i] = win[s].x[i];
+          } else {
+            win_unpack_rt(W, win[s], lane, v);
+          }
+          if (DYN && in.kind == FOR_DYN_BP) {
+            const unsigned ref = __builtin_amdgcn_readlane(dbA, s);
 #pragma unroll
-          for (int i = 0; i < 8; i++) v[i] += ref;
-        } else if (DYN && in.kind == DELTA_DYN_BP) {
+            for (int i = 0; i < 8; i++) v[i] += ref;
+          } else if (DYN && in.kind == DELTA_DYN_BP) {
 #pragma unroll
-          for (int i = 1; i < 8; i++) v[i] += v[i - 1];
-          const unsigned excl = wave_excl_scan(v[7], lane) + __builtin_amdgcn_readlane(dbA, s);
+            for (int i = 1; i < 8; i++) v[i] += v[i - 1];
+            const unsigned excl = wave_excl_scan(v[7], lane) + __builtin_amdgcn_readlane(dbA, s);
 #pragma unroll
-          for (int i = 0; i < 8; i++) v[i] += excl;
-        }
-        if (!check || j + kPre < njm) {
+            for (int i = 0; i < 8; i++) v[i] += excl;
+          }
+          const unsigned long long jn = min(j + kPre, njm - 1);
           unsigned Wn;
           unsigned long long offn;
-          locate(j + kPre, s, dwB, doB, Wn, offn);
+          locate(jn, s, dwB, doB, Wn, offn);
+          issue(in.payload + offn, Wn, win[s]);
+          // keep the reload ahead of the body: the scheduler would otherwise sink the
+          // loads of all four slots to the end of the group
+          __builtin_amdgcn_sched_barrier(0);
+          body(c, v);
+        } else {
+          unsigned Wn;
+          unsigned long long offn;
+          locate(njm - 1, s, dwB, doB, Wn, offn);
           issue(in.payload + offn, Wn, win[s]);
         }
-        // keep the reload ahead of the body: the scheduler would otherwise sink the
-        // loads of all four slots to the end of the group
-        __builtin_amdgcn_sched_barrier(0);
-        body(c, v);
       };
       static_assert(kPre == 4, "four slots below");
       slot(std::integral_constant<int, 0>{});
@@ -910,16 +911,11 @@ __device__ __forceinline__ void stream_blocks(const InCol &in, unsigned long lon
       slot(std::integral_constant<int, 3>{});
       dwA = dwB; doA = doB; dbA = dbB;
       dwB = dwC; doB = doC; dbB = dbC;
-    };
-    // groups g with kPre * (g + 2) <= njm have all four slots and all four reloads
-    const unsigned long long g_steady = njm / kPre >= 2 ? njm / kPre - 1 : 0ull;
-    unsigned long long g = 0;
-    for (; g < g_steady; g++) group(g, std::false_type{});
-    for (; kPre * g < njm; g++) group(g, std::true_type{});
+    }
   }
   unsigned long long rle_hint = 0;
   for (unsigned long long j = njm; j < nj; j++) {
-    const unsigned long long c = first + kWaves * j;
+    const unsigned long long c = first + STRIDE * j;
     unsigned v[8];
     decode_chunk(in, c, lane, v, rle_hint);
     body(c, v);
@@ -936,14 +932,35 @@ __device__ __forceinline__ void stream_chunks(const InCol &in, unsigned long lon
                                               unsigned w, unsigned lane, unsigned *ring, const void *dummy,
                                               Body &&body) {
   (void)dummy;
-  if (in.kind == RLE)
-    rle_stream(in, cb, ce, w, lane, ring, body);
-  else if (in.kind == UNCOMPR)
-    stream_blocks<0>(in, cb, ce, w, lane, body);
+  if (in.kind == RLE) {  // a contiguous quarter of the segment per wave
+    const unsigned long long nseg = ce - cb;
+    rle_stream(in, cb + nseg * w / kWaves, cb + nseg * (w + 1) / kWaves, lane, ring, body);
+    return;
+  }
+  const unsigned long long first = cb + w;
+  const unsigned long long nj = first < ce ? (ce - first + kWaves - 1) / kWaves : 0ull;
+  if (in.kind == UNCOMPR)
+    stream_blocks<0, kWaves>(in, first, nj, lane, body);
   else if (in.kind == STATIC_BP)
-    stream_blocks<1>(in, cb, ce, w, lane, body);
+    stream_blocks<1, kWaves>(in, first, nj, lane, body);
   else
-    stream_blocks<2>(in, cb, ce, w, lane, body);
+    stream_blocks<2, kWaves>(in, first, nj, lane, body);
+}
+
+// Walk the chunks [c_begin, c_end) in order (one wave; used where a chunk needs the
+// value before it).  ring: the wave's kRing * 512 LDS words (RLE input only).
+template <class Body>
+__device__ __forceinline__ void stream_range(const InCol &in, unsigned long long c_begin, unsigned long long c_end,
+                                             unsigned lane, unsigned *ring, Body &&body) {
+  if (c_begin >= c_end) return;
+  if (in.kind == RLE)
+    rle_stream(in, c_begin, c_end, lane, ring, body);
+  else if (in.kind == UNCOMPR)
+    stream_blocks<0, 1>(in, c_begin, c_end - c_begin, lane, body);
+  else if (in.kind == STATIC_BP)
+    stream_blocks<1, 1>(in, c_begin, c_end - c_begin, lane, body);
+  else
+    stream_blocks<2, 1>(in, c_begin, c_end - c_begin, lane, body);
 }
 
 // Walk chunks cb + w, cb + w + kWaves, ... < ce with one chunk of look-ahead;

@@ -67,7 +67,7 @@ hipError_t launch_morph(const ColView &in, const ColView &out, unsigned auto_w, 
                         void *s);
 hipError_t launch_decode(const ColView &in, unsigned *out, unsigned G, void *s);
 hipError_t launch_rle(unsigned mode, const ColView &a, const ColView &b, const ColView &out, unsigned G,
-                      unsigned *seg_count, unsigned *partials, void *s);
+                      unsigned *wave_count, unsigned *partials, void *s);  // wave_count: kWaves * G words
 hipError_t launch_project(const ColView &pos, const ColView &data, const ColView &out, unsigned auto_w, unsigned G,
                           unsigned *partials, void *s);
 hipError_t launch_pred(const PredArgs &a, unsigned G, void *s);

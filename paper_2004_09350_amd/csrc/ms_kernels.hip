@@ -174,22 +174,24 @@ __device__ __forceinline__ unsigned src_value(const ChunkSrc &s, const InCol &ia
   return x;
 }
 
-// Both RLE phases walk the segment's chunks in lockstep, kWaves at a time, so that the
-// value before a chunk (needed to see whether the chunk starts a new run) is the last
-// value of the neighbouring wave's chunk, passed through LDS.  The emit phase stages a
-// chunk's runs in LDS and writes them with coalesced stores.  MODE 0 decodes column a
-// (morph), MODE 1 gathers b at the positions in a (project).
-template <unsigned MODE, bool EMIT>
-__device__ __forceinline__ void rle_walk(const ChunkSrc &s, const ColView &outv, const unsigned *seg_count,
-                                         unsigned *seg_out, unsigned *partials) {
-  __shared__ __attribute__((aligned(16))) unsigned lds_all[kWaves * kBlk];
+// Both RLE phases give each wave a contiguous quarter of its workgroup's segment and
+// walk it in order, so the value before a chunk (needed to see whether the chunk starts
+// a new run) is the last value of the wave's previous chunk; only the wave's first
+// chunk looks one value back in the column.  The count phase records each wave's run
+// count (wave_count, kWaves per workgroup); the emit phase takes its offset from those,
+// stages a chunk's runs in LDS and writes them with coalesced stores.  MODE 0 decodes
+// column a (morph), MODE 1 gathers b at the positions in a (project).
+// LDS: the run staging of RLE input (rle_ring_words(), only when column a is RLE) is
+// dynamic, so that the other inputs keep the occupancy of the smaller static buffers.
+constexpr unsigned kRleRingWords = kWaves * kRing * kBlk;
+template <unsigned MODE, bool DRLE, bool EMIT>
+__device__ __forceinline__ void rle_walk(const ChunkSrc &s, const ColView &outv, const unsigned *wave_count,
+                                         unsigned *wave_out, unsigned *partials) {
+  extern __shared__ __attribute__((aligned(16))) unsigned ring[];
   __shared__ __attribute__((aligned(16))) unsigned gblk[MODE == 1 ? kWaves * kBlk : 1];
-  __shared__ unsigned gstage[MODE == 1 ? kWaves * kBlk : 1];
-  __shared__ unsigned rstage[EMIT ? 2 * kWaves * kBlk : 1];
+  __shared__ __attribute__((aligned(16))) unsigned gstage[MODE == 1 ? kWaves * kBlk : 1];
+  __shared__ __attribute__((aligned(16))) unsigned rstage[EMIT ? 2 * kWaves * kBlk : 1];
   __shared__ unsigned long long red[kWaves];
-  __shared__ unsigned s_chunk_runs[kWaves];
-  __shared__ unsigned s_last[kWaves];
-  __shared__ unsigned s_first_prev;
   __shared__ unsigned redu[kWaves];
   const InCol ia = load_in(s.a);
   InCol ib = ia;
@@ -199,97 +201,87 @@ __device__ __forceinline__ void rle_walk(const ChunkSrc &s, const ColView &outv,
   const unsigned long long C = (n + kBlk - 1) / kBlk;
   unsigned long long cb, ce;
   segment(C, blockIdx.x, G, cb, ce);
-  unsigned long long base = 0, total = 0;
+  const unsigned long long nseg = ce - cb;
+  const unsigned long long cw0 = cb + nseg * w / kWaves, cw1 = cb + nseg * (w + 1) / kWaves;
+  // output offset of this wave's runs
+  unsigned long long g = 0;
   if (EMIT) {
-    unsigned long long before = 0;
-    for (unsigned i = threadIdx.x; i < G; i += kWG) {
-      total += seg_count[i];
-      if (i < blockIdx.x) before += seg_count[i];
+    unsigned long long before = 0, total = 0;
+    const unsigned me = kWaves * blockIdx.x + w;
+    for (unsigned i = threadIdx.x; i < kWaves * G; i += kWG) {
+      const unsigned x = wave_count[i];
+      total += x;
+      before += (i < kWaves * blockIdx.x) ? x : 0u;
     }
-    base = wg_add64(before, red);
+    before = wg_add64(before, red);
     total = wg_add64(total, red);
+    g = before;
+    for (unsigned j = kWaves * blockIdx.x; j < me; j++) g += wave_count[j];
     if (blockIdx.x == 0 && threadIdx.x == 0) {
       outv.hdr->n = n;
       outv.hdr->runs = total;
     }
   }
-  if (threadIdx.x == 0 && cb > 0 && cb < ce) s_first_prev = src_value(s, ia, ib, cb * kBlk - 1);
-  __syncthreads();
-  unsigned carry = s_first_prev;  // last value before the current round's first chunk
+  // the value before the wave's first chunk
+  unsigned carry = 0;
+  if (cw0 > 0 && cw0 < cw1) carry = uni(src_value(s, ia, ib, cw0 * kBlk - 1));
   unsigned or_all = 0, cnt_all = 0;
   bool bad = false;
-  unsigned *lds = lds_all + w * kBlk;
   unsigned *rv = rstage + (EMIT ? 2 * w * kBlk : 0), *rs = rv + kBlk;
-  Raw cur;
-  if (cb + w < ce) cur = issue_chunk(ia, cb + w, lane);
-  for (unsigned long long c0 = cb; c0 < ce; c0 += kWaves) {
-    const unsigned long long c = c0 + w;
-    Raw nxt;
-    if (c + kWaves < ce) nxt = issue_chunk(ia, c + kWaves, lane);
-    unsigned v[8] = {0, 0, 0, 0, 0, 0, 0, 0};
-    if (c < ce) {
-      finish_chunk(ia, cur, c, lane, lds, v);
-      if (MODE == 1)
-        gather8(ib, v, valid_mask(c * kBlk + 8ull * lane, n), bad, lane, gblk + w * kBlk, gstage + w * kBlk);
-      if (lane == 63) s_last[w] = v[7];
-    }
-    __syncthreads();
-    const unsigned before_chunk = (w > 0) ? s_last[w - 1] : carry;
-    const unsigned next_carry = s_last[kWaves - 1];
-    unsigned flags = 0;
-    if (c < ce) {
-      const unsigned long long idx0 = c * kBlk + 8ull * lane;
-      unsigned prev = lane_prev(v[7]);
-      if (lane == 0) prev = before_chunk;
-      const unsigned valid = valid_mask(idx0, n);
+  stream_range(ia, cw0, cw1, lane, ring + w * kRing * kBlk, [&](unsigned long long c, const unsigned (&pv)[8]) {
+    unsigned v[8];
 #pragma unroll
-      for (int i = 0; i < 8; i++) {
-        const unsigned pv = i ? v[i - 1] : prev;
-        if ((valid >> i) & 1u) {
-          or_all |= v[i];
-          if (idx0 + i == 0 || v[i] != pv) flags |= 1u << i;
-        }
+    for (int i = 0; i < 8; i++) v[i] = pv[i];
+    const unsigned long long idx0 = c * kBlk + 8ull * lane;
+    const unsigned valid = valid_mask(idx0, n);
+    if (MODE == 1) {
+      if constexpr (DRLE)
+        gather8_rle(ib, v, valid, bad, lane, gblk + w * kBlk, gstage + w * kBlk);
+      else
+        gather8<false>(ib, v, valid, bad, lane, gblk + w * kBlk, gstage + w * kBlk);
+    }
+    unsigned prev = lane_prev(v[7]);
+    if (lane == 0) prev = carry;
+    unsigned flags = 0;
+#pragma unroll
+    for (int i = 0; i < 8; i++) {
+      const unsigned q = i ? v[i - 1] : prev;
+      if ((valid >> i) & 1u) {
+        or_all |= v[i];
+        if (idx0 + i == 0 || v[i] != q) flags |= 1u << i;
       }
     }
+    carry = lane_last(v[7]);  // full chunks only are followed by another chunk
     const unsigned cnt = __popc(flags);
     cnt_all += cnt;
     if (EMIT) {
       const unsigned off = wave_excl_scan(cnt, lane);
       const unsigned chunk_total = lane_last(off + cnt);
-      if (lane == 0) s_chunk_runs[w] = chunk_total;
-      __syncthreads();
-      unsigned long long my = base;
-      for (unsigned j = 0; j < w; j++) my += s_chunk_runs[j];
-      unsigned long long all = base;
-      for (unsigned j = 0; j < kWaves; j++) all += s_chunk_runs[j];
-      if (c < ce) {
-        const unsigned idx0 = (unsigned)(c * kBlk) + 8u * lane;
+      if (chunk_total > 0) {
+        const unsigned i0 = (unsigned)idx0;
         unsigned q = off;
 #pragma unroll
         for (int i = 0; i < 8; i++) {
           if (flags & (1u << i)) {
             rv[q] = v[i];
-            rs[q] = idx0 + i;
+            rs[q] = i0 + i;
             q++;
           }
         }
         wave_sync();
-        if (my + chunk_total <= outv.n_cap) {
+        if (g + chunk_total <= outv.n_cap) {
           for (unsigned t = lane; t < chunk_total; t += 64) {  // consecutive lanes, consecutive runs
-            outv.rvalues[my + t] = rv[t];
-            outv.rstarts[my + t] = rs[t];
+            outv.rvalues[g + t] = rv[t];
+            outv.rstarts[g + t] = rs[t];
           }
-        } else if (chunk_total > 0) {
+        } else {
           raise_err(E_INVALID);
         }
         wave_sync();
+        g += chunk_total;
       }
-      base = all;
     }
-    __syncthreads();  // s_last and s_chunk_runs are rewritten next round
-    carry = next_carry;
-    cur = nxt;
-  }
+  });
   if (bad) raise_err(E_RANGE);
   if (EMIT) {
     or_all = wg_or(or_all, redu);
@@ -298,24 +290,26 @@ __device__ __forceinline__ void rle_walk(const ChunkSrc &s, const ColView &outv,
       partials[2 * blockIdx.x + 1] = 0;
     }
   } else {
-    const unsigned long long t = wg_add64(cnt_all, red);
-    if (threadIdx.x == 0) seg_out[blockIdx.x] = (unsigned)t;
+    const unsigned t = wave_add(cnt_all);
+    if (lane == 0) wave_out[kWaves * blockIdx.x + w] = t;
   }
 }
 
-__global__ __launch_bounds__(kWG) void k_rle_count(ChunkSrc s, unsigned *seg_count) {
-  rle_walk<0, false>(s, s.a, nullptr, seg_count, nullptr);
+__global__ __launch_bounds__(kWG) void k_rle_count(ChunkSrc s, unsigned *wave_count) {
+  rle_walk<0, false, false>(s, s.a, nullptr, wave_count, nullptr);
 }
-__global__ __launch_bounds__(kWG) void k_rle_emit(ChunkSrc s, ColView outv, const unsigned *seg_count,
+__global__ __launch_bounds__(kWG) void k_rle_emit(ChunkSrc s, ColView outv, const unsigned *wave_count,
                                                   unsigned *partials) {
-  rle_walk<0, true>(s, outv, seg_count, nullptr, partials);
+  rle_walk<0, false, true>(s, outv, wave_count, nullptr, partials);
 }
-__global__ __launch_bounds__(kWG) void k_rle_count_proj(ChunkSrc s, unsigned *seg_count) {
-  rle_walk<1, false>(s, s.a, nullptr, seg_count, nullptr);
+template <bool DRLE>
+__global__ __launch_bounds__(kWG) void k_rle_count_proj(ChunkSrc s, unsigned *wave_count) {
+  rle_walk<1, DRLE, false>(s, s.a, nullptr, wave_count, nullptr);
 }
-__global__ __launch_bounds__(kWG) void k_rle_emit_proj(ChunkSrc s, ColView outv, const unsigned *seg_count,
+template <bool DRLE>
+__global__ __launch_bounds__(kWG) void k_rle_emit_proj(ChunkSrc s, ColView outv, const unsigned *wave_count,
                                                        unsigned *partials) {
-  rle_walk<1, true>(s, outv, seg_count, nullptr, partials);
+  rle_walk<1, DRLE, true>(s, outv, wave_count, nullptr, partials);
 }
 
 // ---------------------------------------------------------------------------------------------
@@ -1121,17 +1115,21 @@ hipError_t launch_decode(const ColView &in, unsigned *out, unsigned G, void *s) 
   return hipGetLastError();
 }
 hipError_t launch_rle(unsigned mode, const ColView &a, const ColView &b, const ColView &out, unsigned G,
-                      unsigned *seg_count, unsigned *partials, void *s) {
+                      unsigned *wave_count, unsigned *partials, void *s) {
   ChunkSrc src;
   src.mode = mode;
   src.a = a;
   src.b = b;
+  const size_t shm = (a.kind == RLE) ? kRleRingWords * sizeof(unsigned) : 0;
   if (mode == 0) {
-    MS_LAUNCH(k_rle_count, G, kWG, s, src, seg_count);
-    MS_LAUNCH(k_rle_emit, G, kWG, s, src, out, seg_count, partials);
+    MS_LAUNCH_SHM("k_rle_count", k_rle_count, G, kWG, shm, s, src, wave_count);
+    MS_LAUNCH_SHM("k_rle_emit", k_rle_emit, G, kWG, shm, s, src, out, wave_count, partials);
+  } else if (b.kind == RLE) {
+    MS_LAUNCH_SHM("k_rle_count_proj", k_rle_count_proj<true>, G, kWG, shm, s, src, wave_count);
+    MS_LAUNCH_SHM("k_rle_emit_proj", k_rle_emit_proj<true>, G, kWG, shm, s, src, out, wave_count, partials);
   } else {
-    MS_LAUNCH(k_rle_count_proj, G, kWG, s, src, seg_count);
-    MS_LAUNCH(k_rle_emit_proj, G, kWG, s, src, out, seg_count, partials);
+    MS_LAUNCH_SHM("k_rle_count_proj", k_rle_count_proj<false>, G, kWG, shm, s, src, wave_count);
+    MS_LAUNCH_SHM("k_rle_emit_proj", k_rle_emit_proj<false>, G, kWG, shm, s, src, out, wave_count, partials);
   }
   return hipGetLastError();
 }

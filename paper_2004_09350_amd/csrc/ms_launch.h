@@ -30,6 +30,12 @@ inline hipStream_t S(void *s) { return reinterpret_cast<hipStream_t>(s); }
     hipLaunchKernelGGL(kern, dim3(grid), dim3(block), 0, S(stream), __VA_ARGS__); \
   } while (0)
 #define MS_LAUNCH(kern, grid, block, stream, ...) MS_LAUNCH_NAMED(#kern, kern, grid, block, stream, __VA_ARGS__)
+// named, with dynamic LDS of shm bytes
+#define MS_LAUNCH_SHM(name, kern, grid, block, shm, stream, ...)                    \
+  do {                                                                              \
+    ProfScope ps_(name, stream);                                                    \
+    hipLaunchKernelGGL(kern, dim3(grid), dim3(block), shm, S(stream), __VA_ARGS__); \
+  } while (0)
 
 // The device error word: init_err_word allocates it and points every unit's copy of
 // g_err_word at it (each unit registers its setter from a static initialiser).
