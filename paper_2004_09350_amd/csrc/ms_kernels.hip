@@ -4,7 +4,7 @@
 // the requested format (the paper's on-the-fly de/re-compression, section 3.2, with
 // the input side at register granularity and the output side at block granularity,
 // section 4.2).  Workgroup s of G owns a contiguous segment of 512-value chunks;
-// its four waves walk the segment's chunks with one chunk of look-ahead.
+// its four waves stream the segment's chunks with several chunks of look-ahead.
 //
 // Operators with a data-dependent output count (select, semi-join, intersect) run
 // in phases: the predicate phase writes one bit per input row plus a count per
@@ -112,7 +112,7 @@ __global__ __launch_bounds__(kWG) void k_narrow_copy(FinishArgs a, const unsigne
 // ---------------------------------------------------------------------------------------------
 // Column statistics needed by later operators: OR of all values (width bound).
 __global__ __launch_bounds__(kWG) void k_colstats(ColView inv, unsigned *partials) {
-  __shared__ __attribute__((aligned(16))) unsigned ring[kWaves * kRing * kBlk];
+  extern __shared__ __attribute__((aligned(16))) unsigned ring[];  // ring_shm() bytes
   __shared__ unsigned red[kWaves];
   const InCol in = load_in(inv);
   const unsigned lane = lane_id(), w = wave_id(), G = gridDim.x;
@@ -139,7 +139,7 @@ __global__ __launch_bounds__(kWG) void k_colstats(ColView inv, unsigned *partial
 
 // Decode into a plain device array.
 __global__ __launch_bounds__(kWG) void k_decode(ColView inv, unsigned *__restrict__ out) {
-  __shared__ __attribute__((aligned(16))) unsigned ring[kWaves * kRing * kBlk];
+  extern __shared__ __attribute__((aligned(16))) unsigned ring[];  // ring_shm() bytes
   const InCol in = load_in(inv);
   const unsigned lane = lane_id(), w = wave_id(), G = gridDim.x;
   const unsigned long long C = (in.n + kBlk - 1) / kBlk;
@@ -319,7 +319,7 @@ __global__ __launch_bounds__(kWG) void k_rle_emit_proj(ChunkSrc s, ColView outv,
 // mode 2: bitmap predicate on values, emits values, checks strict increase (intersect)
 template <unsigned MODE>
 __global__ __launch_bounds__(kWG) void k_pred(PredArgs a) {
-  __shared__ __attribute__((aligned(16))) unsigned ring[kWaves * kRing * kBlk];
+  extern __shared__ __attribute__((aligned(16))) unsigned ring[];  // ring_shm() bytes
   __shared__ unsigned long long red[kWaves];
   __shared__ unsigned redo[kWaves];
   const InCol in = load_in(a.in);
@@ -338,7 +338,7 @@ __global__ __launch_bounds__(kWG) void k_pred(PredArgs a) {
   unsigned *chunk_first = a.chunk_first, *chunk_last = a.chunk_last;
   // A semi-join bitmap that fits the workgroup's LDS (its ring, which only RLE input
   // uses) is probed there instead of through the caches.
-  const bool lds_bm = mode == 1 && in.kind != RLE && domain <= 32ull * kWaves * kRing * kBlk;
+  const bool lds_bm = mode == 1 && in.kind != RLE && domain <= kLdsBitmapBits;
   if (lds_bm) {
     const unsigned nw = (unsigned)((domain + 31) / 32);
     for (unsigned t = threadIdx.x; t < nw; t += kWG) ring[t] = bitmap[t];
@@ -708,7 +708,7 @@ __global__ __launch_bounds__(kWG) void k_emit_fix(EmitArgs a) {
 // ---------------------------------------------------------------------------------------------
 // Sum and group-sum.
 __global__ __launch_bounds__(kWG) void k_sum(ColView inv, unsigned long long *partials) {
-  __shared__ __attribute__((aligned(16))) unsigned ring[kWaves * kRing * kBlk];
+  extern __shared__ __attribute__((aligned(16))) unsigned ring[];  // ring_shm() bytes
   __shared__ unsigned long long red[kWaves];
   const InCol in = load_in(inv);
   const unsigned lane = lane_id(), w = wave_id(), G = gridDim.x;
@@ -1084,7 +1084,7 @@ hipError_t launch_narrow(const FinishArgs &a, unsigned *tmp, unsigned G, void *s
   return hipGetLastError();
 }
 hipError_t launch_colstats(const ColView &in, unsigned G, unsigned *partials, void *s) {
-  MS_LAUNCH(k_colstats, G, kWG, s, in, partials);
+  MS_LAUNCH_SHM("k_colstats", k_colstats, G, kWG, ring_shm(in), s, in, partials);
   FinishArgs f{};
   f.out = in;
   f.n_src = in.hdr;
@@ -1111,7 +1111,7 @@ hipError_t launch_morph(const ColView &in, const ColView &out, unsigned auto_w, 
 #undef MS_L
 }
 hipError_t launch_decode(const ColView &in, unsigned *out, unsigned G, void *s) {
-  MS_LAUNCH(k_decode, G, kWG, s, in, out);
+  MS_LAUNCH_SHM("k_decode", k_decode, G, kWG, ring_shm(in), s, in, out);
   return hipGetLastError();
 }
 hipError_t launch_rle(unsigned mode, const ColView &a, const ColView &b, const ColView &out, unsigned G,
@@ -1140,12 +1140,14 @@ hipError_t launch_project(const ColView &pos, const ColView &data, const ColView
 #undef MS_L
 }
 hipError_t launch_pred(const PredArgs &a, unsigned G, void *s) {
+  // the semi-join probes bitmaps of up to kLdsBitmapBits in LDS
+  const size_t shm = (a.mode == 1 && a.domain <= kLdsBitmapBits) ? kRingBytes : ring_shm(a.in);
   if (a.mode == 0)
-    MS_LAUNCH(k_pred<0>, G, kWG, s, a);
+    MS_LAUNCH_SHM("k_pred<0>", k_pred<0>, G, kWG, shm, s, a);
   else if (a.mode == 1)
-    MS_LAUNCH(k_pred<1>, G, kWG, s, a);
+    MS_LAUNCH_SHM("k_pred<1>", k_pred<1>, G, kWG, shm, s, a);
   else
-    MS_LAUNCH(k_pred<2>, G, kWG, s, a);
+    MS_LAUNCH_SHM("k_pred<2>", k_pred<2>, G, kWG, shm, s, a);
   return hipGetLastError();
 }
 hipError_t launch_emit(const EmitArgs &a, unsigned G, void *s) {
@@ -1156,7 +1158,7 @@ hipError_t launch_emit(const EmitArgs &a, unsigned G, void *s) {
 }
 hipError_t launch_sum(const ColView &in, unsigned long long *result, unsigned G, unsigned long long *partials,
                       void *s) {
-  MS_LAUNCH(k_sum, G, kWG, s, in, partials);
+  MS_LAUNCH_SHM("k_sum", k_sum, G, kWG, ring_shm(in), s, in, partials);
   MS_LAUNCH(k_sum_finish, 1, kWG, s, partials, G, result);
   return hipGetLastError();
 }
@@ -1196,7 +1198,7 @@ hipError_t launch_shrink_payload(const unsigned *src, const unsigned *old_off, c
 hipError_t launch_footprints(const ColView &in, unsigned G, unsigned long long *part, unsigned *first, unsigned *last,
                              unsigned long long *bpart, unsigned G2, unsigned long long *out6, void *s) {
   FpArgs a{in, part, first, last};
-  MS_LAUNCH(k_footprints, G, kWG, s, a);
+  MS_LAUNCH_SHM("k_footprints", k_footprints, G, kWG, ring_shm(in), s, a);
   MS_LAUNCH(k_chunk_changes, G2, kWG, s, first, last, in, bpart);
   MS_LAUNCH(k_footprints_finish, 1, kWG, s, part, G, bpart, G2, in, out6);
   return hipGetLastError();

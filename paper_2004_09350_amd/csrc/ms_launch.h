@@ -24,6 +24,12 @@ struct ProfScope {
 
 inline hipStream_t S(void *s) { return reinterpret_cast<hipStream_t>(s); }
 
+// Dynamic LDS of the kernels that stage RLE input runs (kRing * 512 words per wave):
+// only an RLE input needs it, so other inputs keep the occupancy of the static buffers.
+constexpr size_t kRingBytes = sizeof(unsigned) * kWaves * kRing * kBlk;
+constexpr unsigned long long kLdsBitmapBits = 32ull * kWaves * kRing * kBlk;
+inline size_t ring_shm(const ColView &c) { return c.kind == RLE ? kRingBytes : 0; }
+
 #define MS_LAUNCH_NAMED(name, kern, grid, block, stream, ...)                     \
   do {                                                                            \
     ProfScope ps_(name, stream);                                                  \

@@ -15,7 +15,7 @@ namespace ms {
 // Morph (and encode): out = encode_fmt(decode(in)), count known.
 template <unsigned OK>
 __global__ __launch_bounds__(kWG) void k_morph(ColView inv, ColView outv, unsigned auto_w, unsigned *partials) {
-  __shared__ __attribute__((aligned(16))) unsigned ring[kWaves * kRing * kBlk];
+  extern __shared__ __attribute__((aligned(16))) unsigned ring[];  // ring_shm() bytes
   __shared__ __attribute__((aligned(16))) unsigned lds_all[kWaves * kBlk];
   __shared__ unsigned red[kWaves];
   const InCol in = load_in(inv);
@@ -45,7 +45,7 @@ hipError_t launch_morph_ok<MS_OK>(const ColView &in, const ColView &out, unsigne
                                   unsigned *partials, void *s) {
   static const char *const names[] = {"k_morph<UNCOMPR>", "k_morph<STATIC_BP>", "k_morph<DYN_BP>",
                                       "k_morph<DELTA_DYN_BP>", "k_morph<FOR_DYN_BP>"};
-  MS_LAUNCH_NAMED(names[MS_OK], k_morph<MS_OK>, G, kWG, s, in, out, auto_w, partials);
+  MS_LAUNCH_SHM(names[MS_OK], k_morph<MS_OK>, G, kWG, ring_shm(in), s, in, out, auto_w, partials);
   return hipGetLastError();
 }
 

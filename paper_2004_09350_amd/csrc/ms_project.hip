@@ -19,7 +19,7 @@ namespace ms {
 template <unsigned OK, bool DRLE>
 __device__ __forceinline__ void project_body(const ColView &posv, const ColView &datav, const ColView &outv,
                                              unsigned auto_w, unsigned *partials) {
-  __shared__ __attribute__((aligned(16))) unsigned ring[kWaves * kRing * kBlk];
+  extern __shared__ __attribute__((aligned(16))) unsigned ring[];  // ring_shm() bytes
   __shared__ __attribute__((aligned(16))) unsigned gblk[kWaves * kBlk];
   __shared__ __attribute__((aligned(16))) unsigned lds_all[kWaves * kBlk];
   __shared__ unsigned red[kWaves];
@@ -76,9 +76,9 @@ hipError_t launch_project_ok<MS_OK>(const ColView &pos, const ColView &data, con
                                           "k_project_rle<DYN_BP>", "k_project_rle<DELTA_DYN_BP>",
                                           "k_project_rle<FOR_DYN_BP>"};
   if (data.kind == RLE)
-    MS_LAUNCH_NAMED(rle_names[MS_OK], k_project_rle<MS_OK>, G, kWG, s, pos, data, out, auto_w, partials);
+    MS_LAUNCH_SHM(rle_names[MS_OK], k_project_rle<MS_OK>, G, kWG, ring_shm(pos), s, pos, data, out, auto_w, partials);
   else
-    MS_LAUNCH_NAMED(names[MS_OK], k_project<MS_OK>, G, kWG, s, pos, data, out, auto_w, partials);
+    MS_LAUNCH_SHM(names[MS_OK], k_project<MS_OK>, G, kWG, ring_shm(pos), s, pos, data, out, auto_w, partials);
   return hipGetLastError();
 }
 
