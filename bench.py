@@ -518,7 +518,7 @@ def run_star(args, M, gen, torch, log):
             row = dict(seed=seed, setting=sname, rows_final=0, policies={})
             for pol in POLICIES:
                 q = queries.Q3(cols, thr, datagen.STAR_DIM_SIZES, n, formats=fmts[pol])
-                q.plan.set_tune(2, 8)
+                q.plan.set_tune(2, 0)
                 tg = time_graph(torch, q.plan, args.steps)
                 te = time_eager(torch, q.plan, max(1, args.steps // 2))
                 o1, o2 = q.results()

@@ -239,7 +239,7 @@ typedef struct {
 } ms_step;
 
 /* Launch shape: parallel branches (1..16) and the persistent-grid cap in workgroups per
- * compute unit (1..32). */
+ * compute unit (1..32, or 0 for each operator's default: 4, and 3 for project). */
 typedef struct {
   uint32_t branches;
   uint32_t wg_per_cu;
@@ -248,7 +248,7 @@ typedef struct {
 typedef struct ms_plan ms_plan;
 
 /* Validates the steps (operand kinds and order) and borrows the input columns, which
- * must outlive the plan.  Default tune: 1 branch, 8 workgroups per CU. */
+ * must outlive the plan.  Default tune: 1 branch, each operator's default grid. */
 ms_status ms_plan_create(const ms_step *steps, uint32_t n_steps, const ms_column *const *inputs, uint32_t n_inputs,
                          ms_plan **out);
 ms_status ms_plan_destroy(ms_plan *plan);

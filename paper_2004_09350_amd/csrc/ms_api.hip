@@ -53,7 +53,7 @@ ms_status hip_fail(hipError_t e, const char *what) {
 // Allocation goes to the calling thread's arena while one is set (plan capture), else to
 // the registered callbacks, else to hipMallocAsync.
 thread_local rt::Arena *t_arena = nullptr;
-thread_local unsigned t_wg_per_cu = 8;
+thread_local unsigned t_wg_per_cu = 0;  // 0: each operator's default
 
 void *dev_alloc(uint64_t bytes, void *stream) {
   if (bytes == 0) bytes = 256;
@@ -102,8 +102,13 @@ struct Scratch {
 
 uint64_t align256(uint64_t x) { return (x + 255) & ~255ull; }
 
-unsigned grid_for(uint64_t chunks) {
-  uint64_t max_wg = (uint64_t)g_cus * t_wg_per_cu;
+// Persistent grid: one workgroup per four chunks, capped at wg_per_cu workgroups per CU
+// (the plan's tune, else the operator's default: a multiple of the workgroups one CU
+// holds at once, so that the last round of workgroups is not a partial one).
+constexpr unsigned kWgPerCuDefault = 4;
+constexpr unsigned kWgPerCuProject = 3;  // the gather kernels hold three workgroups per CU
+unsigned grid_for(uint64_t chunks, unsigned dflt = kWgPerCuDefault) {
+  uint64_t max_wg = (uint64_t)g_cus * (t_wg_per_cu ? t_wg_per_cu : dflt);
   uint64_t g = (chunks + 3) / 4;
   if (g < 1) g = 1;
   if (g > max_wg) g = max_wg;
@@ -315,7 +320,7 @@ namespace ms {
 namespace rt {
 void set_thread_arena(Arena *a) { t_arena = a; }
 Arena *thread_arena() { return t_arena; }
-void set_thread_wg_per_cu(unsigned w) { t_wg_per_cu = w ? w : 8; }
+void set_thread_wg_per_cu(unsigned w) { t_wg_per_cu = w; }
 unsigned thread_wg_per_cu() { return t_wg_per_cu; }
 void *alloc(uint64_t bytes, void *stream) { return dev_alloc(bytes, stream); }
 void free(void *p, uint64_t bytes, void *stream) { dev_free(p, bytes, stream); }
@@ -768,7 +773,7 @@ ms_status ms_project(const ms_column *data, const ms_column *pos, ms_format fmt,
   st = check_fmt(fmt);
   if (st != MS_OK) return st;
   const uint64_t n_cap = pos->n_host != kUnknown ? pos->n_host : pos->n_cap;
-  const unsigned G = grid_for(chunks_of(n_cap));
+  const unsigned G = grid_for(chunks_of(n_cap), kWgPerCuProject);
   unsigned auto_w = 0;
   st = make_output(fmt, n_cap, stream, out, auto_w);
   if (st != MS_OK) return st;

@@ -88,7 +88,7 @@ uint64_t fnv(uint64_t h, const void *p, size_t n) {
 struct ms_plan {
   std::vector<ms_step> steps;
   std::vector<const ms_column *> inputs;
-  ms_tune tune{1, 8};
+  ms_tune tune{1, 0};
   std::vector<int> branch_of;
   std::vector<Result> eager, graph_res;
   bool last_graph = false;
@@ -342,7 +342,7 @@ ms_status ms_plan_set_format(ms_plan *p, uint32_t step, ms_format fmt) {
 ms_status ms_plan_set_tune(ms_plan *p, const ms_tune *t) {
   if (!p || !t) return fail(MS_ERR_INVALID_ARG, "NULL argument");
   if (t->branches < 1 || t->branches > kMaxBranches) return fail(MS_ERR_INVALID_ARG, "branches must be 1..16");
-  if (t->wg_per_cu < 1 || t->wg_per_cu > kMaxWgPerCu) return fail(MS_ERR_INVALID_ARG, "wg_per_cu must be 1..32");
+  if (t->wg_per_cu > kMaxWgPerCu) return fail(MS_ERR_INVALID_ARG, "wg_per_cu must be 0..32");
   if (t->branches != p->tune.branches || t->wg_per_cu != p->tune.wg_per_cu) {
     drop_graph(p);
     p->tune = *t;
@@ -483,12 +483,12 @@ ms_status ms_plan_autotune(ms_plan *p, void *stream, uint32_t reps, const char *
     }
   }
   static const uint32_t kBranches[] = {1, 2, 4, 8};
-  static const uint32_t kWg[] = {2, 4, 8, 16};
+  static const uint32_t kWg[] = {0, 2, 4, 8, 16};  // 0: each operator's default
   hipStream_t s = reinterpret_cast<hipStream_t>(stream);
   hipEvent_t e0, e1;
   if (hipEventCreate(&e0) != hipSuccess || hipEventCreate(&e1) != hipSuccess)
     return fail(MS_ERR_HIP, "event create failed");
-  ms_tune bt{1, 8};
+  ms_tune bt{1, 0};
   float bms = 1e30f;
   ms_status st = MS_OK;
   for (uint32_t b : kBranches) {

@@ -119,7 +119,7 @@ def test_q3_exhaustive_matches_oracle(M, Q, star):
     q3.plan.close()
 
 
-@pytest.mark.parametrize("tune", [(2, 4), (4, 8), (8, 2)])
+@pytest.mark.parametrize("tune", [(1, 0), (2, 4), (4, 8), (8, 2)])
 def test_q3_branches(M, Q, star, tune):
     cols, thr, want, enc = star
     q3 = Q.Q3(enc, thr, datagen.STAR_DIM_SIZES, N_FACT)
