@@ -153,7 +153,7 @@ def test_autotune_and_cache(M, Q, tmp_path):
     cache = str(tmp_path / "tune.txt")
     plan = Q.q1_plan(A, B, 103)
     best, ms = plan.autotune(reps=2, cache=cache)
-    assert best[0] in (1, 2, 4, 8) and best[1] in (2, 4, 8, 16) and ms > 0
+    assert best[0] in (1, 2, 4, 8) and best[1] in (0, 2, 4, 8, 16) and ms > 0
     assert plan.tune() == best
     lines = open(cache).read().split()
     assert len(lines) == 4 and (int(lines[1]), int(lines[2])) == best
