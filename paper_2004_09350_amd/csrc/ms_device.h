@@ -733,7 +733,14 @@ __device__ __forceinline__ void rle_stream(const InCol &in, unsigned long long c
     const unsigned long long idx0 = c0 + 8ull * lane;
     unsigned v[8];
     unsigned j = 0;  // staged index relative to r
-    if (idx0 < c1) {
+    // Runs of one value each across a full chunk: run r holds c0, and the run 511 later
+    // starting at c0 + 511 forces runs r + k to start at c0 + k, so value k is run r + k.
+    const bool unit_runs = c1 - c0 == kBlk && nst >= kBlk && S[(r + kBlk - 1) & kRunMask] == (unsigned)(c0 + kBlk - 1);
+    if (unit_runs) {
+#pragma unroll
+      for (int i = 0; i < 8; i++) v[i] = V[(r + 8ull * lane + i) & kRunMask];
+      j = 8u * lane + 7u;
+    } else if (idx0 < c1) {
       const unsigned x0 = (unsigned)idx0;
       unsigned lo = 0, hi = (unsigned)nst;  // last staged run starting at or before idx0
       while (hi - lo > 1) {
@@ -1129,11 +1136,50 @@ __device__ __forceinline__ void gather8_rle(const InCol &d, unsigned (&v)[8], un
     for (int i = 0; i < 8; i++) v[i] = ((pend >> i) & 1u) ? value_at(d, v[i]) : 0u;
     return;
   }
-  unsigned res[8];
-#pragma unroll
-  for (int i = 0; i < 8; i++) res[i] = 0;
   unsigned long long r = 0;
   bool first = true;
+  unsigned res_init[8] = {0, 0, 0, 0, 0, 0, 0, 0};
+  if (__ballot(pend != 0) != 0ull) {
+    // Runs of one value each: position p then lies in run r0 + (p - pmin), where r0 holds
+    // the wave's smallest position pmin; a run found to start at p holds p.  Both arrays
+    // are gathered at once; the misses go on through the staged windows below.
+    unsigned mine = 0xFFFFFFFFu;
+#pragma unroll
+    for (int i = 0; i < 8; i++)
+      if ((pend >> i) & 1u) mine = min(mine, v[i]);
+    const unsigned pmin = wave_min(mine);
+    const unsigned long long r0 = rle_find_wave(d, pmin, lane, 0ull);
+    unsigned cand[8];
+    unsigned hitm = 0;  // values resolved here
+#pragma unroll
+    for (int i = 0; i < 8; i++) {
+      cand[i] = 0u;
+      if ((pend >> i) & 1u) {
+        const unsigned long long q = r0 + (v[i] - pmin);
+        if (q < d.runs) {
+          const unsigned s = d.rstarts[q];
+          cand[i] = d.rvalues[q];
+          if (s == v[i] || v[i] == pmin) hitm |= 1u << i;
+        }
+      }
+    }
+    pend &= ~hitm;
+    if (__ballot(pend != 0) == 0ull) {
+#pragma unroll
+      for (int i = 0; i < 8; i++) v[i] = cand[i];
+      return;
+    }
+#pragma unroll
+    for (int i = 0; i < 8; i++) cand[i] = ((hitm >> i) & 1u) ? cand[i] : 0u;
+    r = r0;
+    first = false;
+    // the misses continue through the staged windows, starting at their own smallest position
+#pragma unroll
+    for (int i = 0; i < 8; i++) res_init[i] = cand[i];
+  }
+  unsigned res[8];
+#pragma unroll
+  for (int i = 0; i < 8; i++) res[i] = res_init[i];
   while (__ballot(pend != 0) != 0ull) {
     unsigned mine = 0xFFFFFFFFu;
 #pragma unroll

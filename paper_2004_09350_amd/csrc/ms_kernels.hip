@@ -717,10 +717,22 @@ __global__ __launch_bounds__(kWG) void k_sum(ColView inv, unsigned long long *pa
     // sum over runs: value * run length (section 2.2)
     unsigned long long rb, re;
     segment(in.runs, blockIdx.x, G, rb, re);
-    for (unsigned long long r = rb + threadIdx.x; r < re; r += kWG) {
-      const unsigned long long st = in.rstarts[r];
-      const unsigned long long en = (r + 1 < in.runs) ? in.rstarts[r + 1] : in.n;
-      s += (unsigned long long)in.rvalues[r] * (en - st);
+    // eight runs per thread per round, all loads issued before the products
+    constexpr unsigned kU = 8;
+    for (unsigned long long r = rb + threadIdx.x; r < re; r += kU * kWG) {
+      unsigned st[kU], en[kU], val[kU];
+#pragma unroll
+      for (unsigned k = 0; k < kU; k++) {
+        const unsigned long long q = r + (unsigned long long)k * kWG;
+        st[k] = en[k] = val[k] = 0u;
+        if (q < re) {
+          st[k] = in.rstarts[q];
+          en[k] = (q + 1 < in.runs) ? in.rstarts[q + 1] : (unsigned)in.n;
+          val[k] = in.rvalues[q];
+        }
+      }
+#pragma unroll
+      for (unsigned k = 0; k < kU; k++) s += (unsigned long long)val[k] * (en[k] - st[k]);
     }
   } else {
     const unsigned long long C = (in.n + kBlk - 1) / kBlk;
