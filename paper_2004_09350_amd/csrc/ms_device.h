@@ -872,12 +872,13 @@ __device__ __forceinline__ void stream_blocks(const InCol &in, unsigned long lon
       auto slot = [&](auto S) {
         constexpr int s = decltype(S)::value;
         const unsigned long long j = kPre * g + s;
-        if (j < njm) {
-          const unsigned long long c = first + STRIDE * j;
+        const bool live = j < njm;
+        const unsigned long long c = first + STRIDE * j;
+        unsigned v[8];
+        if (live) {
           unsigned W;
           unsigned long long off;
           locate(j, s, dwA, doA, W, off);
-          unsigned v[8];
           if (UNC) {
 #pragma unroll
             for (int i = 0; i < 8; i++) v[i] = win[s].x[i];
@@ -895,21 +896,18 @@ __device__ __forceinline__ void stream_blocks(const InCol &in, unsigned long lon
 #pragma unroll
             for (int i = 0; i < 8; i++) v[i] += excl;
           }
-          const unsigned long long jn = min(j + kPre, njm - 1);
+        }
+        // the reload, outside any branch: chunk j + kPre, or the wave's last full block again
+        {
           unsigned Wn;
           unsigned long long offn;
-          locate(jn, s, dwB, doB, Wn, offn);
-          issue(in.payload + offn, Wn, win[s]);
-          // keep the reload ahead of the body: the scheduler would otherwise sink the
-          // loads of all four slots to the end of the group
-          __builtin_amdgcn_sched_barrier(0);
-          body(c, v);
-        } else {
-          unsigned Wn;
-          unsigned long long offn;
-          locate(njm - 1, s, dwB, doB, Wn, offn);
+          locate(min(j + kPre, njm - 1), s, dwB, doB, Wn, offn);
           issue(in.payload + offn, Wn, win[s]);
         }
+        // keep the reload ahead of the body: the scheduler would otherwise sink the
+        // loads of all four slots to the end of the group
+        __builtin_amdgcn_sched_barrier(0);
+        if (live) body(c, v);
       };
       static_assert(kPre == 4, "four slots below");
       slot(std::integral_constant<int, 0>{});
