@@ -666,8 +666,7 @@ __device__ __forceinline__ void win_unpack_rt(unsigned W, const Win &r, unsigned
     MS_WIDTH_CASES(MS_WUNPACK_CASE)
 #undef MS_WUNPACK_CASE
     default:
-#pragma unroll
-      for (int i = 0; i < 8; i++) v[i] = 0;
+      __builtin_unreachable();  // widths come from locate(), which maps a corrupt one to 0
   }
 }
 

@@ -43,6 +43,12 @@ __device__ __forceinline__ unsigned wg_or(unsigned x, unsigned *sh) {
 __device__ __forceinline__ unsigned valid_mask(unsigned long long idx0, unsigned long long n) {
   return idx0 >= n ? 0u : (idx0 + 8 <= n ? 0xFFu : ((1u << (unsigned)(n - idx0)) - 1u));
 }
+// The same for lane `lane` of chunk c, where c and n are wave-uniform: a scalar test
+// settles every full chunk.
+__device__ __forceinline__ unsigned chunk_valid(unsigned long long c, unsigned lane, unsigned long long n) {
+  if ((c + 1) * kBlk <= n) return 0xFFu;
+  return valid_mask(c * kBlk + 8ull * lane, n);
+}
 
 // ---------------------------------------------------------------------------------------------
 // Output side.

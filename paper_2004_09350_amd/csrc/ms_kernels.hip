@@ -233,7 +233,7 @@ __device__ __forceinline__ void rle_walk(const ChunkSrc &s, const ColView &outv,
 #pragma unroll
     for (int i = 0; i < 8; i++) v[i] = pv[i];
     const unsigned long long idx0 = c * kBlk + 8ull * lane;
-    const unsigned valid = valid_mask(idx0, n);
+    const unsigned valid = chunk_valid(c, lane, n);
     if (MODE == 1) {
       if constexpr (DRLE)
         gather8_rle(ib, v, valid, bad, lane, gblk + w * kBlk, gstage + w * kBlk);
@@ -346,7 +346,7 @@ __global__ __launch_bounds__(kWG) void k_pred(PredArgs a) {
   }
   stream_chunks(in, cb, ce, w, lane, ring + w * kRing * kBlk, a.in.hdr, [&](unsigned long long c, const unsigned (&v)[8]) {
     const unsigned long long idx0 = c * kBlk + 8ull * lane;
-    const unsigned valid = valid_mask(idx0, in.n);
+    const unsigned valid = chunk_valid(c, lane, in.n);
     unsigned mask = 0;
     if constexpr (mode == 0) {
 #pragma unroll
@@ -739,7 +739,7 @@ __global__ __launch_bounds__(kWG) void k_sum(ColView inv, unsigned long long *pa
     unsigned long long cb, ce;
     segment(C, blockIdx.x, G, cb, ce);
     stream_chunks(in, cb, ce, w, lane, ring + w * kRing * kBlk, inv.hdr, [&](unsigned long long c, const unsigned (&v)[8]) {
-      const unsigned valid = valid_mask(c * kBlk + 8ull * lane, in.n);
+      const unsigned valid = chunk_valid(c, lane, in.n);
       unsigned long long t = 0;
 #pragma unroll
       for (int i = 0; i < 8; i++) t += ((valid >> i) & 1u) ? v[i] : 0u;
@@ -792,7 +792,7 @@ __global__ __launch_bounds__(kWG) void k_group_sum(ColView gv, ColView vv, unsig
       unsigned g[8], v[8];
       finish_chunk(ig, rg, c, lane, ldg, g);
       finish_chunk(iv, rv, c, lane, ldv, v);
-      const unsigned valid = valid_mask(c * kBlk + 8ull * lane, n);
+      const unsigned valid = chunk_valid(c, lane, n);
 #pragma unroll
       for (int i = 0; i < 8; i++) {
         if ((valid >> i) & 1u) {
@@ -875,7 +875,7 @@ __global__ __launch_bounds__(kWG) void k_bitmap(ColView posv, unsigned long long
   const bool increasing = uni(posv.hdr->sorted) != 0 || chunk_first != nullptr;
   stream_chunks(in, cb, ce, w, lane, ring + w * kRing * kBlk, posv.hdr, [&](unsigned long long c, const unsigned (&v)[8]) {
     const unsigned long long idx0 = c * kBlk + 8ull * lane;
-    const unsigned valid = valid_mask(idx0, in.n);
+    const unsigned valid = chunk_valid(c, lane, in.n);
     if (chunk_first) {
       const unsigned prev = lane_prev(v[7]);
 #pragma unroll

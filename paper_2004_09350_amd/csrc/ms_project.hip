@@ -40,7 +40,7 @@ __device__ __forceinline__ void project_body(const ColView &posv, const ColView 
     unsigned v[8];
 #pragma unroll
     for (int i = 0; i < 8; i++) v[i] = pv[i];
-    const unsigned valid = valid_mask(c * kBlk + 8ull * lane, ip.n);
+    const unsigned valid = chunk_valid(c, lane, ip.n);
     if constexpr (DRLE)
       gather8_rle(id, v, valid, bad, lane, gblk + w * kBlk, lds);
     else
