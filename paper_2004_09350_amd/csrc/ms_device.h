@@ -223,6 +223,27 @@ __device__ __forceinline__ void pack8_lds(unsigned *dst, unsigned s, const unsig
     if constexpr (W % 4 == 0) {
 #pragma unroll
       for (int k = 0; k < NW; k++) dst[k] = w[k];  // word-aligned, owned by this lane alone
+    } else if constexpr (W > 4) {
+      // 8W > 32 bits per lane: a word holds bits of at most two neighbouring lanes.  The
+      // lane writes every word it touches except a partial last one, which the next lane
+      // writes with this lane's part brought over by a lane shift; every word of the
+      // block is written exactly once, so the buffer needs no clearing and no atomics.
+      unsigned g[NW + 1];  // the lane's bits of words 0..NW of its window
+#pragma unroll
+      for (int k = 0; k <= NW; k++) {
+        const unsigned hi = k < NW ? w[k] : 0u, lo = k > 0 ? w[k - 1] : 0u;
+        g[k] = (unsigned)(((((unsigned long long)hi) << 32) | lo) >> (32u - s));
+      }
+      const unsigned e = s + 8u * W;          // end bit relative to the window's first word
+      const unsigned nspan = (e + 31u) >> 5;  // NW or NW + 1 words
+      const bool last_partial = (e & 31u) != 0u;
+      const unsigned last = (nspan == (unsigned)NW + 1u) ? g[NW] : g[NW - 1];
+      const unsigned from_prev = lane_prev(last_partial ? last : 0u);
+      if (s != 0u) g[0] |= from_prev;  // the previous lane ended inside this word
+      const unsigned nwrite = last_partial ? nspan - 1u : nspan;
+#pragma unroll
+      for (int k = 0; k <= NW; k++)
+        if ((unsigned)k < nwrite) dst[k] = g[k];
     } else {
       unsigned prev = 0;
 #pragma unroll
@@ -254,7 +275,7 @@ __device__ __forceinline__ void pack_block(unsigned W, const unsigned (&r)[8], u
                                            unsigned *__restrict__ dst) {
   if (W == 0) return;
   const unsigned words = 16u * W;
-  if (W % 4 != 0) {
+  if (W < 4) {  // several lanes share a word: OR-ed in with LDS atomics
     for (unsigned q = lane; q < words; q += 64) lds[q] = 0;
     wave_sync();
   }
