@@ -338,9 +338,12 @@ __global__ __launch_bounds__(kWG) void k_pred(PredArgs a) {
   unsigned *chunk_first = a.chunk_first, *chunk_last = a.chunk_last;
   // A semi-join bitmap that fits the workgroup's LDS (its ring, which only RLE input
   // uses) is probed there instead of through the caches.
-  const bool lds_bm = mode == 1 && in.kind != RLE && domain <= kLdsBitmapBits;
+  // A larger bitmap keeps its first kLdsBitmapBits bits there, which spares the caches
+  // the probes of the keys below that bound.
+  const bool lds_bm = mode == 1 && in.kind != RLE;
+  const unsigned long long lds_bits = min(domain, kLdsBitmapBits);
   if (lds_bm) {
-    const unsigned nw = (unsigned)((domain + 31) / 32);
+    const unsigned nw = (unsigned)((lds_bits + 31) / 32);
     for (unsigned t = threadIdx.x; t < nw; t += kWG) ring[t] = bitmap[t];
     __syncthreads();
   }
@@ -352,11 +355,20 @@ __global__ __launch_bounds__(kWG) void k_pred(PredArgs a) {
 #pragma unroll
       for (int i = 0; i < 8; i++)
         if (((v[i] - lo) <= span) != neg) mask |= 1u << i;
-    } else if (mode == 1 && lds_bm) {
+    } else if (mode == 1 && lds_bm && domain <= kLdsBitmapBits) {
 #pragma unroll
       for (int i = 0; i < 8; i++) {
         const unsigned x = v[i];
         if ((unsigned long long)x < domain && ((ring[x >> 5] >> (x & 31)) & 1u)) mask |= 1u << i;
+      }
+    } else if (mode == 1 && lds_bm) {
+#pragma unroll
+      for (int i = 0; i < 8; i++) {
+        const unsigned x = v[i];
+        if ((unsigned long long)x < domain) {
+          const unsigned word = (unsigned long long)x < lds_bits ? ring[x >> 5] : bitmap[x >> 5];
+          if ((word >> (x & 31)) & 1u) mask |= 1u << i;
+        }
       }
     } else {
 #pragma unroll
@@ -1152,8 +1164,8 @@ hipError_t launch_project(const ColView &pos, const ColView &data, const ColView
 #undef MS_L
 }
 hipError_t launch_pred(const PredArgs &a, unsigned G, void *s) {
-  // the semi-join probes bitmaps of up to kLdsBitmapBits in LDS
-  const size_t shm = (a.mode == 1 && a.domain <= kLdsBitmapBits) ? kRingBytes : ring_shm(a.in);
+  // the semi-join probes (the first kLdsBitmapBits bits of) its bitmap in LDS
+  const size_t shm = a.mode == 1 ? kRingBytes : ring_shm(a.in);
   if (a.mode == 0)
     MS_LAUNCH_SHM("k_pred<0>", k_pred<0>, G, kWG, shm, s, a);
   else if (a.mode == 1)
