@@ -336,10 +336,10 @@ __global__ __launch_bounds__(kWG) void k_pred(PredArgs a) {
   const unsigned *bitmap = a.bitmap;
   unsigned char *bitmask = a.bitmask;
   unsigned *chunk_first = a.chunk_first, *chunk_last = a.chunk_last;
-  // A semi-join bitmap that fits the workgroup's LDS (its ring, which only RLE input
-  // uses) is probed there instead of through the caches.
-  // A larger bitmap keeps its first kLdsBitmapBits bits there, which spares the caches
-  // the probes of the keys below that bound.
+  // A semi-join bitmap that fits the workgroup's dynamic LDS (kLdsBitmapBits, the size
+  // of the ring that RLE input uses otherwise) is probed there instead of through the
+  // caches; a larger one keeps its first kLdsBitmapBits bits there, which spares the
+  // caches the probes of the keys below that bound.
   const bool lds_bm = mode == 1 && in.kind != RLE;
   const unsigned long long lds_bits = min(domain, kLdsBitmapBits);
   if (lds_bm) {

@@ -180,10 +180,10 @@ def test_semijoin_and_bitmap(M):
     del rng
 
 
-@pytest.mark.parametrize("D", [2_500, 200_000, 262_144])
+@pytest.mark.parametrize("D", [2_500, 262_144, 2_000_000])
 def test_semijoin_small_domains(M, D):
     """Bitmaps built from select outputs (recorded as increasing), domains that fit the
-    probe's LDS, and keys in and out of the domain."""
+    probe's LDS or exceed it (probed partly in LDS), and keys in and out of the domain."""
     dim = datagen.uniform_range(61, D, 0, 100)
     s = O.select(dim, O.LT, 13)
     keys = datagen.uniform_range(62, 2_000_003, 0, D + D // 50)
