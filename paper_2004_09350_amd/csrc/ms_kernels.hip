@@ -543,9 +543,40 @@ __global__ __launch_bounds__(kWG) void k_emit(EmitArgs a) {
 
   // Emit one unit: lane bits m (bit i = value i, which is pos0 + i, or v[i] when the
   // chunk's values are emitted) in row order across the lanes; at most 512 outputs.
-  auto emit_unit = [&](unsigned long long m, unsigned pos0, const unsigned (&v)[8], bool vals) {
+  // A chunk's unit has eight bits per lane (unsigned), a group's 64 (unsigned long long).
+  auto emit_unit = [&](auto m, unsigned pos0, const unsigned (&v)[8], bool vals) {
+    constexpr bool BYTE = sizeof(m) == 4;
     auto value = [&](unsigned i) { return vals ? select8(v, i) : pos0 + i; };
-    const unsigned cntl = __popcll(m);
+    auto lowest = [](auto x) -> unsigned {
+      if constexpr (sizeof(x) == 4) return (unsigned)__ffs(x) - 1u;
+      else return (unsigned)__ffsll(x) - 1u;
+    };
+    // stage a lane's set bits at dst[k + (set bits below)]: unrolled for eight bits,
+    // else a loop over the set bits; returns the OR of the values
+    auto scatter = [&](auto &dst_at, unsigned k) -> unsigned {
+      unsigned orl = 0;
+      if constexpr (BYTE) {
+#pragma unroll
+        for (unsigned i = 0; i < 8; i++) {
+          if ((m >> i) & 1u) {
+            const unsigned val = value(i);
+            dst_at(k + __popc(m & ((1u << i) - 1u))) = val;
+            orl |= val;
+          }
+        }
+        m = 0;
+      } else {
+        while (m) {
+          const unsigned i = lowest(m);
+          m &= m - 1;
+          const unsigned val = value(i);
+          dst_at(k++) = val;
+          orl |= val;
+        }
+      }
+      return orl;
+    };
+    const unsigned cntl = BYTE ? (unsigned)__popc(m) : (unsigned)__popcll(m);
     const unsigned off = wave_excl_scan(cntl, lane);
     const unsigned tot = lane_last(off + cntl);
     unsigned gl = g + off;  // this lane's first output
@@ -553,28 +584,13 @@ __global__ __launch_bounds__(kWG) void k_emit(EmitArgs a) {
     if (blocky) {
       if (cap_ok && gend <= n_main_o && gl >= A32 && gend <= B32) {
         // owned, staged block elements: append to the ring
-        unsigned k = gl - A32, orl = 0;
-        while (m) {
-          const unsigned i = __ffsll(m) - 1;
-          m &= m - 1;
-          const unsigned val = value(i);
-          ring[k & (kEmitRing - 1)] = val;
-          orl |= val;
-          k++;
-        }
-        or_main |= orl;
+        auto at = [&](unsigned k) -> unsigned & { return ring[k & (kEmitRing - 1)]; };
+        or_main |= scatter(at, gl - A32);
       }
     } else if (cap_ok && tot > 0) {
       // uncompressed and RLE outputs: stage the unit's outputs, then coalesced stores
-      unsigned k = off, orl = 0;
-      while (m) {
-        const unsigned i = __ffsll(m) - 1;
-        m &= m - 1;
-        const unsigned val = value(i);
-        lds[k++] = val;
-        orl |= val;
-      }
-      or_main |= orl;  // n_main = N for these kinds
+      auto at = [&](unsigned k) -> unsigned & { return lds[k]; };
+      or_main |= scatter(at, off);  // n_main = N for these kinds
       wave_sync();
       if (kind == UNCOMPR) {
         for (unsigned t = lane; t < tot; t += 64) a.out.payload[g + t] = lds[t];
@@ -587,7 +603,7 @@ __global__ __launch_bounds__(kWG) void k_emit(EmitArgs a) {
       wave_sync();
     }
     while (m) {  // elements outside the fast paths
-      const unsigned i = __ffsll(m) - 1;
+      const unsigned i = lowest(m);
       m &= m - 1;
       const unsigned val = value(i);
       if (gl < n_main_o) or_main |= val;
@@ -668,16 +684,16 @@ __global__ __launch_bounds__(kWG) void k_emit(EmitArgs a) {
           const unsigned lo = __shfl((unsigned)m, src), hi = __shfl((unsigned)(m >> 32), src);
           const unsigned sh = 8u * (lane & 7u);
           const unsigned mb = (unsigned)(((((unsigned long long)hi) << 32) | lo) >> sh) & 0xFFu;
-          emit_unit(mb, (unsigned)((c + k) * kBlk) + 8u * lane, novals, false);
+          emit_unit((unsigned)mb, (unsigned)((c + k) * kBlk) + 8u * lane, novals, false);
         }
       }
     }
-    for (; c < cw1; c++) emit_unit(bm[c * 64], (unsigned)(c * kBlk) + 8u * lane, novals, false);
+    for (; c < cw1; c++) emit_unit((unsigned)bm[c * 64], (unsigned)(c * kBlk) + 8u * lane, novals, false);
   } else {
     for (unsigned long long c = cw0; c < cw1; c++) {
       unsigned v[8];
       decode_chunk(in, c, lane, v);
-      emit_unit(bm[c * 64], (unsigned)(c * kBlk) + 8u * lane, v, true);
+      emit_unit((unsigned)bm[c * 64], (unsigned)(c * kBlk) + 8u * lane, v, true);
     }
   }
   or_main = wg_or(or_main, redo);
