@@ -1,6 +1,6 @@
 """Learned format selection (section 5.2: formats chosen per intermediate by a cost model
 over data characteristics; exhaustive selection, whose per-column optimum is the plan
-optimum because footprints add up, is the judge).
+optimum because footprints add up, is the reference its regret is measured against).
 
 The engine produces its own training data: it runs star-query plans (the shape of the
 evaluation workload, with other seeds, sizes and selectivities), and for every

@@ -1,6 +1,6 @@
 """The learned format selector end to end on the GPU: training data produced by the
 engine (statistics + exact footprints of star-plan intermediates), training with the
-library's own kernels, and its picks on star plans with other seeds judged against
+library's own kernels, and its picks on star plans with other seeds compared with
 exhaustive selection, an untrained network and the naive all-static-BP plan."""
 import numpy as np
 import pytest
