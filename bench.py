@@ -281,10 +281,20 @@ def cpu_baseline(rows: int):
 KIND_NAMES = ("UNCOMPR", "STATIC_BP", "DYN_BP", "DELTA_DYN_BP", "FOR_DYN_BP", "RLE")
 
 
-def traffic_for(kernel: str):
-    """HBM bytes per launch of `kernel` from the committed counter summary, while its
-    source hash matches the kernels being measured (else None)."""
-    f = os.path.join(ROOT, "profiles", "traffic.json")
+def calib_copy(M, log, col, rows):
+    """Decode an uncompressed column once: the known-size reference (4 B read + 4 B
+    written per row) that scales the HBM counters."""
+    dst = col.decode()
+    M.sync()
+    log(f"calibration copy: k_decode of {rows} rows ({4 * rows} B read, {4 * rows} B written)")
+    del dst
+
+
+def traffic_for(kernel: str, name: str = "traffic"):
+    """HBM bytes per launch of `kernel` from the committed counter summary of the same
+    workload (profiles/<name>.json), while its source hash matches the kernels being
+    measured (else None)."""
+    f = os.path.join(ROOT, "profiles", name + ".json")
     if not os.path.exists(f):
         return None
     try:
@@ -308,10 +318,7 @@ def run_sweep(args, M, gen, torch, log):
     rows = args.rows or 100_000_000
     sw = Sweep(M, gen, rows, args.quick, log)
     if args.calib_copy:
-        dst = sw.cols[("U32", M.UNCOMPR)].decode()
-        M.sync()
-        log(f"calibration copy: k_decode of {rows} rows ({4 * rows} B read, {4 * rows} B written)")
-        del dst
+        calib_copy(M, log, sw.cols[("U32", M.UNCOMPR)], rows)
     sw.account()
     log("accounting pass done")
     if args.dump:
@@ -426,9 +433,9 @@ def plan_account(M, plan, inputs, log=None):
     return ue_total, alg
 
 
-def plan_roofline(M, plan, alg):
+def plan_roofline(M, plan, alg, workload: str):
     """Dominant kernel of one profiled eager run; achieved = its algorithmic bytes per
-    launch / its mean launch time."""
+    launch / its mean launch time; traffic from the workload's own counter summary."""
     M.sync()
     tune = plan.tune()
     plan.set_tune(1, tune[1])  # one branch: concurrent kernels would inflate each launch's events
@@ -449,7 +456,7 @@ def plan_roofline(M, plan, alg):
     bpl = alg.get(dom, 0) / cnt[dom]
     ach = bpl / (avg_ms * 1e-3) / 1e9
     roof = dict(bound="hbm", achieved=round(ach, 1), peak=HBM_PEAK_GBS, unit="GB/s",
-                frac=round(ach / HBM_PEAK_GBS, 4), traffic=traffic_for(dom))
+                frac=round(ach / HBM_PEAK_GBS, 4), traffic=traffic_for(dom, "traffic_" + workload))
     info = dict(kernel=dom, launches=cnt[dom], avg_ms=round(avg_ms, 4), bytes_per_launch=int(bpl),
                 share_of_run=round(tot[dom] / sum(tot.values()), 3),
                 per_kernel_ms={k: round(v, 3) for k, v in sorted(tot.items())})
@@ -494,6 +501,8 @@ def run_star(args, M, gen, torch, log):
         X, F, N, _ = selector.collect(300, log=log)
         params = selector.train(X, selector.targets(F, N), epochs=60, log=log)
         wsrc = "trained in this run on 300 plans"
+    if args.calib_copy:
+        calib_copy(M, log, M.encode(gen.uniform_bits(3, n, 32), M.fmt(M.UNCOMPR)), n)
     settings = (("wide", datagen.STAR_WIDE), ("narrow", datagen.STAR_NARROW))
     results, ue_sum, t_sum = [], 0, 0.0
     roof = dom = None
@@ -534,7 +543,7 @@ def run_star(args, M, gen, torch, log):
                     ue_sum += ue
                     t_sum += tg
                     if roof is None:
-                        roof, dom = plan_roofline(M, q.plan, alg)
+                        roof, dom = plan_roofline(M, q.plan, alg, "star")
                 q.plan.close()
                 del q
             ex = row["policies"]["exhaustive"]["intermediates_bytes"]
@@ -654,7 +663,7 @@ def run_batch(args, M, gen, torch, log):
     tg = time_graph(torch, plan, reps)
     log(f"autotuned {best} ({best_ms:.2f} ms in tuning), graph {tg * 1e3:.2f} ms")
     ue, alg = plan_account(M, plan, inputs)
-    roof, dom = plan_roofline(M, plan, alg)
+    roof, dom = plan_roofline(M, plan, alg, "batch")
     res = base_line(args, "uncompressed-equivalent GB/s of 512 mixed column-operator tasks in one captured graph",
                     round(ue / tg / 1e9, 2), "GB/s", tg,
                     f"batch: {T} tasks, rows log-uniform in [1e4, 5e7] ({rows} rows), operator "
@@ -718,7 +727,7 @@ def run_q1(args, M, gen, torch, log):
     tg = time_graph(torch, plan, reps)
     te = time_eager(torch, plan, reps)
     ue, alg = plan_account(M, plan, [A, B])
-    roof, dom = plan_roofline(M, plan, alg)
+    roof, dom = plan_roofline(M, plan, alg, "q1")
     res = base_line(args, "uncompressed-equivalent GB/s of Q1 (select -> project -> sum, captured graph)",
                     round(ue / tg / 1e9, 2), "GB/s", tg,
                     f"Q1: {n} rows, A uniform 10-bit static BP, B uniform 20-bit static BP, positions of A < 103 "

@@ -1,11 +1,13 @@
 """Summaries of rocprofv3 output for profiles/ (kernel statistics and HBM traffic).
 
-    python -m paper_2004_09350_amd.profsum <trace_dir> <fetch_dir> <write_dir> <out_prefix> <command...>
+    python -m paper_2004_09350_amd.profsum <trace_dir> <fetch_dir> <write_dir> <out_prefix> [--traffic=NAME] <command...>
 
-reads <trace_dir>/*_kernel_stats.csv (``rocprofv3 --kernel-trace --stats``) and the
-``--pmc FETCH_SIZE`` / ``--pmc WRITE_SIZE`` counter collections, and writes
-<out_prefix>.md (top kernels by time, average durations, per-dispatch traffic) and
-profiles/traffic.json (per kernel: HBM bytes per launch, the figure bench.py reports).
+reads <trace_dir>/*_kernel_stats.csv (``rocprofv3 --kernel-trace --stats``), the
+``--pmc FETCH_SIZE`` / ``--pmc WRITE_SIZE`` counter collections and the fetch run's log
+(<fetch_dir>.log), and writes <out_prefix>.md (top kernels by time, average durations,
+per-dispatch traffic) and profiles/NAME.json (default ``traffic``; per kernel: HBM bytes
+per launch, the figure bench.py reports for the same workload: ``traffic`` for the
+sweep, ``traffic_star`` etc. for the plan workloads).
 
 Counter scaling: FETCH_SIZE and WRITE_SIZE (KiB per dispatch) are each scaled by
 known / measured for the reference copy kernel ``k_decode`` of an uncompressed column
@@ -54,13 +56,18 @@ def counters(d: str, counter: str):
 
 def main(argv):
     trace_dir, fetch_dir, write_dir, out_prefix = argv[:4]
-    command = " ".join(argv[4:])
+    rest = argv[4:]
+    traffic_name = "traffic"  # profiles/<name>.json, read by bench.py for the same workload
+    if rest and rest[0].startswith("--traffic="):
+        traffic_name = rest[0].split("=", 1)[1]
+        rest = rest[1:]
+    command = " ".join(rest)
     stats = list(csv.DictReader(open(glob.glob(os.path.join(trace_dir, "*_kernel_stats.csv"))[0])))
     fetch = counters(fetch_dir, "FETCH_SIZE")
     write = counters(write_dir, "WRITE_SIZE")
     # calibration: the first k_decode dispatch is the reference copy (bench --calib-copy)
     rows = None
-    for line in open(os.path.join(os.path.dirname(fetch_dir), "prof_fetch.log")):
+    for line in open(fetch_dir.rstrip("/") + ".log"):
         m = re.search(r"calibration copy: k_decode of (\d+) rows", line)
         if m:
             rows = int(m.group(1))
@@ -82,7 +89,7 @@ def main(argv):
             "write_bytes_per_launch": sum(wv) / len(wv) * 1024 * f_write,
             "bytes_per_launch": (sum(fv) / len(fv) * 1024 * f_fetch + sum(wv) / len(wv) * 1024 * f_write),
         }
-    json.dump(traffic, open(os.path.join(ROOT, "profiles", "traffic.json"), "w"), indent=1)
+    json.dump(traffic, open(os.path.join(ROOT, "profiles", traffic_name + ".json"), "w"), indent=1)
     total = sum(float(r["TotalDurationNs"]) for r in stats)
     lines = [f"# rocprofv3 kernel statistics: {os.path.basename(out_prefix)}", "",
              f"Command (from the repository root): `rocprofv3 --kernel-trace --stats -d <dir> -o trace "
