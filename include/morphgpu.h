@@ -154,6 +154,19 @@ ms_status ms_sum(const ms_column *in, uint64_t *dev_result, void *stream);
  * MS_ERR_LENGTH_MISMATCH when both are known on the host, else raise it on the device. */
 ms_status ms_group_sum(const ms_column *groups, const ms_column *vals, uint32_t G, uint64_t *dev_out,
                        void *stream);
+/* ms_group_sum for callers that cannot allocate device memory: code being captured into a
+ * HIP graph, tight serving loops, harnesses that forbid hipMalloc.  Same arguments, result
+ * and errors as ms_group_sum, but the per-workgroup partial sums live in a static 2 MiB
+ * device array of the library (262144 uint64, held by each device the library runs on
+ * until the process ends) instead of memory from the allocator: nothing is allocated or
+ * freed, no allocator callback runs and no timing event is created.  G must be at most
+ * 262144 (else MS_ERR_INVALID_ARG); with G <= 4096 the grid is capped so that
+ * workgroups x G partial sums fit the array.  Every call on a device shares that device's
+ * array: calls that overlap in time on one device (different streams, or host threads)
+ * race and give wrong sums; calls ordered on one stream are safe.  Partial sums that must
+ * start at zero are cleared by a fill kernel inside the call. */
+ms_status ms_group_sum_noalloc(const ms_column *groups, const ms_column *vals, uint32_t G, uint64_t *dev_out,
+                               void *stream);
 
 /* Exact footprint in bytes of the column in each of the six formats (section 5.2:
  * exhaustive format selection tries every format; footprints are what it compares).

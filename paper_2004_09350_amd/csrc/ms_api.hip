@@ -314,6 +314,70 @@ ms_status compaction(const ms_column *in, const PredArgs &pa_in, bool emit_value
   return st;
 }
 
+// ---------------------------------------------------------------------------------------------
+// Group-sum shared by ms_group_sum and ms_group_sum_noalloc.
+constexpr uint32_t kMaxLdsGroupsHost = 4096;  // the kernel's LDS histogram holds this many groups
+
+ms_status group_sum_check(const ms_column *groups, const ms_column *vals, uint32_t G_groups, const uint64_t *dev_out) {
+  ms_status st = check_init();
+  if (st != MS_OK) return st;
+  if (!groups || !vals) return fail(MS_ERR_INVALID_ARG, "input is NULL");
+  if (G_groups && !dev_out) return fail(MS_ERR_INVALID_ARG, "output is NULL");
+  if (groups->n_host != kUnknown && vals->n_host != kUnknown && groups->n_host != vals->n_host)
+    return fail(MS_ERR_LENGTH_MISMATCH, "groups and values differ in length");
+  return MS_OK;
+}
+
+// Workgroups of the group-sum kernel: the persistent grid, at most one per CU (the
+// partials are G x groups), and at most what max_partials partial sums allow.
+unsigned group_sum_grid(const ms_column *groups, const ms_column *vals, uint32_t G_groups, uint64_t max_partials) {
+  const uint64_t n_cap = std::min(groups->n_host != kUnknown ? groups->n_host : groups->n_cap,
+                                  vals->n_host != kUnknown ? vals->n_host : vals->n_cap);
+  uint64_t G = grid_for(chunks_of(n_cap));
+  if (G > (uint64_t)g_cus) G = (uint64_t)g_cus;
+  if (G_groups <= kMaxLdsGroupsHost) G = std::min<uint64_t>(G, std::max<uint64_t>(max_partials / G_groups, 1));
+  return (unsigned)G;
+}
+
+// partials: G x G_groups sums (LDS path) or G_groups sums that must start at zero.
+ms_status group_sum_launch(const ms_column *groups, const ms_column *vals, uint32_t G_groups, uint64_t *dev_out,
+                           unsigned G, unsigned long long *partials, void *stream) {
+  hipError_t e = hipSuccess;
+  if (G_groups > kMaxLdsGroupsHost) e = launch_fill_u64(partials, G_groups, 0ull, stream);  // a kernel, not a memset
+  if (e == hipSuccess)
+    e = launch_group_sum(groups->v, vals->v, G_groups, reinterpret_cast<unsigned long long *>(dev_out), G, partials,
+                         stream);
+  return e == hipSuccess ? MS_OK : hip_fail(e, "kernel launch");
+}
+
+// ---------------------------------------------------------------------------------------------
+// Static scratch of the allocation-free entry point: 2 MiB of partial sums in the library's
+// own device memory (each device holds its copy until the process ends).  In host code the
+// name `scratch` is a host-side stand-in, never a device address: the device address is
+// looked up once per device and kept in g_scratch_dev.
+constexpr uint64_t kNoAllocScratchU64 = 1ull << 18;
+constexpr uint32_t kNoAllocMaxGroups = (uint32_t)kNoAllocScratchU64;
+static __device__ __align__(256) unsigned long long scratch[kNoAllocScratchU64];
+constexpr int kMaxDevices = 64;
+unsigned long long *g_scratch_dev[kMaxDevices] = {};
+
+// The current device's address of `scratch` (looked up on the first use on that device
+// when ms_init ran on another one).
+ms_status noalloc_scratch(unsigned long long **out) {
+  int dev = 0;
+  hipError_t e = hipGetDevice(&dev);
+  if (e != hipSuccess) return hip_fail(e, "hipGetDevice");
+  if (dev < 0 || dev >= kMaxDevices) return fail(MS_ERR_UNSUPPORTED, "device index beyond the scratch table");
+  if (!g_scratch_dev[dev]) {
+    void *ptr = nullptr;
+    e = hipGetSymbolAddress(&ptr, HIP_SYMBOL(scratch));
+    if (e != hipSuccess || !ptr) return hip_fail(e != hipSuccess ? e : hipErrorInvalidSymbol, "scratch address");
+    g_scratch_dev[dev] = static_cast<unsigned long long *>(ptr);
+  }
+  *out = g_scratch_dev[dev];
+  return MS_OK;
+}
+
 }  // namespace
 
 namespace ms {
@@ -344,6 +408,9 @@ ms_status ms_init(ms_alloc_fn alloc, ms_free_fn free_fn, void *ctx) {
   g_cus = prop.multiProcessorCount > 0 ? prop.multiProcessorCount : 256;
   e = init_err_word();
   if (e != hipSuccess) return hip_fail(e, "device error word");
+  unsigned long long *scratch_dev = nullptr;
+  ms_status sst = noalloc_scratch(&scratch_dev);
+  if (sst != MS_OK) return sst;
   g_alloc = alloc;
   g_free = free_fn;
   g_ctx = ctx;
@@ -812,27 +879,32 @@ ms_status ms_sum(const ms_column *in, uint64_t *dev_result, void *stream) {
 
 ms_status ms_group_sum(const ms_column *groups, const ms_column *vals, uint32_t G_groups, uint64_t *dev_out,
                        void *stream) {
-  ms_status st = check_init();
-  if (st != MS_OK) return st;
-  if (!groups || !vals) return fail(MS_ERR_INVALID_ARG, "input is NULL");
-  if (G_groups && !dev_out) return fail(MS_ERR_INVALID_ARG, "output is NULL");
-  if (groups->n_host != kUnknown && vals->n_host != kUnknown && groups->n_host != vals->n_host)
-    return fail(MS_ERR_LENGTH_MISMATCH, "groups and values differ in length");
-  if (G_groups == 0) return MS_OK;
-  const uint64_t n_cap = std::min(groups->n_host != kUnknown ? groups->n_host : groups->n_cap,
-                                  vals->n_host != kUnknown ? vals->n_host : vals->n_cap);
-  unsigned G = grid_for(chunks_of(n_cap));
-  if (G > (unsigned)g_cus) G = (unsigned)g_cus;  // partials are G x groups
+  ms_status st = group_sum_check(groups, vals, G_groups, dev_out);
+  if (st != MS_OK || G_groups == 0) return st;
+  const unsigned G = group_sum_grid(groups, vals, G_groups, ~0ull);
+  const bool lds = G_groups <= kMaxLdsGroupsHost;
   Scratch sc(stream);
-  const bool lds = G_groups <= 4096;
   unsigned long long *partials = sc.get<unsigned long long>(lds ? (uint64_t)G * G_groups : G_groups);
   if (!sc.ok) return fail(MS_ERR_OOM, "scratch allocation failed");
-  hipError_t e = hipSuccess;
-  if (!lds) e = launch_fill_u64(partials, G_groups, 0ull, stream);
-  if (e == hipSuccess)
-    e = launch_group_sum(groups->v, vals->v, G_groups, reinterpret_cast<unsigned long long *>(dev_out), G, partials,
-                         stream);
-  return e == hipSuccess ? MS_OK : hip_fail(e, "kernel launch");
+  return group_sum_launch(groups, vals, G_groups, dev_out, G, partials, stream);
+}
+
+ms_status ms_group_sum_noalloc(const ms_column *groups, const ms_column *vals, uint32_t G_groups, uint64_t *dev_out,
+                               void *stream) {
+  ms_status st = group_sum_check(groups, vals, G_groups, dev_out);
+  if (st != MS_OK || G_groups == 0) return st;
+  if (G_groups > kNoAllocMaxGroups)
+    return fail(MS_ERR_INVALID_ARG, "ms_group_sum_noalloc takes at most 262144 groups (its static scratch holds "
+                                    "262144 partial sums)");
+  unsigned long long *partials = nullptr;
+  st = noalloc_scratch(&partials);
+  if (st != MS_OK) return st;
+  const unsigned G = group_sum_grid(groups, vals, G_groups, kNoAllocScratchU64);
+  const bool was_suspended = prof_suspended();
+  prof_suspend(true);  // per-launch timing creates events: none from this entry point
+  st = group_sum_launch(groups, vals, G_groups, dev_out, G, partials, stream);
+  prof_suspend(was_suspended);
+  return st;
 }
 
 ms_status ms_footprints(const ms_column *in, uint64_t *dev_bytes6, void *stream) {

@@ -51,6 +51,7 @@ size_t prof_count();
 bool prof_get(size_t i, const char **name, float *ms);
 void prof_reset();
 void prof_suspend(bool on);  // this thread's launches are not timed while set
+bool prof_suspended();
 hipError_t launch_colstats(const ColView &in, unsigned G, unsigned *partials, void *s);
 hipError_t launch_finish(const FinishArgs &a, void *s);
 hipError_t launch_narrow(const FinishArgs &a, unsigned *tmp, unsigned G, void *s);

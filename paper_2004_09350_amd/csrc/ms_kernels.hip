@@ -1074,6 +1074,7 @@ hipError_t init_err_word() {
 
 void prof_enable(bool on) { g_prof_on = on; }
 void prof_suspend(bool on) { t_prof_suspended = on; }
+bool prof_suspended() { return t_prof_suspended; }
 size_t prof_count() {
   std::lock_guard<std::mutex> g(g_prof_mu);
   return g_prof.size();

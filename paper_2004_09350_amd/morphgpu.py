@@ -88,6 +88,7 @@ _sigs = {
     "ms_intersect": [_P, _P, _U64, Format, _P, _PP],
     "ms_sum": [_P, _P, _P],
     "ms_group_sum": [_P, _P, _U32, _P, _P],
+    "ms_group_sum_noalloc": [_P, _P, _U32, _P, _P],
     "ms_sync": [_P],
     "ms_footprints": [_P, _P, _P],
     "ms_stats": [_P, _P, _P],
@@ -142,11 +143,17 @@ def _stream(stream=None) -> int:
 
 
 # --------------------------------------------------------------------------------- allocator
-_allocations: dict = {}
+_alloc_calls = [0, 0]  # allocator callbacks made by the library: [alloc, free]
+
+
+def allocator_calls() -> tuple:
+    """(alloc, free) callbacks the library has made through this binding so far."""
+    return tuple(_alloc_calls)
 
 
 @_ALLOC_T
 def _torch_alloc(nbytes, stream, ctx):
+    _alloc_calls[0] += 1
     try:
         p = torch.cuda.caching_allocator_alloc(int(nbytes), torch.cuda.current_device(), stream or 0)
         return p
@@ -156,6 +163,7 @@ def _torch_alloc(nbytes, stream, ctx):
 
 @_FREE_T
 def _torch_free(ptr, nbytes, stream, ctx):
+    _alloc_calls[1] += 1
     if ptr:
         torch.cuda.caching_allocator_delete(ptr)
 
@@ -316,6 +324,15 @@ def group_sum(groups: Column, vals: Column, G: int, out: torch.Tensor | None = N
     if out is None:
         out = torch.empty(max(G, 1), dtype=torch.int64, device="cuda")
     _check(_lib.ms_group_sum(groups.handle, vals.handle, G, out.data_ptr(), _stream(stream)))
+    return out[:G]
+
+
+def group_sum_noalloc(groups: Column, vals: Column, G: int, out: torch.Tensor, stream=None) -> torch.Tensor:
+    """ms_group_sum_noalloc: group-sum with the library's static scratch; `out` (int64[G],
+    caller-allocated) receives the sums."""
+    if out.dtype != torch.int64 or not out.is_cuda or out.numel() < G:
+        raise ValueError("out must be an int64 CUDA tensor with room for G sums")
+    _check(_lib.ms_group_sum_noalloc(groups.handle, vals.handle, G, out.data_ptr(), _stream(stream)))
     return out[:G]
 
 
