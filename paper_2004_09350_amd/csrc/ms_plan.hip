@@ -223,14 +223,13 @@ ms_status run_steps(ms_plan *p, hipStream_t origin, std::vector<Result> &r) {
 }
 
 void drop_graph(ms_plan *p) {
+  // Replays may still be queued on any stream the caller launched them on: wait for the
+  // device before the executable graph, its kernel arguments and the arena go away.
+  if (p->exec || p->graph || p->arena || !p->graph_res.empty()) (void)hipDeviceSynchronize();
   if (p->exec) (void)hipGraphExecDestroy(p->exec);
   if (p->graph) (void)hipGraphDestroy(p->graph);
   p->exec = nullptr;
   p->graph = nullptr;
-  if (p->arena || !p->graph_res.empty()) {
-    if (p->arena_stream) (void)hipStreamSynchronize(reinterpret_cast<hipStream_t>(p->arena_stream));
-    (void)hipDeviceSynchronize();
-  }
   for (auto &x : p->graph_res)
     if (x.col) ms_column_free(x.col);  // arena columns: frees only the handle
   p->graph_res.clear();

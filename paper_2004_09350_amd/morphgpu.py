@@ -9,6 +9,7 @@ from __future__ import annotations
 
 import ctypes
 import os
+import weakref
 
 import numpy as np
 import torch
@@ -198,7 +199,17 @@ class Column:
 
     @property
     def handle(self):
+        if not self._h.value and self._stale:
+            raise MorphError(1, "borrowed plan result used after the plan's results changed (run, launch after a "
+                                "change, set_format, set_tune, autotune or close); take plan.column() again")
         return self._h
+
+    _stale = False
+
+    def _invalidate(self):
+        """Drop a borrowed handle whose results the plan is about to free."""
+        self._h = ctypes.c_void_p(0)
+        self._stale = True
 
     def free(self):
         if self._h and self._h.value and self._owned:
@@ -213,13 +224,14 @@ class Column:
 
     def info(self, stream=None) -> dict:
         ci = ColumnInfo()
-        _check(_lib.ms_column_info_get(self._h, _stream(stream), ctypes.byref(ci)))
+        _check(_lib.ms_column_info_get(self.handle, _stream(stream), ctypes.byref(ci)))
         return {f: getattr(ci, f) for f, _ in ColumnInfo._fields_}
 
     def read_section(self, sec: int, nbytes: int, dtype, stream=None) -> np.ndarray:
         buf = np.zeros(max(nbytes, 1), np.uint8)
         got = _U64(0)
-        _check(_lib.ms_column_read_section(self._h, sec, buf.ctypes.data, nbytes, _stream(stream), ctypes.byref(got)))
+        _check(_lib.ms_column_read_section(self.handle, sec, buf.ctypes.data, nbytes, _stream(stream),
+                                           ctypes.byref(got)))
         return buf[: got.value].view(dtype).copy()
 
     def sections(self, stream=None) -> dict:
@@ -242,11 +254,11 @@ class Column:
         if n is None:
             n = self.info(stream)["n"]
         out = torch.empty(max(n, 4), dtype=torch.int32, device="cuda")
-        _check(_lib.ms_column_decode(self._h, out.data_ptr(), _stream(stream)))
+        _check(_lib.ms_column_decode(self.handle, out.data_ptr(), _stream(stream)))
         return out[:n]
 
     def shrink(self, stream=None):
-        _check(_lib.ms_column_shrink(self._h, _stream(stream)))
+        _check(_lib.ms_column_shrink(self.handle, _stream(stream)))
         return self
 
     def __len__(self):
@@ -425,8 +437,17 @@ class Plan:
         h = ctypes.c_void_p(0)
         _check(_lib.ms_plan_create(arr, len(self.steps), ins, len(self.inputs), ctypes.byref(h)))
         self._h = h
+        self._borrowed = weakref.WeakSet()  # result views handed out by column()
+        self._borrowed_graph = False        # whether they view the captured graph's results
+
+    def _drop_borrowed(self):
+        for c in list(self._borrowed):
+            c._invalidate()
+        self._borrowed = weakref.WeakSet()
+        self._borrowed_graph = False
 
     def close(self):
+        self._drop_borrowed()
         if self._h and self._h.value:
             _lib.ms_plan_destroy(self._h)
             self._h = ctypes.c_void_p(0)
@@ -438,10 +459,12 @@ class Plan:
             pass
 
     def set_format(self, i: int, f: Format):
+        self._drop_borrowed()
         _check(_lib.ms_plan_set_format(self._h, i, f))
         self.steps[i].out = f
 
     def set_tune(self, branches: int, wg_per_cu: int):
+        self._drop_borrowed()
         t = Tune(branches, wg_per_cu)
         _check(_lib.ms_plan_set_tune(self._h, ctypes.byref(t)))
 
@@ -451,12 +474,19 @@ class Plan:
         return t.branches, t.wg_per_cu
 
     def run(self, stream=None):
+        self._drop_borrowed()
         _check(_lib.ms_plan_run(self._h, _stream(stream)))
 
     def launch(self, stream=None):
+        # a replay of the captured graph keeps its results in place; a (re)capture or a
+        # switch from eager results does not
+        if not self._borrowed_graph:
+            self._drop_borrowed()
         _check(_lib.ms_plan_launch(self._h, _stream(stream)))
+        self._borrowed_graph = True
 
     def autotune(self, reps: int = 3, cache: str | None = None, stream=None):
+        self._drop_borrowed()
         t = Tune()
         ms = ctypes.c_float(0)
         _check(_lib.ms_plan_autotune(self._h, _stream(stream), reps, cache.encode() if cache else None,
@@ -472,7 +502,9 @@ class Plan:
         _check(_lib.ms_plan_result(self._h, i, ctypes.byref(c), None))
         if not c.value:
             raise MorphError(1, "step has no column result")
-        return Column(c.value, keep=self, owned=False)
+        col = Column(c.value, keep=self, owned=False)
+        self._borrowed.add(col)
+        return col
 
     def read(self, i: int, stream=None) -> np.ndarray:
         """Host copy of a non-column result: uint64 for sums, group sums and footprints,

@@ -34,14 +34,16 @@ def assert_column(col, values, kind, bit_width=O.BW_AUTO, canonical=False):
             np.testing.assert_array_equal(got["bases"], exp["bases"])
         np.testing.assert_array_equal(got["rem"], exp["rem"])
         w = exp["widths"].astype(np.int64) * 16
-        if w.size:
-            # gather each block's words through both directories
-            rel = np.arange(int(w.max()) if w.max() else 0)
-            for k in np.nonzero(w)[0][:: max(1, w.size // 4096)] if w.size > 4096 else np.nonzero(w)[0]:
-                g0, e0 = int(got["offsets"][k]), int(exp["offsets"][k])
-                np.testing.assert_array_equal(got["payload"][g0:g0 + w[k]], exp["payload"][e0:e0 + w[k]],
-                                              err_msg=f"block {k}")
-            del rel
+        if int(w.sum()):
+            # every block's words, gathered through both directories
+            go, eo = got["offsets"].astype(np.int64), exp["offsets"].astype(np.int64)
+            blk = np.repeat(np.arange(w.size), w)
+            within = np.arange(blk.size) - np.repeat(np.cumsum(w) - w, w)
+            gw, ew = got["payload"][go[blk] + within], exp["payload"][eo[blk] + within]
+            if not np.array_equal(gw, ew):
+                bad = np.nonzero(gw != ew)[0]
+                raise AssertionError(f"payload words differ in {np.unique(blk[bad]).size} blocks, first block "
+                                     f"{blk[bad[0]]} word {within[bad[0]]}")
         if canonical:
             np.testing.assert_array_equal(got["offsets"], exp["offsets"])
             np.testing.assert_array_equal(got["payload"][: exp["payload_words"]], exp["payload"])

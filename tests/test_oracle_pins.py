@@ -272,10 +272,20 @@ def test_semijoin_bitmap_project_intersect_sum_groupsum_vs_numpy():
     assert int(np.sum(got, dtype=np.uint64)) == O.sum_(v)  # sum over groups = total sum
 
 
-def test_sum_wraps_mod_2_64():
-    v = np.full(1 << 33 >> 31, 0xFFFFFFFF, np.uint32)  # 4 values
-    assert O.sum_(v) == 4 * 0xFFFFFFFF
+def test_sum_exact_in_64_bits():
+    """Sums are exact uint64 arithmetic: beyond 32 bits and beyond the 53 bits a double
+    holds exactly (a wrap past 2^64 needs more than 2^32 values, more than a column holds)."""
+    n = 1 << 22
+    v = np.full(n, 0xFFFFFFFF, np.uint32)
+    want = n * 0xFFFFFFFF                      # 18 014 398 505 287 680 > 2^53
+    assert want > 1 << 53
+    assert O.sum_(v) == want
+    v[-1] = 0xFFFFFFFE                         # off by one in the last bit: still exact
+    assert O.sum_(v) == want - 1
     assert O.group_sum([0, 0], [0xFFFFFFFF, 1], 1)[0] == 0x100000000
+    g = np.arange(n, dtype=np.uint32) & 1
+    got = O.group_sum(g, v, 2)
+    assert int(got[0]) == (n // 2) * 0xFFFFFFFF and int(got[1]) == (n // 2) * 0xFFFFFFFF - 1
 
 
 def test_error_paths():
@@ -362,6 +372,65 @@ def test_stats_closed_forms():
     # 65536 sampled values drawn from 2^16 keys hold 2^16 (1 - 1/e) distinct values on average
     assert f[22] == pytest.approx(np.log2(65536 * (1 - np.exp(-1))) / 32, abs=np.log2(1.25) / 32)
     assert 0.45 < f[20] < 0.55
+
+
+@pytest.mark.parametrize("k", range(2, 8))
+def test_stats_delta_width_classes(k):
+    """Constant-stride ramps: every neighbouring difference (mod 2^32) equals the stride,
+    whose bit width 5(k-1)+1 falls in delta class k; feature 27 is that width / 32."""
+    t = 5 * (k - 1)
+    stride = 1 << t
+    n = 4096
+    v = (np.arange(n, dtype=np.uint64) * stride % (1 << 32)).astype(np.uint32)
+    f = O.stats(v)
+    want = np.zeros(8)
+    want[k] = 1.0
+    np.testing.assert_array_equal(f[12:20], want)
+    assert f[27] == pytest.approx((t + 1) / 32)
+
+
+@pytest.mark.parametrize("t", [0, 3, 11, 20])
+def test_stats_for_residual_width(t):
+    """Ascending ramps v = j * 2^t inside 512-value chunks (no wrap): the chunk minimum is
+    the first value, the residuals are j' * 2^t for j' < 512, whose OR is 511 * 2^t, so
+    feature 26 is (9 + t) / 32; feature 25 (OR of the values) is bw of the last chunk's
+    OR averaged over chunks."""
+    n = 512 * 8
+    v = (np.arange(n, dtype=np.uint64) << np.uint64(t)).astype(np.uint32)
+    f = O.stats(v)
+    assert f[26] == pytest.approx((9 + t) / 32)
+    or_bw = [int(np.bitwise_or.reduce(v[c * 512:(c + 1) * 512])).bit_length() for c in range(8)]
+    assert f[25] == pytest.approx(np.mean(or_bw) / 32)
+
+
+def test_stats_mean_width():
+    """Feature 30 is the bit width of floor(mean): values 0 and 2^20 in equal numbers have
+    mean 2^19 (width 20); one more zero pulls the mean just below it (width 19)."""
+    v = np.tile(np.array([0, 1 << 20], np.uint32), 2048)
+    assert O.stats(v)[30] == pytest.approx(20 / 32)
+    v = np.concatenate([v, np.zeros(1, np.uint32)])
+    assert O.stats(v)[30] == pytest.approx(19 / 32)
+
+
+def test_stats_sampled_chunks():
+    """Above 65536 values the statistics read 128 chunks: chunk floor(s * C / 128) for
+    s < 128, C = floor(n / 512).  Chunk c holds the constant c when it is one of those and
+    0xFFFFFFFF otherwise: every read chunk is constant, the largest value read is the last
+    sampled index, and the unread chunks (which hold the maximum uint32) never show."""
+    C = 1000
+    n = 512 * C + 77
+    sampled = sorted({(s * C) // 128 for s in range(128)})
+    v = np.full(n, 0xFFFFFFFF, np.uint32)
+    for c in sampled:
+        v[512 * c:512 * (c + 1)] = c
+    f = O.stats(v)
+    assert f[31] == 1.0                                   # every sampled chunk is constant
+    assert f[29] == pytest.approx(max(sampled).bit_length() / 32)   # 992 -> 10 bits
+    assert f[28] == 0.0                                   # chunk 0 is read
+    mean = sum((s * C) // 128 for s in range(128)) * 512 // (128 * 512)
+    assert f[30] == pytest.approx(int(mean).bit_length() / 32)
+    assert f[23] == pytest.approx(np.log2(max(sampled) + 1) / 32)
+    assert f[20] == 1.0 and f[12] == 1.0                  # constant chunks: differences 0
 
 
 # ----------------------------------------------------------------------------- selector network
