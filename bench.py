@@ -1,6 +1,16 @@
-"""Benchmark: the operator/format sweep over 1e8-row uint32 columns on one MI355X.
+"""Benchmark on one MI355X.
 
-One step = one pass of the whole sweep (every row of the hot path that applies to
+Default: the fused star query (6e8 fact rows, static-BP base columns) under six format
+policies -- plain uncompressed execution (uncompressed base columns and intermediates),
+uncompressed intermediates, all static BP, exhaustive selection, and the learned
+selector's picks for footprint and for decode time -- each run eagerly and as an
+autotuned captured graph, every run timed cold (a 2 GiB write evicts the caches between
+runs); the value is the uncompressed-equivalent GB/s of the learned plan's graph.  The
+line also carries the footprint regret against exhaustive selection, the roofline of
+the dominant kernel, measured copy bandwidth, the CPU oracle (one thread and all cores)
+and, under "sweep", the operator/format sweep:
+
+One sweep step = one pass of the whole sweep (every row of the hot path that applies to
 single operators): for each of six value distributions (uniform 4/12/24/32-bit,
 sorted with small gaps, runs of mean length 64), each stored in each of the six
 formats:
@@ -38,11 +48,15 @@ SELECTIVITIES = (0.01, 0.10, 0.50)
 def parse():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
-    ap.add_argument("--workload", default="sweep", choices=("sweep", "star", "batch", "q1"),
-                    help="sweep: operator/format sweep (default); star: star query under every format "
-                         "policy; batch: 512 mixed tasks, one graph vs one launch sequence per task; "
-                         "q1: the simple select-project-sum query")
-    ap.add_argument("--steps", type=int, default=3)
+    ap.add_argument("--workload", default="star", choices=("sweep", "star", "batch", "q1"),
+                    help="star: the fused star query under every format policy (default; the operator/format "
+                         "sweep rides along unless --no-sweep); sweep: operator/format sweep alone; batch: 512 "
+                         "mixed tasks, one graph vs one launch sequence per task; q1: the simple "
+                         "select-project-sum query")
+    ap.add_argument("--no-sweep", action="store_true", help="star: skip the operator/format sweep")
+    ap.add_argument("--no-greedy", action="store_true", help="star: skip the greedy runtime search policy")
+    ap.add_argument("--sweep-steps", type=int, default=2)
+    ap.add_argument("--steps", type=int, default=5)
     ap.add_argument("--warmup", type=int, default=1)
     ap.add_argument("--rows", type=int, default=None, help="rows per column (default per workload)")
     ap.add_argument("--seeds", default="1", help="star: comma-separated instance seeds")
@@ -438,7 +452,7 @@ def plan_roofline(M, plan, alg, workload: str):
     launch / its mean launch time; traffic from the workload's own counter summary."""
     M.sync()
     tune = plan.tune()
-    plan.set_tune(1, tune[1])  # one branch: concurrent kernels would inflate each launch's events
+    plan.set_tune(1, tune[1], tune[2])  # one branch: concurrent kernels would inflate each launch's events
     M.prof_enable(True)
     M.prof_reset()
     plan.run()
@@ -486,78 +500,167 @@ def time_eager(torch, plan, reps):
 
 
 # ------------------------------------------------------------------------------ star query
-POLICIES = ("uncompr", "static", "exhaustive", "learned")
+# Format policies: base columns x intermediates.  "plain" is plain uncompressed execution
+# (uncompressed base columns and intermediates); the others keep the base columns in static
+# BP (the paper's base-data compression) and choose the intermediates' formats.
+POLICIES = ("plain", "uncompr_inter", "static", "exhaustive", "learned", "learned_decode", "greedy")
+FLUSH_BYTES = 2 << 30  # written between timed runs: evicts the 256 MB MALL and the L2s
+
+
+def cold_times(torch, fn, reps, flush):
+    """Per-run GPU times (s) of `reps` runs of fn, each bracketed by events on the current
+    stream and preceded by a 2 GiB write that evicts the caches (not timed)."""
+    ts = []
+    for _ in range(reps):
+        flush.fill_(len(ts) + 1)
+        e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+        e0.record()
+        fn()
+        e1.record()
+        e1.synchronize()
+        ts.append(e0.elapsed_time(e1) / 1e3)
+    return ts
+
+
+def copy_bandwidth(M, torch, log):
+    """Achievable HBM bandwidth: a 4 GiB device-to-device copy (torch) and the library's
+    decode of a 1e9-value uncompressed column (4 B read + 4 B written per value)."""
+    n = 1 << 30
+    src = torch.ones(n, dtype=torch.int32, device="cuda")
+    dst = torch.empty_like(src)
+    col = M.wrap(src)
+    out = {}
+    for name, fn in (("torch_copy", lambda: dst.copy_(src)), ("k_decode", lambda: col.decode(n=n))):
+        fn()
+        torch.cuda.synchronize()
+        e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+        e0.record()
+        for _ in range(5):
+            fn()
+        e1.record()
+        e1.synchronize()
+        out[name] = round(8.0 * n * 5 / (e0.elapsed_time(e1) / 1e3) / 1e9, 1)
+    del col, src, dst
+    log(f"copy bandwidth (read + write GB/s): {out}")
+    return out
 
 
 def run_star(args, M, gen, torch, log):
     from paper_2004_09350_amd import datagen, queries, selector
     n = args.rows or 600_000_000
-    wpath = args.weights or os.path.join(ROOT, "paper_2004_09350_amd", "selector_weights.npy")
-    if os.path.exists(wpath):
-        params = selector.load(wpath)
-        wsrc = os.path.relpath(wpath, ROOT)
-    else:
-        log("no selector weights: training on 300 star plans")
-        X, F, N, _ = selector.collect(300, log=log)
-        params = selector.train(X, selector.targets(F, N), epochs=60, log=log)
-        wsrc = "trained in this run on 300 plans"
+    wpath = args.weights or selector.WEIGHTS
+    sel = selector.load(wpath)
+    wsrc = os.path.relpath(wpath, ROOT)
     if args.calib_copy:
         calib_copy(M, log, M.encode(gen.uniform_bits(3, n, 32), M.fmt(M.UNCOMPR)), n)
+    flush = torch.empty(FLUSH_BYTES // 4, dtype=torch.int32, device="cuda")
+    copy_bw = copy_bandwidth(M, torch, log)
     settings = (("wide", datagen.STAR_WIDE), ("narrow", datagen.STAR_NARROW))
-    results, ue_sum, t_sum = [], 0, 0.0
+    cache = os.path.join(tempfile.gettempdir(), "ms_plan_tune_cache.txt")
+    results, ue_sum, t_sum, t_all = [], 0, 0.0, []
     roof = dom = None
     for seed in [int(x) for x in args.seeds.split(",")]:
         t0 = time.time()
         cols, _ = selector.star_inputs(seed, n)
+        plain_cols, _ = selector.star_inputs(seed, n, fact_fmt=M.fmt(M.UNCOMPR))
+        for k in ("dimattr0", "dimattr1", "dimattr2", "dimattr3", "dimgroup3"):
+            plain_cols[k] = M.morph(cols[k], M.fmt(M.UNCOMPR))
         torch.cuda.synchronize()
         base_fp = sum(c.info()["footprint"] for c in cols.values())
-        log(f"seed {seed}: base columns {base_fp / 1e9:.2f} GB compressed, {time.time() - t0:.1f}s")
-        for sname, sel in settings:
-            thr = datagen.star_thresholds(sel)
+        plain_fp = sum(c.info()["footprint"] for c in plain_cols.values())
+        log(f"seed {seed}: base columns {base_fp / 1e9:.2f} GB static BP, {plain_fp / 1e9:.2f} GB uncompressed, "
+            f"{time.time() - t0:.1f}s")
+        for sname, sel_s in settings:
+            thr = datagen.star_thresholds(sel_s)
             probe = queries.Q3(cols, thr, datagen.STAR_DIM_SIZES, n, extra=("stats", "footprints"))
             probe.plan.run()
-            fps = {k: probe.plan.read(probe.fp_step[k]) for k in probe.names}
-            feats = np.stack([probe.plan.read(probe.stats_step[k]) for k in probe.names])
+            names = list(probe.names)
+            fps = np.stack([probe.plan.read(probe.fp_step[k]) for k in names]).astype(np.uint64)
+            feats = np.stack([probe.plan.read(probe.stats_step[k]) for k in names])
             ref = probe.results()
             probe.plan.close()
-            picks = selector.pick(params, feats)
-            fmts = {"uncompr": queries.uniform_formats(fps, M.UNCOMPR),
-                    "static": queries.uniform_formats(fps, M.STATIC_BP),
-                    "exhaustive": {k: M.fmt(int(np.argmin(f))) for k, f in fps.items()},
-                    "learned": {k: M.fmt(int(p)) for k, p in zip(fps, picks)}}
+            kinds = {"uncompr_inter": np.zeros(len(names), int), "static": np.full(len(names), M.STATIC_BP),
+                     "exhaustive": selector.exhaustive(fps), "learned": selector.pick(sel, feats),
+                     "learned_decode": selector.pick(sel, feats, M.OBJ_DECODE)}
+            kinds["plain"] = kinds["uncompr_inter"]
             row = dict(seed=seed, setting=sname, rows_final=0, policies={})
             for pol in POLICIES:
-                q = queries.Q3(cols, thr, datagen.STAR_DIM_SIZES, n, formats=fmts[pol])
-                q.plan.set_tune(2, 0)
-                tg = time_graph(torch, q.plan, args.steps)
-                te = time_eager(torch, q.plan, max(1, args.steps // 2))
+                if pol == "greedy" and args.no_greedy:
+                    continue
+                greedy_inputs, t_search = {}, 0.0
+                if pol == "greedy":
+                    # the paper's greedy runtime search from plain uncompressed execution: base
+                    # columns first, then the intermediates in plan order
+                    ts0 = time.time()
+                    gcols, gfmt, _, n_trials = queries.greedy_runtime_formats(
+                        plain_cols, thr, datagen.STAR_DIM_SIZES, n, {k: M.fmt(M.UNCOMPR) for k in names}, reps=3)
+                    t_search = time.time() - ts0
+                    greedy_inputs = gcols
+                    kinds["greedy"] = [gfmt[k].kind for k in names]
+                    q = queries.Q3(gcols, thr, datagen.STAR_DIM_SIZES, n, formats=gfmt)
+                else:
+                    fm = {k: M.fmt(int(kk)) for k, kk in zip(names, kinds[pol])}
+                    q = queries.Q3(plain_cols if pol == "plain" else cols, thr, datagen.STAR_DIM_SIZES, n,
+                                   formats=fm)
+                te = cold_times(torch, q.plan.run, max(2, args.steps // 2), flush)
+                tune, _ = q.plan.autotune(reps=2, cache=cache)  # right after the eager runs
+                q.plan.launch()
+                torch.cuda.synchronize()
+                tg = cold_times(torch, q.plan.launch, args.steps, flush)
                 o1, o2 = q.results()
                 if not (np.array_equal(o1, ref[0]) and np.array_equal(o2, ref[1])):
                     raise SystemExit(f"star query answers differ under policy {pol}")
-                fp = sum(int(fps[k][fmts[pol][k].kind]) for k in fps)
+                fp = int(sum(int(fps[i][kinds[pol][i]]) for i in range(len(names))))
                 ue, alg = plan_account(M, q.plan, q.plan.inputs)
                 row["rows_final"] = int(q.plan.column(q.names["P"]).info()["n"])
-                row["policies"][pol] = dict(graph_ms=round(tg * 1e3, 3), eager_ms=round(te * 1e3, 3),
-                                            intermediates_bytes=fp, ue_gbs=round(ue / tg / 1e9, 1))
+                tgm = float(np.mean(tg))
+                row["policies"][pol] = dict(
+                    graph_ms_mean=round(tgm * 1e3, 3), graph_ms_median=round(float(np.median(tg)) * 1e3, 3),
+                    eager_ms_mean=round(float(np.mean(te)) * 1e3, 3),
+                    eager_ms_median=round(float(np.median(te)) * 1e3, 3), tune=list(tune),
+                    intermediates_bytes=fp,
+                    base_bytes=(plain_fp if pol == "plain" else base_fp if pol != "greedy" else
+                                sum(c.info()["footprint"] for c in q.plan.inputs)),
+                    ue_gbs=round(ue / tgm / 1e9, 1), hbm_frac=round(sum(alg.values()) / tgm / 1e9 / HBM_PEAK_GBS, 4))
                 if pol == "learned":
                     ue_sum += ue
-                    t_sum += tg
+                    t_sum += tgm
+                    t_all += tg
                     if roof is None:
                         roof, dom = plan_roofline(M, q.plan, alg, "star")
+                if pol == "greedy":
+                    row["policies"][pol].update(
+                        search_s=round(t_search, 1), trials=n_trials,
+                        base_kinds={queries.Q3_INPUTS[j]: KIND_NAMES[int(c.info()["kind"])]
+                                    for j, c in enumerate(q.plan.inputs)},
+                        intermediate_kinds={k: KIND_NAMES[int(kk)] for k, kk in zip(names, kinds["greedy"])})
                 q.plan.close()
-                del q
-            ex = row["policies"]["exhaustive"]["intermediates_bytes"]
-            row["regret_learned"] = round(row["policies"]["learned"]["intermediates_bytes"] / ex - 1, 5)
+                del q, greedy_inputs
+            P = row["policies"]
+            ex = P["exhaustive"]["intermediates_bytes"]
+            row["regret_learned"] = round(P["learned"]["intermediates_bytes"] / ex - 1, 5)
+            row["regret_learned_decode"] = round(P["learned_decode"]["intermediates_bytes"] / ex - 1, 5)
+            row["learned_vs_plain_graph"] = round(P["plain"]["graph_ms_mean"] / P["learned"]["graph_ms_mean"], 3)
+            row["learned_vs_plain_eager"] = round(P["plain"]["eager_ms_mean"] / P["learned"]["eager_ms_mean"], 3)
+            if "greedy" in P:
+                row["time_regret_vs_greedy"] = {k: round(P[k]["graph_ms_mean"] / P["greedy"]["graph_ms_mean"] - 1, 4)
+                                                for k in P if k != "greedy"}
+            row["footprint_learned_vs_plain"] = round(
+                (P["learned"]["intermediates_bytes"] + base_fp) / (P["plain"]["intermediates_bytes"] + plain_fp), 4)
             results.append(row)
             log(json.dumps(row))
-        del cols
-    res = base_line(args, "uncompressed-equivalent GB/s of the star query (learned formats, captured graph)",
+        del cols, plain_cols
+    del flush
+    res = base_line(args, "uncompressed-equivalent GB/s of the fused star query (learned formats, captured graph, "
+                          "cold) + %HBM roofline; footprint vs exhaustive",
                     round(ue_sum / t_sum / 1e9, 2), "GB/s", t_sum / len(results),
                     f"star query: {n}-row fact table, 4 foreign keys over dimensions of "
-                    f"{'/'.join(str(d) for d in datagen.STAR_DIM_SIZES)} rows, 2 measures, semi-joins via "
-                    "dimension bitmaps, intersect of 4 position lists, group-sum into 250 groups; wide and narrow "
-                    "filters", {"rows": n, "selector_weights": wsrc})
-    res.update(roofline=roof, dominant_kernel=dom, runs=results, source_sha=source_sha())
+                    f"{'/'.join(str(d) for d in datagen.STAR_DIM_SIZES)} rows, 2 measures, static-BP base columns, "
+                    "semi-joins via dimension bitmaps, intersect of 4 position lists, group-sum into 250 groups; "
+                    "wide and narrow filters", {"rows": n, "selector": wsrc})
+    res.update(ms_per_step_median=round(float(np.median(t_all)) * 1e3, 3), roofline=roof, dominant_kernel=dom,
+               runs=results, copy_bandwidth_gbs=copy_bw, source_sha=source_sha(),
+               protocol="each timed run preceded by a 2 GiB device write (not timed); HIP events per run")
     if not args.no_cpu_baseline:
         res["cpu_baseline"] = cpu_baseline_star(min(n, args.cpu_rows or 40_000_000))
     return res
@@ -567,20 +670,10 @@ def _sectors(pos) -> int:
     return int(np.unique(np.asarray(pos, np.int64) >> 4).size)
 
 
-def cpu_baseline_star(rows: int):
-    """The oracle's star query (wide filters) on a bounded fact table, single thread;
-    bytes counted by the rules of plan_account."""
-    import oracle.queries as OQ
+def _star_ue(it, rows) -> int:
+    """Uncompressed-equivalent bytes of one star query over `rows` fact rows (the rules of
+    plan_account)."""
     from paper_2004_09350_amd import datagen
-    cols = datagen.star_columns(1, rows)
-    thr = datagen.star_thresholds(datagen.STAR_WIDE)
-    t0 = time.perf_counter()
-    reps = 0
-    while reps == 0 or time.perf_counter() - t0 < 10.0:  # repeat to a measurable CPU time
-        r = OQ.q3(cols, thr, datagen.STAR_DIM_SIZES)
-        reps += 1
-    dt = (time.perf_counter() - t0) / reps
-    it = r["intermediates"]
     D = datagen.STAR_DIM_SIZES
     ue = 0
     for d in range(4):
@@ -592,9 +685,44 @@ def cpu_baseline_star(rows: int):
     P = it["P"]
     ue += 3 * (8 * P.size + 64 * _sectors(P)) + 8 * it["kp"].size + 64 * _sectors(it["kp"])
     ue += 2 * (4 * 2 * P.size + 8 * 250)
-    return dict(value=round(ue / dt / 1e9, 4), unit="GB/s", cores=1, kind="oracle",
-                sample=f"the star query (wide filters) on a {rows}-row fact table, single thread, "
-                       f"{reps} runs of {dt:.2f} s", seconds=round(dt * reps, 2))
+    return ue
+
+
+def cpu_baseline_star(rows: int):
+    """The oracle's star query (wide filters) on a bounded fact table: single thread, then
+    over fact-row slices on all host cores (the plan is row-local up to its additive
+    group-sums, and the C oracle releases the interpreter lock)."""
+    from concurrent.futures import ThreadPoolExecutor
+
+    import oracle.queries as OQ
+    from paper_2004_09350_amd import datagen
+    cols = datagen.star_columns(1, rows)
+    thr = datagen.star_thresholds(datagen.STAR_WIDE)
+    t0 = time.perf_counter()
+    r = OQ.q3(cols, thr, datagen.STAR_DIM_SIZES)
+    dt1 = time.perf_counter() - t0
+    ue = _star_ue(r["intermediates"], rows)
+    nproc = os.cpu_count() or 1
+    workers = max(1, min(16, nproc))  # the GPU box's CPU share is 16 cores
+    bounds = [(r0, min(rows, r0 + -(-rows // workers))) for r0 in range(0, rows, -(-rows // workers))]
+
+    def part(b):
+        sub = {k: (v[b[0]:b[1]] if not k.startswith("dim") else v) for k, v in cols.items()}
+        return OQ.q3(sub, thr, datagen.STAR_DIM_SIZES)
+
+    t0 = time.perf_counter()
+    with ThreadPoolExecutor(workers) as ex:
+        parts = list(ex.map(part, bounds))
+    dtn = time.perf_counter() - t0
+    with np.errstate(over="ignore"):
+        tot = np.sum(np.stack([p["out1"] for p in parts]), axis=0, dtype=np.uint64)
+    if not np.array_equal(tot, r["out1"]):
+        raise SystemExit("sliced oracle star query differs from the whole one")
+    return dict(value=round(ue / dtn / 1e9, 4), unit="GB/s", cores=workers, kind="oracle",
+                single_thread_value=round(ue / dt1 / 1e9, 4), nproc=nproc,
+                sample=f"the star query (wide filters) on a {rows}-row fact table: {dt1:.2f} s on one thread, "
+                       f"{dtn:.2f} s over {len(bounds)} row slices on {workers} threads (nproc {nproc})",
+                seconds=round(dt1 + dtn, 2))
 
 
 # ------------------------------------------------------------------------------ batch
@@ -661,6 +789,7 @@ def run_batch(args, M, gen, torch, log):
     cache = os.path.join(tempfile.gettempdir(), "ms_plan_tune_cache.txt")
     best, best_ms = plan.autotune(reps=2, cache=cache)
     tg = time_graph(torch, plan, reps)
+    arena = plan.arena_bytes()  # read before plan_roofline's eager run drops the captured graph
     log(f"autotuned {best} ({best_ms:.2f} ms in tuning), graph {tg * 1e3:.2f} ms")
     ue, alg = plan_account(M, plan, inputs)
     roof, dom = plan_roofline(M, plan, alg, "batch")
@@ -671,7 +800,7 @@ def run_batch(args, M, gen, torch, log):
                     {"tasks": T, "rows_total": rows})
     res.update(graph_ms=round(tg * 1e3, 3), eager_one_stream_ms=round(te1 * 1e3, 3),
                eager_8_streams_ms=round(te8 * 1e3, 3), speedup_vs_one_launch_sequence_per_task=round(te1 / tg, 3),
-               tune={"branches": best[0], "wg_per_cu": best[1]}, arena_gb=round(plan.arena_bytes() / 1e9, 2),
+               tune={"branches": best[0], "wg_per_cu": best[1], "chunks_per_wg": best[2]}, arena_gb=round(arena / 1e9, 2),
                roofline=roof, dominant_kernel=dom, source_sha=source_sha())
     if not args.no_cpu_baseline:
         res["cpu_baseline"] = cpu_baseline_batch(spec, cap=args.cpu_rows or 1_000_000, max_tasks=len(spec))
@@ -769,6 +898,13 @@ def main():
         res = run_sweep(args, M, gen, torch, log)
     elif args.workload == "star":
         res = run_star(args, M, gen, torch, log)
+        if not args.no_sweep:
+            sargs = argparse.Namespace(**vars(args))
+            sargs.steps, sargs.warmup, sargs.rows, sargs.no_cpu_baseline = args.sweep_steps, 1, None, True
+            sargs.calib_copy = False
+            sw = run_sweep(sargs, M, gen, torch, log)
+            res["sweep"] = {k: sw[k] for k in ("metric", "value", "unit", "ms_per_step", "hbm_frac_step", "roofline",
+                                               "dominant_kernel", "config")}
     elif args.workload == "batch":
         res = run_batch(args, M, gen, torch, log)
     else:

@@ -168,6 +168,29 @@ ms_status ms_group_sum(const ms_column *groups, const ms_column *vals, uint32_t 
 ms_status ms_group_sum_noalloc(const ms_column *groups, const ms_column *vals, uint32_t G, uint64_t *dev_out,
                                void *stream);
 
+/* Element-wise arithmetic on two columns of equal length (section 4.2 lists calc among
+ * the operators; the star-schema plans of section 5.2 compute measures from two columns):
+ * out_i = a_i op b_i in unsigned 32-bit arithmetic modulo 2^32.  Lengths that differ raise
+ * MS_ERR_LENGTH_MISMATCH (at once when both are known on the host, else on the device). */
+typedef enum { MS_CALC_ADD = 0, MS_CALC_SUB = 1, MS_CALC_MUL = 2 } ms_calc_op;
+ms_status ms_calc(const ms_column *a, const ms_column *b, uint32_t op, ms_format fmt, void *stream, ms_column **out);
+/* Join of a foreign-key column with a dimension whose qualifying rows are marked in
+ * dev_bitmap (as ms_semijoin; the star plans of section 5.2 join fact and dimension tables
+ * on dense surrogate keys, i.e. dimension row positions), emitting position pairs: *left =
+ * the ascending fact positions i with keys_i < domain and bit keys_i set, in fmt_left;
+ * *right = the dimension positions keys_i of those rows, in the same order, in fmt_right.
+ * Both columns are owned by the caller. */
+ms_status ms_join(const ms_column *keys, const uint32_t *dev_bitmap, uint64_t domain, ms_format fmt_left,
+                  ms_format fmt_right, void *stream, ms_column **left, ms_column **right);
+/* Group-by with group ids assigned from the data (section 4.2's grouping, whose ids the
+ * group-based aggregation consumes): *distinct = the distinct keys in ascending order, in
+ * fmt_keys; *ids = for every row the rank of its key among them (0 .. #groups - 1), in
+ * fmt_ids, ready for ms_group_sum with G >= #groups (the count is *distinct's element
+ * count).  Every key must be below `domain` (1 .. 2^28; the presence bitmap takes domain / 8
+ * bytes of scratch), else MS_ERR_OUT_OF_RANGE is raised on the device. */
+ms_status ms_group_by(const ms_column *keys, uint64_t domain, ms_format fmt_ids, ms_format fmt_keys, void *stream,
+                      ms_column **ids, ms_column **distinct);
+
 /* Exact footprint in bytes of the column in each of the six formats (section 5.2:
  * exhaustive format selection tries every format; footprints are what it compares).
  * dev_bytes6[kind] (device, 6 x uint64, indexed by ms_kind) receives the size that
@@ -199,10 +222,14 @@ ms_status ms_footprints(const ms_column *in, uint64_t *dev_bytes6, void *stream)
  * An empty column gives all zeros except [20] = 1.  Computed in double, stored as float. */
 ms_status ms_stats(const ms_column *in, float *dev_features32, void *stream);
 
-/* Learned format selector: a 32-64-64-6 perceptron with ReLU hidden layers that maps
- * the 32 features to the predicted size of each format (bits per value / 32, index =
- * ms_kind); the selection is the smallest output (section 5.2 selects formats by a
- * cost model over data characteristics; the network is this library's cost model).
+/* Learned format selection (section 5.2 selects formats with a cost model over data
+ * characteristics that estimates the compression rate and the (de)compression performance
+ * of each algorithm).  The model here is a 32-64-64-6 perceptron with ReLU hidden layers
+ * that maps the 32 features to one cost per format (index = ms_kind); the selection is the
+ * smallest output.  The library trains two of them (ms_selector below): a size network,
+ * whose targets are t_k = log2(1 + 8 * footprint_k / n) / 6 (log-scaled bits per value),
+ * and a decode-cost network, whose targets are t_k = log2(1 + 1000 * ns_k / n) / 16
+ * (log-scaled picoseconds per value of decoding format k).
  * Parameters: one device float vector of ms_mlp_nparam() = 6662 values, row-major
  * W1[64][32], b1[64], W2[64][64], b2[64], W3[6][64], b3[6].  All buffers device,
  * float, batch-major (x: n x 32, y and targets: n x 6). */
@@ -220,6 +247,73 @@ ms_status ms_mlp_grad(const float *params, const float *x, const float *t, uint6
  * with params. */
 ms_status ms_adam_step(float *params, const float *grad, float *m, float *v, uint64_t step, float lr, float beta1,
                        float beta2, float eps, void *stream);
+
+/* Selector: the size network and the decode-cost network with their parameters on the
+ * device (section 5.2's cost model covers both the compression rate and the (de)compression
+ * performance).  ms_selector_create copies the initial parameters (host, 6662 floats each,
+ * drawn by the caller) to the device.  Every call below is asynchronous on `stream` unless
+ * it says otherwise. */
+typedef struct ms_selector ms_selector;
+enum { MS_NET_SIZE = 0, MS_NET_COST = 1 };
+enum { MS_OBJ_FOOTPRINT = 0, MS_OBJ_DECODE = 1 };  /* which network's costs a pick minimises */
+ms_status ms_selector_create(const float *host_init_size, const float *host_init_cost, ms_selector **out);
+/* Waits for the device, then frees the selector. */
+ms_status ms_selector_destroy(ms_selector *sel);
+/* Copies network `net`'s 6662 parameters to dev_dst (device, 6662 floats). */
+ms_status ms_selector_params(const ms_selector *sel, uint32_t net, float *dev_dst, void *stream);
+/* Bit k set: network k was trained by ms_selector_train or loaded as trained. */
+uint32_t ms_selector_trained(const ms_selector *sel);
+/* File format: 8 bytes "MSSEL001", uint32 6662, uint32 2, uint32 trained bits, then the
+ * size network's and the decode-cost network's parameters (float32, little-endian).  Both
+ * calls synchronise the device; a file of any other shape is MS_ERR_INVALID_ARG. */
+ms_status ms_selector_save(const ms_selector *sel, const char *path);
+ms_status ms_selector_load(const char *path, ms_selector **out);
+/* Training targets on the device from the engine's labels, for `count` columns:
+ * size: dev_bytes6 (count x 6 uint64 footprints, as ms_footprints writes them) and dev_n
+ * (count uint64 element counts; 0 counts as 1) -> dev_t6[i][k] = log2(1 + 8 * bytes / n) / 6;
+ * cost: dev_ns6 (count x 6 float decode times in ns, as ms_decode_cost measures them) ->
+ * dev_t6[i][k] = log2(1 + 1000 * ns / n) / 16.  Computed in double, stored as float. */
+ms_status ms_selector_size_targets(const uint64_t *dev_bytes6, const uint64_t *dev_n, uint64_t count, float *dev_t6,
+                                   void *stream);
+ms_status ms_selector_cost_targets(const float *dev_ns6, const uint64_t *dev_n, uint64_t count, float *dev_t6,
+                                   void *stream);
+/* Mini-batch Adam on network `net` over `count` samples (dev_x count x 32, dev_t count x 6):
+ * `epochs` passes; pass e visits the rows in the order j -> (a_e * j + b_e) mod count, a
+ * permutation drawn from SplitMix64 (Steele, Lea and Flood 2014; mix64 its output function,
+ * gamma = 0x9E3779B97F4A7C15): key = mix64(seed), x = mix64(key + (2e + 1) * gamma),
+ * y = mix64(key + (2e + 2) * gamma), a_e = 1 + x mod (count - 1), then a_e + 1 (after
+ * count - 1 comes 1) until gcd(a_e, count) = 1, b_e = y mod count (a = 1, b = 0 when
+ * count = 1).  Consecutive `batch` positions form a batch (the last one may be short); each
+ * batch takes the gradient ms_mlp_grad computes on its rows and one Adam step (Adam starts
+ * from zero moments at step 1 in every call).
+ * host_last_loss (may be NULL; else the call synchronises `stream`) receives the mean batch
+ * loss of the last pass.  count must be in [1, 2^31), batch in [1, 2^26). */
+typedef struct {
+  uint32_t epochs, batch;
+  float lr, beta1, beta2, eps;
+  uint64_t seed;
+} ms_train_cfg;
+ms_status ms_selector_train(ms_selector *sel, uint32_t net, const float *dev_x, const float *dev_t, uint64_t count,
+                            const ms_train_cfg *cfg, float *host_last_loss, void *stream);
+/* Inference: dev_kinds[i] (may be NULL) = the format of least predicted cost under
+ * `objective` (MS_OBJ_FOOTPRINT: the size network, MS_OBJ_DECODE: the decode-cost network),
+ * ties to the lower kind; dev_pred6 (may be NULL) = that network's count x 6 outputs. */
+ms_status ms_selector_pick(const ms_selector *sel, uint32_t objective, const float *dev_x, uint64_t count,
+                           uint32_t *dev_kinds, float *dev_pred6, void *stream);
+/* Exhaustive selection (section 5.2: every format is tried per column and the smallest
+ * physical size kept; column footprints add up, so the per-column choice is the plan's
+ * optimum).  ms_select_exhaustive writes the column's six exact footprints (as
+ * ms_footprints) to dev_bytes6 and the least one's kind, ties to the lower kind, to
+ * *dev_kind (device uint32).  ms_select_argmin does the choice for `count` footprint rows
+ * already on the device (count x 6 uint64 -> count uint32). */
+ms_status ms_select_exhaustive(const ms_column *in, uint64_t *dev_bytes6, uint32_t *dev_kind, void *stream);
+ms_status ms_select_argmin(const uint64_t *dev_bytes6, uint64_t count, uint32_t *dev_kinds, void *stream);
+/* Decode-cost labels: morphs the column into each of the six formats (static BP at the
+ * automatic width) and times `reps` decodes of each (ms_column_decode, HIP events on
+ * `stream`, after one untimed decode); host_ns6[k] receives the mean nanoseconds per decode
+ * of format k.  Allocates the six trial columns and a decode buffer through the allocator;
+ * synchronises `stream`. */
+ms_status ms_decode_cost(const ms_column *in, uint32_t reps, float *host_ns6, void *stream);
 
 /* ------------------------------------------------------------------------------------
  * Plans (section 3.3: a query is a plan of operators; every intermediate is materialised
@@ -251,11 +345,14 @@ typedef struct {
   ms_format out;        /* output format of column-producing steps */
 } ms_step;
 
-/* Launch shape: parallel branches (1..16) and the persistent-grid cap in workgroups per
- * compute unit (1..32, or 0 for each operator's default: 4, and 3 for project). */
+/* Launch shape: parallel branches (1..16), the persistent-grid cap in workgroups per
+ * compute unit (1..32, or 0 for each operator's default: 4, and 3 for project) and the
+ * chunks of 512 values per workgroup that size the grid below that cap (1..64, or 0 for
+ * the default of 4): grid = min(ceil(chunks / chunks_per_wg), CUs x wg_per_cu). */
 typedef struct {
   uint32_t branches;
   uint32_t wg_per_cu;
+  uint32_t chunks_per_wg;
 } ms_tune;
 
 typedef struct ms_plan ms_plan;
@@ -268,6 +365,8 @@ ms_status ms_plan_destroy(ms_plan *plan);
 /* Change a step's output format or the launch shape (drops a captured graph). */
 ms_status ms_plan_set_format(ms_plan *plan, uint32_t step, ms_format fmt);
 ms_status ms_plan_set_tune(ms_plan *plan, const ms_tune *tune);
+/* The output format a step currently has (as set at creation or by ms_plan_set_format). */
+ms_status ms_plan_get_format(const ms_plan *plan, uint32_t step, ms_format *fmt);
 ms_status ms_plan_get_tune(const ms_plan *plan, ms_tune *tune);
 /* Eager run on `stream`: frees the previous run's results (after synchronising), then
  * launches step by step through the allocator given to ms_init. */
@@ -286,8 +385,9 @@ ms_status ms_plan_read_result(const ms_plan *plan, uint32_t step, void *host_dst
                               uint64_t *copied);
 /* Arena bytes of the captured graph (0 before the first ms_plan_launch). */
 uint64_t ms_plan_arena_bytes(const ms_plan *plan);
-/* Autotuner: times ms_plan_launch for every (branches, wg_per_cu) candidate over `reps`
- * replays and keeps the fastest.  With cache_path, a tune recorded there for the same
+/* Autotuner: times ms_plan_launch for every (branches in {1, 2, 4, 8}, wg_per_cu in {0, 2,
+ * 4, 8, 16}) candidate over `reps` replays, then chunks_per_wg in {1, 2, 8, 16} at the best
+ * of those, and keeps the fastest.  With cache_path, a tune recorded there for the same
  * plan signature (steps and input shapes) is applied without timing, and new results are
  * appended.  best (may be NULL) receives the tune; best_ms (may be NULL) its time. */
 ms_status ms_plan_autotune(ms_plan *plan, void *stream, uint32_t reps, const char *cache_path, ms_tune *best,

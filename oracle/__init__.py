@@ -258,3 +258,86 @@ def adam_step(params, grad, m, v, step, lr, beta1=0.9, beta2=0.999, eps=1e-8):
     """In-place Adam update of float64 arrays params, m, v."""
     lib().or_adam_step(_p(params), _p(np.ascontiguousarray(grad, np.float64)), _p(m), _p(v), step, lr,
                        beta1, beta2, eps, params.size)
+
+
+# ----------------------------------------------------------------------------- format selection
+def exhaustive_choice(bytes6) -> np.ndarray:
+    """Section 5.2's exhaustive selection for rows of six footprints: the format of least
+    physical size, scanning the formats in their fixed order so that ties keep the lower
+    format number."""
+    F = np.asarray(bytes6, np.uint64).reshape(-1, 6)
+    out = np.zeros(F.shape[0], np.int64)
+    for i in range(F.shape[0]):
+        best = 0
+        for k in range(1, 6):
+            if int(F[i, k]) < int(F[i, best]):
+                best = k
+        out[i] = best
+    return out
+
+
+def size_targets(bytes6, n) -> np.ndarray:
+    """Targets of the size network: t_k = log2(1 + bits per value of format k) / 6, with
+    bits per value = 8 * footprint_k / n (an empty column counts as n = 1), in float64."""
+    F = np.asarray(bytes6, np.float64).reshape(-1, 6)
+    nv = np.maximum(np.asarray(n, np.float64).reshape(-1, 1), 1.0)
+    return np.log2(1.0 + 8.0 * F / nv) / 6.0
+
+
+def cost_targets(ns6, n) -> np.ndarray:
+    """Targets of the decode-cost network: t_k = log2(1 + picoseconds per value spent
+    decoding format k) / 16, from measured nanoseconds per decode (negative times count
+    as 0; an empty column counts as n = 1), in float64."""
+    C = np.maximum(np.asarray(ns6, np.float64).reshape(-1, 6), 0.0)
+    nv = np.maximum(np.asarray(n, np.float64).reshape(-1, 1), 1.0)
+    return np.log2(1.0 + 1000.0 * C / nv) / 16.0
+
+
+# ----------------------------------------------------------------------------- wider operator set
+# The operators of the paper's star-schema plans beyond select / semi-join / intersect /
+# project / aggregation (section 4.2's operator list, section 5.2's SSB plans): element-wise
+# arithmetic on two columns ("calc"), a join that emits position pairs, and a group-by that
+# assigns group ids itself.
+CALC_ADD, CALC_SUB, CALC_MUL = range(3)
+
+
+def calc(a, b, op: int) -> np.ndarray:
+    """out_i = a_i (+, -, *) b_i, unsigned 32-bit arithmetic wrapping modulo 2^32."""
+    a = _u32(a).astype(np.uint64)
+    b = _u32(b).astype(np.uint64)
+    if a.size != b.size:
+        raise OracleError(ERR_LENGTH_MISMATCH, "calc")
+    with np.errstate(over="ignore"):
+        if op == CALC_ADD:
+            r = a + b
+        elif op == CALC_SUB:
+            r = a + (np.uint64(1 << 32) - b)
+        elif op == CALC_MUL:
+            r = a * b  # both factors < 2^32: the product fits 64 bits
+        else:
+            raise OracleError(ERR_INVALID_ARG, "calc")
+    return (r & np.uint64(0xFFFFFFFF)).astype(np.uint32)
+
+
+def join_pairs(keys, bitmap, domain: int):
+    """Join of a foreign-key column with a dimension whose qualifying rows are marked in
+    `bitmap` (bit k of word k // 32): the ascending fact positions i with keys_i < domain
+    and bit keys_i set (left), and the matching dimension positions keys_i (right)."""
+    k = _u32(keys)
+    bm = _u32(bitmap)
+    left = []
+    for i in range(k.size):
+        x = int(k[i])
+        if x < domain and (int(bm[x >> 5]) >> (x & 31)) & 1:
+            left.append(i)
+    left = np.asarray(left, np.uint32)
+    return left, k[left.astype(np.int64)].astype(np.uint32) if left.size else np.zeros(0, np.uint32)
+
+
+def group_by(keys):
+    """Group ids assigned from the data: the distinct keys in ascending order, and for
+    every row the rank of its key among them (ids 0 .. #groups - 1)."""
+    k = _u32(keys)
+    distinct = np.array(sorted(set(int(x) for x in k)), np.uint32)
+    rank = {int(v): i for i, v in enumerate(distinct)}
+    return np.array([rank[int(x)] for x in k], np.uint32), distinct

@@ -18,7 +18,9 @@ COMMON = ["-O3", "-std=c++17", "-fPIC", f"--offload-arch={ARCH}",
 # (MS_OK = UNCOMPR 0 .. FOR_DYN_BP 4) so that the instantiations build in parallel.
 _PER_KIND = [(src, [f"-DMS_OK={k}"]) for src in ("ms_project.hip", "ms_morph.hip") for k in range(5)]
 LIBS = {
-    "libmorphgpu.so": _PER_KIND + [("ms_kernels.hip", []), ("ms_api.hip", []), ("ms_plan.hip", [])],
+    "libmorphgpu.so": _PER_KIND + [("ms_kernels.hip", []), ("ms_api.hip", []), ("ms_plan.hip", []),
+                                   ("ms_selector.hip", []), ("ms_pred.hip", []),
+                                   ("ms_ops2.hip", [])],
     "libmsgen.so": [("datagen.hip", [])],
 }
 JOBS = max(1, min(16, int(os.environ.get("MAX_JOBS", os.cpu_count() or 1))))

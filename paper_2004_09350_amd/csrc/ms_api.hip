@@ -6,6 +6,7 @@
 #include <atomic>
 #include <cstdio>
 #include <cstring>
+#include <functional>
 #include <string>
 #include <vector>
 
@@ -33,6 +34,7 @@ struct ms_column {
 namespace {
 
 constexpr uint64_t kUnknown = ~0ull;
+constexpr uint64_t kGroupByMaxDomain = 1ull << 28;  // presence bitmap of at most 32 MB
 
 ms_alloc_fn g_alloc = nullptr;
 ms_free_fn g_free = nullptr;
@@ -54,6 +56,7 @@ ms_status hip_fail(hipError_t e, const char *what) {
 // the registered callbacks, else to hipMallocAsync.
 thread_local rt::Arena *t_arena = nullptr;
 thread_local unsigned t_wg_per_cu = 0;  // 0: each operator's default
+thread_local unsigned t_chunks_per_wg = 0;  // 0: the default of four
 
 void *dev_alloc(uint64_t bytes, void *stream) {
   if (bytes == 0) bytes = 256;
@@ -102,14 +105,17 @@ struct Scratch {
 
 uint64_t align256(uint64_t x) { return (x + 255) & ~255ull; }
 
-// Persistent grid: one workgroup per four chunks, capped at wg_per_cu workgroups per CU
-// (the plan's tune, else the operator's default: a multiple of the workgroups one CU
-// holds at once, so that the last round of workgroups is not a partial one).
+// Persistent grid: one workgroup per four chunks (or the plan's chunks_per_wg), capped at
+// wg_per_cu workgroups per CU (the plan's tune, else the operator's default: a multiple of
+// the workgroups one CU holds at once, so that the last round of workgroups is not a
+// partial one).
 constexpr unsigned kWgPerCuDefault = 4;
 constexpr unsigned kWgPerCuProject = 3;  // the gather kernels hold three workgroups per CU
+constexpr unsigned kChunksPerWgDefault = 4;
 unsigned grid_for(uint64_t chunks, unsigned dflt = kWgPerCuDefault) {
   uint64_t max_wg = (uint64_t)g_cus * (t_wg_per_cu ? t_wg_per_cu : dflt);
-  uint64_t g = (chunks + 3) / 4;
+  const uint64_t cpw = t_chunks_per_wg ? t_chunks_per_wg : kChunksPerWgDefault;
+  uint64_t g = (chunks + cpw - 1) / cpw;
   if (g < 1) g = 1;
   if (g > max_wg) g = max_wg;
   return (unsigned)g;
@@ -386,6 +392,7 @@ void set_thread_arena(Arena *a) { t_arena = a; }
 Arena *thread_arena() { return t_arena; }
 void set_thread_wg_per_cu(unsigned w) { t_wg_per_cu = w; }
 unsigned thread_wg_per_cu() { return t_wg_per_cu; }
+void set_thread_chunks_per_wg(unsigned c) { t_chunks_per_wg = c; }
 void *alloc(uint64_t bytes, void *stream) { return dev_alloc(bytes, stream); }
 void free(void *p, uint64_t bytes, void *stream) { dev_free(p, bytes, stream); }
 unsigned cus() { return (unsigned)g_cus; }
@@ -905,6 +912,153 @@ ms_status ms_group_sum_noalloc(const ms_column *groups, const ms_column *vals, u
   st = group_sum_launch(groups, vals, G_groups, dev_out, G, partials, stream);
   prof_suspend(was_suspended);
   return st;
+}
+
+// ---------------------------------------------------------------------------------------------
+// The wider operator set: calc, join with position pairs, group-by with its own group ids.
+
+// A count-known transform of one or two columns into fmt (RLE outputs go through an
+// uncompressed column that is then morphed).
+static ms_status transform_out(uint64_t n_cap, const ColHdr *n_src, ms_format fmt, void *stream, ms_column **out,
+                               const std::function<hipError_t(const ColView &, unsigned, unsigned *)> &launch) {
+  *out = nullptr;
+  ms_status st = check_fmt(fmt);
+  if (st != MS_OK) return st;
+  const ms_format direct = fmt.kind == MS_RLE ? ms_format{MS_UNCOMPR, 0} : fmt;
+  const unsigned G = grid_for(chunks_of(n_cap));
+  unsigned auto_w = 0;
+  ms_column *o = nullptr;
+  st = make_output(direct, n_cap, stream, &o, auto_w);
+  if (st != MS_OK) return st;
+  Scratch sc(stream);
+  unsigned *partials = sc.get<unsigned>(2 * G);
+  unsigned *narrow_tmp = (direct.kind == MS_STATIC_BP && auto_w) ? sc.get<unsigned>(n_cap + kPayloadSlackWords) : nullptr;
+  if (!sc.ok) {
+    free_column(o);
+    return fail(MS_ERR_OOM, "scratch allocation failed");
+  }
+  hipError_t e = launch(o->v, G, partials);
+  if (e == hipSuccess) e = finish_produced(o->v, n_src, partials, G, auto_w, 0, narrow_tmp, stream);
+  st = launched(e, &o);
+  if (st != MS_OK) return st;
+  if (fmt.kind != MS_RLE) {
+    *out = o;
+    return MS_OK;
+  }
+  st = ms_morph(o, fmt, stream, out);
+  free_column(o);
+  return st;
+}
+
+ms_status ms_calc(const ms_column *a, const ms_column *b, uint32_t op, ms_format fmt, void *stream, ms_column **out) {
+  if (!out) return fail(MS_ERR_INVALID_ARG, "out is NULL");
+  *out = nullptr;
+  ms_status st = check_init();
+  if (st != MS_OK) return st;
+  if (!a || !b) return fail(MS_ERR_INVALID_ARG, "input is NULL");
+  if (op > MS_CALC_MUL) return fail(MS_ERR_INVALID_ARG, "unknown calc operation");
+  if (a->n_host != kUnknown && b->n_host != kUnknown && a->n_host != b->n_host)
+    return fail(MS_ERR_LENGTH_MISMATCH, "calc inputs differ in length");
+  const uint64_t n_cap = a->n_host != kUnknown ? a->n_host : a->n_cap;
+  st = transform_out(n_cap, a->v.hdr, fmt, stream, out, [&](const ColView &o, unsigned G, unsigned *partials) {
+    return launch_calc(a->v, b->v, op, o, G, partials, stream);
+  });
+  if (st == MS_OK) (*out)->n_host = a->n_host;
+  return st;
+}
+
+ms_status ms_join(const ms_column *keys, const uint32_t *dev_bitmap, uint64_t domain, ms_format fmt_left,
+                  ms_format fmt_right, void *stream, ms_column **left, ms_column **right) {
+  if (!left || !right) return fail(MS_ERR_INVALID_ARG, "out is NULL");
+  *left = *right = nullptr;
+  ms_status st = ms_semijoin(keys, dev_bitmap, domain, fmt_left, stream, left);
+  if (st != MS_OK) return st;
+  st = ms_project(keys, *left, fmt_right, stream, right);
+  if (st != MS_OK) {
+    free_column(*left);
+    *left = nullptr;
+  }
+  return st;
+}
+
+ms_status ms_group_by(const ms_column *keys, uint64_t domain, ms_format fmt_ids, ms_format fmt_keys, void *stream,
+                      ms_column **ids, ms_column **distinct) {
+  if (!ids || !distinct) return fail(MS_ERR_INVALID_ARG, "out is NULL");
+  *ids = *distinct = nullptr;
+  ms_status st = check_init();
+  if (st != MS_OK) return st;
+  if (!keys) return fail(MS_ERR_INVALID_ARG, "input is NULL");
+  if (domain == 0 || domain > kGroupByMaxDomain)
+    return fail(MS_ERR_INVALID_ARG, "group-by domain must be in [1, 2^28]");
+  st = check_fmt(fmt_ids);
+  if (st == MS_OK) st = check_fmt(fmt_keys);
+  if (st != MS_OK) return st;
+  const uint64_t n_cap = keys->n_host != kUnknown ? keys->n_host : keys->n_cap;
+  const uint64_t C = chunks_of(domain), words = (domain + 31) / 32;
+  Scratch sc(stream);
+  // the bitmap doubles as the emit phase's row-order bitmask: 64 bytes per chunk and one more
+  unsigned *bitmap = reinterpret_cast<unsigned *>(sc.get<unsigned char>(C * 64 + 64));
+  unsigned *block_sums = sc.get<unsigned>((words + 1023) / 1024 + 1);
+  unsigned *wprefix = sc.get<unsigned>(words + 1);
+  if (!sc.ok) return fail(MS_ERR_OOM, "scratch allocation failed");
+  hipError_t e = launch_fill_u32(bitmap, (C * 64 + 64) / 4, 0u, stream);
+  if (e == hipSuccess) e = launch_mark_keys(keys->v, domain, bitmap, grid_for(chunks_of(n_cap)), stream);
+  if (e == hipSuccess) e = launch_word_prefix(bitmap, words, block_sums, wprefix, stream);
+  if (e != hipSuccess) return hip_fail(e, "kernel launch");
+  // ids: the rank of every key
+  st = transform_out(n_cap, keys->v.hdr, fmt_ids, stream, ids, [&](const ColView &o, unsigned G, unsigned *partials) {
+    return launch_rank(keys->v, domain, bitmap, wprefix, o, G, partials, stream);
+  });
+  if (st != MS_OK) return st;
+  (*ids)->n_host = keys->n_host;
+  // distinct keys: the set positions of the bitmap, through the compaction's emit phase
+  const unsigned G = grid_for(C);
+  unsigned auto_w = 0;
+  st = make_output(fmt_keys, domain, stream, distinct, auto_w);
+  if (st != MS_OK) {
+    free_column(*ids);
+    *ids = nullptr;
+    return st;
+  }
+  const bool blocky = fmt_keys.kind != MS_UNCOMPR && fmt_keys.kind != MS_RLE;
+  Scratch se(stream);
+  ColHdr *hdr = reinterpret_cast<ColHdr *>(se.get<unsigned char>(sizeof(ColHdr)));
+  EmitArgs ea;
+  std::memset(&ea, 0, sizeof(ea));
+  ea.in.kind = MS_UNCOMPR;
+  ea.in.hdr = hdr;
+  ea.in.n_cap = domain;
+  ea.out = (*distinct)->v;
+  ea.auto_w = auto_w;
+  ea.bitmask = reinterpret_cast<const unsigned char *>(bitmap);
+  unsigned *seg_count = se.get<unsigned>(G);
+  unsigned *seg_or = se.get<unsigned>(G);
+  ea.seg_count = seg_count;
+  ea.seg_or = seg_or;
+  ea.stage_g = blocky ? se.get<unsigned>(domain + 1) : nullptr;
+  ea.wave_count = se.get<unsigned>(2ull * kWaves * G);
+  ea.partials = se.get<unsigned>(2 * G);
+  unsigned *narrow_tmp = (fmt_keys.kind == MS_STATIC_BP && auto_w) ? se.get<unsigned>(domain + kPayloadSlackWords)
+                                                                  : nullptr;
+  if (!se.ok) {
+    free_column(*ids);
+    free_column(*distinct);
+    *ids = *distinct = nullptr;
+    return fail(MS_ERR_OOM, "scratch allocation failed");
+  }
+  e = launch_set_hdr(hdr, domain, 0, 0, 0, 0, 0, stream);
+  if (e == hipSuccess) e = launch_bitmask_segments(bitmap, domain, G, seg_count, seg_or, stream);
+  if (e == hipSuccess) e = launch_emit(ea, G, stream);
+  if (e == hipSuccess && fmt_keys.kind == MS_STATIC_BP && auto_w)
+    e = finish_produced((*distinct)->v, nullptr, ea.partials, G, 1, 1, narrow_tmp, stream);
+  st = launched(e, distinct);
+  if (st != MS_OK) {
+    free_column(*ids);
+    *ids = nullptr;
+    return st;
+  }
+  (*distinct)->sorted = 1;
+  return MS_OK;
 }
 
 ms_status ms_footprints(const ms_column *in, uint64_t *dev_bytes6, void *stream) {

@@ -66,6 +66,26 @@ hipError_t launch_project_ok(const ColView &pos, const ColView &data, const ColV
                              unsigned *partials, void *s);
 hipError_t launch_morph(const ColView &in, const ColView &out, unsigned auto_w, unsigned G, unsigned *partials,
                         void *s);
+// calc and group-by ids into a block or uncompressed output kind (one unit per kind)
+template <unsigned OK>
+hipError_t launch_calc_ok(const ColView &a, const ColView &b, unsigned op, const ColView &out, unsigned G,
+                          unsigned *partials, void *s);
+template <unsigned OK>
+hipError_t launch_rank_ok(const ColView &keys, unsigned long long domain, const unsigned *bitmap,
+                          const unsigned *wprefix, const ColView &out, unsigned G, unsigned *partials, void *s);
+hipError_t launch_calc(const ColView &a, const ColView &b, unsigned op, const ColView &out, unsigned G,
+                       unsigned *partials, void *s);
+hipError_t launch_rank(const ColView &keys, unsigned long long domain, const unsigned *bitmap,
+                       const unsigned *wprefix, const ColView &out, unsigned G, unsigned *partials, void *s);
+// Group-by support: presence bitmap of the keys (domain bits, zeroed first; keys >= domain
+// raise E_RANGE), per-word exclusive prefix counts of its set bits (block_sums: one word
+// per 1024 bitmap words), and the per-segment counts / position ORs of a row-order bitmap
+// for the compaction's emit phase.
+hipError_t launch_mark_keys(const ColView &keys, unsigned long long domain, unsigned *bitmap, unsigned G, void *s);
+hipError_t launch_word_prefix(const unsigned *bitmap, unsigned long long words, unsigned *block_sums,
+                              unsigned *wprefix, void *s);
+hipError_t launch_bitmask_segments(const unsigned *bitmap, unsigned long long domain, unsigned G, unsigned *seg_count,
+                                   unsigned *seg_or, void *s);
 hipError_t launch_decode(const ColView &in, unsigned *out, unsigned G, void *s);
 hipError_t launch_rle(unsigned mode, const ColView &a, const ColView &b, const ColView &out, unsigned G,
                       unsigned *wave_count, unsigned *partials, void *s);  // wave_count: kWaves * G words

@@ -313,101 +313,6 @@ __global__ __launch_bounds__(kWG) void k_rle_emit_proj(ChunkSrc s, ColView outv,
 }
 
 // ---------------------------------------------------------------------------------------------
-// Compaction phase 1: predicate -> one bit per row, count and OR per segment.
-// mode 0: range predicate ((v - lo) <= span) != neg, emits positions
-// mode 1: bitmap predicate v < domain && bit(v), emits positions (semi-join)
-// mode 2: bitmap predicate on values, emits values, checks strict increase (intersect)
-template <unsigned MODE>
-__global__ __launch_bounds__(kWG) void k_pred(PredArgs a) {
-  extern __shared__ __attribute__((aligned(16))) unsigned ring[];  // ring_shm() bytes
-  __shared__ unsigned long long red[kWaves];
-  __shared__ unsigned redo[kWaves];
-  const InCol in = load_in(a.in);
-  const unsigned lane = lane_id(), w = wave_id(), G = gridDim.x;
-  const unsigned long long C = (in.n + kBlk - 1) / kBlk;
-  unsigned long long cb, ce;
-  segment(C, blockIdx.x, G, cb, ce);
-  unsigned cnt = 0, orv = 0;
-  bool unsorted = false;
-  constexpr unsigned mode = MODE;
-  const unsigned lo = a.lo, span = a.span;
-  const bool neg = a.neg != 0;
-  const unsigned long long domain = a.domain;
-  const unsigned *bitmap = a.bitmap;
-  unsigned char *bitmask = a.bitmask;
-  unsigned *chunk_first = a.chunk_first, *chunk_last = a.chunk_last;
-  // A semi-join bitmap that fits the workgroup's dynamic LDS (kLdsBitmapBits, the size
-  // of the ring that RLE input uses otherwise) is probed there instead of through the
-  // caches; a larger one keeps its first kLdsBitmapBits bits there, which spares the
-  // caches the probes of the keys below that bound.
-  const bool lds_bm = mode == 1 && in.kind != RLE;
-  const unsigned long long lds_bits = min(domain, kLdsBitmapBits);
-  if (lds_bm) {
-    const unsigned nw = (unsigned)((lds_bits + 31) / 32);
-    for (unsigned t = threadIdx.x; t < nw; t += kWG) ring[t] = bitmap[t];
-    __syncthreads();
-  }
-  stream_chunks(in, cb, ce, w, lane, ring + w * kRing * kBlk, a.in.hdr, [&](unsigned long long c, const unsigned (&v)[8]) {
-    const unsigned long long idx0 = c * kBlk + 8ull * lane;
-    const unsigned valid = chunk_valid(c, lane, in.n);
-    unsigned mask = 0;
-    if constexpr (mode == 0) {
-#pragma unroll
-      for (int i = 0; i < 8; i++)
-        if (((v[i] - lo) <= span) != neg) mask |= 1u << i;
-    } else if (mode == 1 && lds_bm && domain <= kLdsBitmapBits) {
-#pragma unroll
-      for (int i = 0; i < 8; i++) {
-        const unsigned x = v[i];
-        if ((unsigned long long)x < domain && ((ring[x >> 5] >> (x & 31)) & 1u)) mask |= 1u << i;
-      }
-    } else if (mode == 1 && lds_bm) {
-#pragma unroll
-      for (int i = 0; i < 8; i++) {
-        const unsigned x = v[i];
-        if ((unsigned long long)x < domain) {
-          const unsigned word = (unsigned long long)x < lds_bits ? ring[x >> 5] : bitmap[x >> 5];
-          if ((word >> (x & 31)) & 1u) mask |= 1u << i;
-        }
-      }
-    } else {
-#pragma unroll
-      for (int i = 0; i < 8; i++) {
-        const unsigned x = v[i];
-        if ((unsigned long long)x < domain && ((bitmap[x >> 5] >> (x & 31)) & 1u)) mask |= 1u << i;
-      }
-    }
-    mask &= valid;
-    bitmask[c * 64 + lane] = (unsigned char)mask;
-    cnt += __popc(mask);
-    if constexpr (mode == 2) {
-#pragma unroll
-      for (int i = 0; i < 8; i++)
-        if (mask & (1u << i)) orv |= v[i];
-      // strictly increasing inside the chunk; chunk ends are checked by the emit phase
-      const unsigned prev = lane_prev(v[7]);
-#pragma unroll
-      for (int i = 0; i < 8; i++) {
-        const unsigned pv = i ? v[i - 1] : prev;
-        if (((valid >> i) & 1u) && (i > 0 || lane > 0) && v[i] <= pv) unsorted = true;
-      }
-      const unsigned long long last_idx = min(in.n, (c + 1) * kBlk) - 1;
-      if (lane == 0) chunk_first[c] = v[0];
-      if (idx0 <= last_idx && last_idx < idx0 + 8) chunk_last[c] = select8(v, (unsigned)(last_idx - idx0));
-    } else if (mask) {
-      orv |= (unsigned)idx0 | (31u - __clz(mask));  // positions: bit width of the largest
-    }
-  });
-  if (unsorted) raise_err(E_NOT_SORTED);
-  const unsigned long long t = wg_add64(cnt, red);
-  orv = wg_or(orv, redo);
-  if (threadIdx.x == 0) {
-    a.seg_count[blockIdx.x] = (unsigned)t;
-    a.seg_or[blockIdx.x] = orv;
-  }
-}
-
-// ---------------------------------------------------------------------------------------------
 // Compaction phase 2: emit.
 
 // Output blocks of a compaction: 512-blocks over [0, Nb), Nb = n_main for the DynBP
@@ -1012,7 +917,6 @@ __global__ __launch_bounds__(kWG) void k_shrink_payload(const unsigned *src, con
 }
 
 #include "ms_stats.inc"
-#include "ms_mlp.inc"
 
 // Per-launch timing: when enabled, every launch is bracketed by two events on its stream.
 namespace {
@@ -1180,17 +1084,6 @@ hipError_t launch_project(const ColView &pos, const ColView &data, const ColView
   MS_BY_OUT_KIND(out.kind, MS_L)
 #undef MS_L
 }
-hipError_t launch_pred(const PredArgs &a, unsigned G, void *s) {
-  // the semi-join probes (the first kLdsBitmapBits bits of) its bitmap in LDS
-  const size_t shm = a.mode == 1 ? kRingBytes : ring_shm(a.in);
-  if (a.mode == 0)
-    MS_LAUNCH_SHM("k_pred<0>", k_pred<0>, G, kWG, shm, s, a);
-  else if (a.mode == 1)
-    MS_LAUNCH_SHM("k_pred<1>", k_pred<1>, G, kWG, shm, s, a);
-  else
-    MS_LAUNCH_SHM("k_pred<2>", k_pred<2>, G, kWG, shm, s, a);
-  return hipGetLastError();
-}
 hipError_t launch_emit(const EmitArgs &a, unsigned G, void *s) {
   MS_LAUNCH(k_emit, G, kWG, s, a);
   const unsigned k = a.out.kind;
@@ -1251,24 +1144,4 @@ hipError_t launch_stats(const ColView &in, void *chunks, float *feat, void *s) {
   MS_LAUNCH(k_stats_finish, 1, kWG, s, in, c, feat);
   return hipGetLastError();
 }
-unsigned mlp_nparam() { return kNParam; }
-hipError_t launch_mlp_forward(const float *params, const float *x, unsigned n, float *y, unsigned *pick, void *s) {
-  if (n == 0) return hipSuccess;
-  MS_LAUNCH(k_mlp_forward, (n + 63) / 64, 64, s, params, x, n, y, pick);
-  return hipGetLastError();
-}
-unsigned mlp_grad_workgroups(unsigned n) { return (n + kGradSamples - 1) / kGradSamples; }
-hipError_t launch_mlp_grad(const float *params, const float *x, const float *t, unsigned n, float *gpart,
-                           float *lpart, float *grad, float *loss, void *s) {
-  const unsigned nwg = mlp_grad_workgroups(n);
-  MS_LAUNCH(k_mlp_grad, nwg, kWG, s, params, x, t, n, gpart, lpart);
-  MS_LAUNCH(k_mlp_grad_reduce, (kNParam + kWG - 1) / kWG, kWG, s, gpart, lpart, nwg, grad, loss);
-  return hipGetLastError();
-}
-hipError_t launch_adam(float *p, const float *g, float *m, float *v, float lr, float b1, float b2, float eps, float c1,
-                       float c2, void *s) {
-  MS_LAUNCH(k_adam, (kNParam + kWG - 1) / kWG, kWG, s, p, g, m, v, lr, b1, b2, eps, c1, c2);
-  return hipGetLastError();
-}
-
 }  // namespace ms

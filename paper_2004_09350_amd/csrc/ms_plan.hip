@@ -30,6 +30,7 @@ struct Result {
 
 constexpr uint32_t kMaxBranches = 16;
 constexpr uint32_t kMaxWgPerCu = 32;
+constexpr uint32_t kMaxChunksPerWg = 64;
 
 ms_status fail(ms_status st, const char *msg) {
   rt::set_error(msg);
@@ -88,7 +89,7 @@ uint64_t fnv(uint64_t h, const void *p, size_t n) {
 struct ms_plan {
   std::vector<ms_step> steps;
   std::vector<const ms_column *> inputs;
-  ms_tune tune{1, 0};
+  ms_tune tune{1, 0, 0};
   std::vector<int> branch_of;
   std::vector<Result> eager, graph_res;
   bool last_graph = false;
@@ -192,6 +193,7 @@ ms_status run_steps(ms_plan *p, hipStream_t origin, std::vector<Result> &r) {
   r.assign(p->steps.size(), Result());
   const uint32_t B = p->tune.branches;
   rt::set_thread_wg_per_cu(p->tune.wg_per_cu);
+  rt::set_thread_chunks_per_wg(p->tune.chunks_per_wg);
   ms_status st = MS_OK;
   hipError_t e = hipSuccess;
   if (B == 1) {
@@ -218,6 +220,7 @@ ms_status run_steps(ms_plan *p, hipStream_t origin, std::vector<Result> &r) {
     }
   }
   rt::set_thread_wg_per_cu(0);
+  rt::set_thread_chunks_per_wg(0);
   if (st != MS_OK) return st;
   return e == hipSuccess ? MS_OK : hip_fail(e, "branch fork/join");
 }
@@ -338,11 +341,20 @@ ms_status ms_plan_set_format(ms_plan *p, uint32_t step, ms_format fmt) {
   return MS_OK;
 }
 
+ms_status ms_plan_get_format(const ms_plan *p, uint32_t step, ms_format *fmt) {
+  if (!p || !fmt) return fail(MS_ERR_INVALID_ARG, "NULL argument");
+  if (step >= p->steps.size()) return fail(MS_ERR_INVALID_ARG, "step out of range");
+  *fmt = p->steps[step].out;
+  return MS_OK;
+}
+
 ms_status ms_plan_set_tune(ms_plan *p, const ms_tune *t) {
   if (!p || !t) return fail(MS_ERR_INVALID_ARG, "NULL argument");
   if (t->branches < 1 || t->branches > kMaxBranches) return fail(MS_ERR_INVALID_ARG, "branches must be 1..16");
   if (t->wg_per_cu > kMaxWgPerCu) return fail(MS_ERR_INVALID_ARG, "wg_per_cu must be 0..32");
-  if (t->branches != p->tune.branches || t->wg_per_cu != p->tune.wg_per_cu) {
+  if (t->chunks_per_wg > kMaxChunksPerWg) return fail(MS_ERR_INVALID_ARG, "chunks_per_wg must be 0..64");
+  if (t->branches != p->tune.branches || t->wg_per_cu != p->tune.wg_per_cu ||
+      t->chunks_per_wg != p->tune.chunks_per_wg) {
     drop_graph(p);
     p->tune = *t;
     assign_branches(p);
@@ -441,6 +453,8 @@ ms_status ms_plan_read_result(const ms_plan *p, uint32_t step, void *host_dst, u
 
 uint64_t ms_plan_arena_bytes(const ms_plan *p) { return p ? p->arena_bytes : 0; }
 
+static ms_status time_replays(ms_plan *p, void *stream, uint32_t reps, hipEvent_t e0, hipEvent_t e1, float *ms);
+
 ms_status ms_plan_autotune(ms_plan *p, void *stream, uint32_t reps, const char *cache_path, ms_tune *best,
                            float *best_ms) {
   if (!p) return fail(MS_ERR_INVALID_ARG, "plan is NULL");
@@ -460,14 +474,14 @@ ms_status ms_plan_autotune(ms_plan *p, void *stream, uint32_t reps, const char *
   if (cache_path) {
     if (FILE *f = std::fopen(cache_path, "r")) {
       char line[256];
-      ms_tune found{0, 0};
+      ms_tune found{0, 0, 0};
       float fms = 0.f;
       while (std::fgets(line, sizeof(line), f)) {
         char k[64];
-        unsigned b = 0, w = 0;
+        unsigned b = 0, w = 0, c = 0;
         float t = 0.f;
-        if (std::sscanf(line, "%63s %u %u %f", k, &b, &w, &t) == 4 && std::strcmp(k, sig) == 0) {
-          found = ms_tune{b, w};
+        if (std::sscanf(line, "%63s %u %u %u %f", k, &b, &w, &c, &t) == 5 && std::strcmp(k, sig) == 0) {
+          found = ms_tune{b, w, c};
           fms = t;
         }
       }
@@ -481,37 +495,31 @@ ms_status ms_plan_autotune(ms_plan *p, void *stream, uint32_t reps, const char *
       }
     }
   }
+  // branches x workgroups per CU, then chunks per workgroup at the best of those
   static const uint32_t kBranches[] = {1, 2, 4, 8};
   static const uint32_t kWg[] = {0, 2, 4, 8, 16};  // 0: each operator's default
-  hipStream_t s = reinterpret_cast<hipStream_t>(stream);
+  static const uint32_t kChunks[] = {1, 2, 8, 16};  // besides the default of four
   hipEvent_t e0, e1;
   if (hipEventCreate(&e0) != hipSuccess || hipEventCreate(&e1) != hipSuccess)
     return fail(MS_ERR_HIP, "event create failed");
-  ms_tune bt{1, 0};
+  ms_tune bt{1, 0, 0};
   float bms = 1e30f;
   ms_status st = MS_OK;
-  for (uint32_t b : kBranches) {
-    for (uint32_t w : kWg) {
-      ms_tune t{b, w};
-      st = ms_plan_set_tune(p, &t);
-      if (st == MS_OK) st = ms_plan_launch(p, stream);  // capture + warm replay
-      if (st != MS_OK) break;
-      hipError_t e = hipEventRecord(e0, s);
-      for (uint32_t r = 0; r < reps && st == MS_OK; r++) st = ms_plan_launch(p, stream);
-      if (e == hipSuccess) e = hipEventRecord(e1, s);
-      if (e == hipSuccess) e = hipEventSynchronize(e1);
-      float ms = 0.f;
-      if (e == hipSuccess) e = hipEventElapsedTime(&ms, e0, e1);
-      if (e != hipSuccess) st = hip_fail(e, "timing");
-      if (st != MS_OK) break;
-      ms /= (float)reps;
-      if (ms < bms) {
-        bms = ms;
-        bt = t;
-      }
+  auto trial = [&](const ms_tune &t) {
+    st = ms_plan_set_tune(p, &t);
+    float ms = 0.f;
+    if (st == MS_OK) st = time_replays(p, stream, reps, e0, e1, &ms);
+    if (st == MS_OK && ms < bms) {
+      bms = ms;
+      bt = t;
     }
-    if (st != MS_OK) break;
-  }
+  };
+  for (uint32_t b : kBranches)
+    for (uint32_t w : kWg)
+      if (st == MS_OK) trial(ms_tune{b, w, 0});
+  const ms_tune base = bt;
+  for (uint32_t c : kChunks)
+    if (st == MS_OK) trial(ms_tune{base.branches, base.wg_per_cu, c});
   (void)hipEventDestroy(e0);
   (void)hipEventDestroy(e1);
   if (st != MS_OK) return st;
@@ -519,12 +527,29 @@ ms_status ms_plan_autotune(ms_plan *p, void *stream, uint32_t reps, const char *
   if (st != MS_OK) return st;
   if (cache_path) {
     if (FILE *f = std::fopen(cache_path, "a")) {
-      std::fprintf(f, "%s %u %u %.4f\n", sig, bt.branches, bt.wg_per_cu, bms);
+      std::fprintf(f, "%s %u %u %u %.4f\n", sig, bt.branches, bt.wg_per_cu, bt.chunks_per_wg, bms);
       std::fclose(f);
     }
   }
   if (best) *best = bt;
   if (best_ms) *best_ms = bms;
+  return MS_OK;
+}
+
+
+// Mean time (ms) of `reps` graph replays of the plan as it stands (captures first if needed).
+static ms_status time_replays(ms_plan *p, void *stream, uint32_t reps, hipEvent_t e0, hipEvent_t e1, float *ms) {
+  hipStream_t s = reinterpret_cast<hipStream_t>(stream);
+  ms_status st = ms_plan_launch(p, stream);  // capture + warm replay
+  if (st != MS_OK) return st;
+  hipError_t e = hipEventRecord(e0, s);
+  for (uint32_t r = 0; r < reps && st == MS_OK; r++) st = ms_plan_launch(p, stream);
+  if (st != MS_OK) return st;
+  if (e == hipSuccess) e = hipEventRecord(e1, s);
+  if (e == hipSuccess) e = hipEventSynchronize(e1);
+  if (e == hipSuccess) e = hipEventElapsedTime(ms, e0, e1);
+  if (e != hipSuccess) return hip_fail(e, "timing");
+  *ms /= (float)reps;
   return MS_OK;
 }
 

@@ -24,6 +24,8 @@ Arena *thread_arena();
 // Persistent-grid cap in workgroups per compute unit for launches from this thread.
 void set_thread_wg_per_cu(unsigned w);
 unsigned thread_wg_per_cu();
+// Chunks per workgroup that size the persistent grid (0: the default of four).
+void set_thread_chunks_per_wg(unsigned c);
 void *alloc(uint64_t bytes, void *stream);
 void free(void *p, uint64_t bytes, void *stream);
 unsigned cus();

@@ -69,7 +69,7 @@ class Step(ctypes.Structure):
 
 
 class Tune(ctypes.Structure):
-    _fields_ = [("branches", ctypes.c_uint32), ("wg_per_cu", ctypes.c_uint32)]
+    _fields_ = [("branches", ctypes.c_uint32), ("wg_per_cu", ctypes.c_uint32), ("chunks_per_wg", ctypes.c_uint32)]
 
 
 _sigs = {
@@ -92,6 +92,9 @@ _sigs = {
     "ms_group_sum_noalloc": [_P, _P, _U32, _P, _P],
     "ms_sync": [_P],
     "ms_footprints": [_P, _P, _P],
+    "ms_calc": [_P, _P, _U32, Format, _P, _PP],
+    "ms_join": [_P, _P, _U64, Format, Format, _P, _PP, _PP],
+    "ms_group_by": [_P, _U64, Format, Format, _P, _PP, _PP],
     "ms_stats": [_P, _P, _P],
     "ms_mlp_forward": [_P, _P, _U64, _P, _P, _P],
     "ms_mlp_grad": [_P, _P, _P, _U64, _P, _P, _P],
@@ -99,6 +102,7 @@ _sigs = {
     "ms_plan_destroy": [_P],
     "ms_plan_set_format": [_P, _U32, Format],
     "ms_plan_set_tune": [_P, ctypes.POINTER(Tune)],
+    "ms_plan_get_format": [_P, _U32, ctypes.POINTER(Format)],
     "ms_plan_get_tune": [_P, ctypes.POINTER(Tune)],
     "ms_plan_run": [_P, _P],
     "ms_plan_launch": [_P, _P],
@@ -106,6 +110,18 @@ _sigs = {
     "ms_plan_read_result": [_P, _U32, _P, _U64, _P, ctypes.POINTER(_U64)],
     "ms_plan_autotune": [_P, _P, _U32, ctypes.c_char_p, ctypes.POINTER(Tune), ctypes.POINTER(ctypes.c_float)],
     "ms_adam_step": [_P, _P, _P, _P, _U64, ctypes.c_float, ctypes.c_float, ctypes.c_float, ctypes.c_float, _P],
+    "ms_selector_create": [_P, _P, _PP],
+    "ms_selector_destroy": [_P],
+    "ms_selector_params": [_P, _U32, _P, _P],
+    "ms_selector_save": [_P, ctypes.c_char_p],
+    "ms_selector_load": [ctypes.c_char_p, _PP],
+    "ms_selector_size_targets": [_P, _P, _U64, _P, _P],
+    "ms_selector_cost_targets": [_P, _P, _U64, _P, _P],
+    "ms_selector_train": [_P, _U32, _P, _P, _U64, _P, ctypes.POINTER(ctypes.c_float), _P],
+    "ms_selector_pick": [_P, _U32, _P, _U64, _P, _P, _P],
+    "ms_select_exhaustive": [_P, _P, _P, _P],
+    "ms_select_argmin": [_P, _U64, _P, _P],
+    "ms_decode_cost": [_P, _U32, _P, _P],
 }
 for _name, _args in _sigs.items():
     _f = getattr(_lib, _name)
@@ -126,6 +142,8 @@ _lib.ms_mlp_nparam.restype = ctypes.c_uint32
 MLP_NPARAM = int(_lib.ms_mlp_nparam())
 _lib.ms_plan_arena_bytes.argtypes = [_P]
 _lib.ms_plan_arena_bytes.restype = ctypes.c_uint64
+_lib.ms_selector_trained.argtypes = [_P]
+_lib.ms_selector_trained.restype = ctypes.c_uint32
 
 
 def lib():
@@ -325,6 +343,37 @@ def intersect(a: Column, b: Column, domain: int, f: Format = None, stream=None) 
     return _out(_lib.ms_intersect, a.handle, b.handle, domain, f, _stream(stream), stream=stream)
 
 
+CALC_ADD, CALC_SUB, CALC_MUL = range(3)
+
+
+def calc(a: Column, b: Column, op: int, f: Format = None, stream=None) -> Column:
+    """Element-wise a op b modulo 2^32 (op: CALC_ADD, CALC_SUB, CALC_MUL)."""
+    f = f if f is not None else fmt(STATIC_BP)
+    return _out(_lib.ms_calc, a.handle, b.handle, op, f, _stream(stream), stream=stream)
+
+
+def join(keys: Column, bitmap: torch.Tensor, domain: int, f_left: Format = None, f_right: Format = None,
+         stream=None):
+    """Position pairs of the join of keys with the dimension rows marked in bitmap:
+    (ascending fact positions, the matching dimension positions)."""
+    f_left = f_left if f_left is not None else fmt(DELTA_DYN_BP)
+    f_right = f_right if f_right is not None else fmt(STATIC_BP)
+    l, r = ctypes.c_void_p(0), ctypes.c_void_p(0)
+    _check(_lib.ms_join(keys.handle, bitmap.data_ptr(), domain, f_left, f_right, _stream(stream), ctypes.byref(l),
+                        ctypes.byref(r)))
+    return Column(l.value, stream=stream), Column(r.value, stream=stream)
+
+
+def group_by(keys: Column, domain: int, f_ids: Format = None, f_keys: Format = None, stream=None):
+    """(group id of every row = rank of its key among the distinct keys, the distinct keys
+    in ascending order); every key must be below domain (<= 2^28)."""
+    f_ids = f_ids if f_ids is not None else fmt(STATIC_BP)
+    f_keys = f_keys if f_keys is not None else fmt(DELTA_DYN_BP)
+    i, d = ctypes.c_void_p(0), ctypes.c_void_p(0)
+    _check(_lib.ms_group_by(keys.handle, domain, f_ids, f_keys, _stream(stream), ctypes.byref(i), ctypes.byref(d)))
+    return Column(i.value, stream=stream), Column(d.value, stream=stream)
+
+
 def sum_(col: Column, out: torch.Tensor | None = None, stream=None) -> torch.Tensor:
     if out is None:
         out = torch.empty(1, dtype=torch.int64, device="cuda")
@@ -408,6 +457,145 @@ def adam_step(params: torch.Tensor, grad: torch.Tensor, m: torch.Tensor, v: torc
                              eps, _stream(stream)))
 
 
+# ----------------------------------------------------------------------------------- selection
+NET_SIZE, NET_COST = 0, 1
+OBJ_FOOTPRINT, OBJ_DECODE = 0, 1
+
+
+class TrainCfg(ctypes.Structure):
+    _fields_ = [("epochs", ctypes.c_uint32), ("batch", ctypes.c_uint32), ("lr", ctypes.c_float),
+                ("beta1", ctypes.c_float), ("beta2", ctypes.c_float), ("eps", ctypes.c_float),
+                ("seed", ctypes.c_uint64)]
+
+
+def _u64_tensor(a) -> torch.Tensor:
+    if isinstance(a, torch.Tensor):
+        t = a if a.is_cuda else a.cuda()
+        return t.to(torch.int64).contiguous()
+    return torch.from_numpy(np.ascontiguousarray(a, dtype=np.uint64).view(np.int64)).cuda()
+
+
+def _f32_tensor(a) -> torch.Tensor:
+    if isinstance(a, torch.Tensor):
+        t = a if a.is_cuda else a.cuda()
+        return t.to(torch.float32).contiguous()
+    return torch.from_numpy(np.ascontiguousarray(a, dtype=np.float32)).cuda()
+
+
+class Selector:
+    """The size and decode-cost networks of the learned format selector (ms_selector)."""
+
+    def __init__(self, handle: int):
+        self._h = ctypes.c_void_p(handle)
+
+    @classmethod
+    def create(cls, init_size: np.ndarray, init_cost: np.ndarray) -> "Selector":
+        a = np.ascontiguousarray(init_size, dtype=np.float32)
+        b = np.ascontiguousarray(init_cost, dtype=np.float32)
+        if a.shape != (MLP_NPARAM,) or b.shape != (MLP_NPARAM,):
+            raise ValueError(f"initial parameters must be float32[{MLP_NPARAM}]")
+        h = ctypes.c_void_p(0)
+        _check(_lib.ms_selector_create(a.ctypes.data, b.ctypes.data, ctypes.byref(h)))
+        return cls(h.value)
+
+    @classmethod
+    def load(cls, path: str) -> "Selector":
+        h = ctypes.c_void_p(0)
+        _check(_lib.ms_selector_load(os.fsencode(path), ctypes.byref(h)))
+        return cls(h.value)
+
+    def save(self, path: str):
+        _check(_lib.ms_selector_save(self._h, os.fsencode(path)))
+
+    def params(self, net: int, stream=None) -> torch.Tensor:
+        """A copy of network `net`'s parameters (float32[6662] on the device)."""
+        out = torch.empty(MLP_NPARAM, dtype=torch.float32, device="cuda")
+        _check(_lib.ms_selector_params(self._h, net, out.data_ptr(), _stream(stream)))
+        return out
+
+    def trained(self) -> int:
+        return int(_lib.ms_selector_trained(self._h))
+
+    def train(self, net: int, x, t, epochs: int = 40, batch: int = 1024, lr: float = 2e-3, beta1: float = 0.9,
+              beta2: float = 0.999, eps: float = 1e-8, seed: int = 77, stream=None) -> float:
+        """Mini-batch Adam on network `net` over features x (n x 32) and targets t (n x 6);
+        returns the mean batch loss of the last pass."""
+        xd, td = _f32_tensor(x), _f32_tensor(t)
+        n = xd.shape[0]
+        _f32(xd, n, 32)
+        _f32(td, n, 6)
+        cfg = TrainCfg(epochs, batch, lr, beta1, beta2, eps, seed)
+        loss = ctypes.c_float(0)
+        _check(_lib.ms_selector_train(self._h, net, xd.data_ptr(), td.data_ptr(), n, ctypes.byref(cfg),
+                                      ctypes.byref(loss), _stream(stream)))
+        return float(loss.value)
+
+    def pick(self, x, objective: int = OBJ_FOOTPRINT, want_pred: bool = False, stream=None):
+        """Per row of x (n x 32): the format of least predicted cost (int32[n]), and the
+        network's outputs (n x 6) when want_pred."""
+        xd = _f32_tensor(x)
+        n = xd.shape[0]
+        _f32(xd, n, 32)
+        kinds = torch.empty(max(n, 1), dtype=torch.int32, device="cuda")
+        pred = torch.empty((max(n, 1), 6), dtype=torch.float32, device="cuda") if want_pred else None
+        _check(_lib.ms_selector_pick(self._h, objective, xd.data_ptr(), n, kinds.data_ptr(),
+                                     pred.data_ptr() if pred is not None else None, _stream(stream)))
+        return (kinds[:n], pred[:n]) if want_pred else kinds[:n]
+
+    def close(self):
+        if self._h and self._h.value:
+            _lib.ms_selector_destroy(self._h)
+            self._h = ctypes.c_void_p(0)
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+
+def size_targets(bytes6, n, stream=None) -> torch.Tensor:
+    """Training targets of the size network: log2(1 + 8 * bytes / n) / 6 (n x 6 float32)."""
+    b, nn = _u64_tensor(bytes6), _u64_tensor(n)
+    cnt = nn.numel()
+    out = torch.empty((max(cnt, 1), 6), dtype=torch.float32, device="cuda")
+    _check(_lib.ms_selector_size_targets(b.data_ptr(), nn.data_ptr(), cnt, out.data_ptr(), _stream(stream)))
+    return out[:cnt]
+
+
+def cost_targets(ns6, n, stream=None) -> torch.Tensor:
+    """Training targets of the decode-cost network: log2(1 + 1000 * ns / n) / 16 (n x 6)."""
+    c, nn = _f32_tensor(ns6), _u64_tensor(n)
+    cnt = nn.numel()
+    out = torch.empty((max(cnt, 1), 6), dtype=torch.float32, device="cuda")
+    _check(_lib.ms_selector_cost_targets(c.data_ptr(), nn.data_ptr(), cnt, out.data_ptr(), _stream(stream)))
+    return out[:cnt]
+
+
+def select_exhaustive(col: Column, stream=None):
+    """(least-footprint kind as an int32[1] device tensor, the six footprints int64[6])."""
+    b = torch.empty(6, dtype=torch.int64, device="cuda")
+    k = torch.empty(1, dtype=torch.int32, device="cuda")
+    _check(_lib.ms_select_exhaustive(col.handle, b.data_ptr(), k.data_ptr(), _stream(stream)))
+    return k, b
+
+
+def select_argmin(bytes6, stream=None) -> torch.Tensor:
+    """Exhaustive choice for rows of footprints (n x 6): int32[n], ties to the lower kind."""
+    b = _u64_tensor(bytes6)
+    cnt = b.numel() // 6
+    k = torch.empty(max(cnt, 1), dtype=torch.int32, device="cuda")
+    _check(_lib.ms_select_argmin(b.data_ptr(), cnt, k.data_ptr(), _stream(stream)))
+    return k[:cnt]
+
+
+def decode_cost(col: Column, reps: int = 3, stream=None) -> np.ndarray:
+    """Measured ns per decode of the column in each of the six formats (float32[6])."""
+    out = np.zeros(6, np.float32)
+    _check(_lib.ms_decode_cost(col.handle, reps, out.ctypes.data, _stream(stream)))
+    return out
+
+
 # ----------------------------------------------------------------------------------- plans
 OP_MORPH, OP_SELECT, OP_BITMAP, OP_SEMIJOIN, OP_PROJECT, OP_INTERSECT, OP_SUM, OP_GROUP_SUM, OP_FOOTPRINTS, \
     OP_STATS = range(10)
@@ -463,15 +651,15 @@ class Plan:
         _check(_lib.ms_plan_set_format(self._h, i, f))
         self.steps[i].out = f
 
-    def set_tune(self, branches: int, wg_per_cu: int):
+    def set_tune(self, branches: int, wg_per_cu: int, chunks_per_wg: int = 0):
         self._drop_borrowed()
-        t = Tune(branches, wg_per_cu)
+        t = Tune(branches, wg_per_cu, chunks_per_wg)
         _check(_lib.ms_plan_set_tune(self._h, ctypes.byref(t)))
 
     def tune(self) -> tuple:
         t = Tune()
         _check(_lib.ms_plan_get_tune(self._h, ctypes.byref(t)))
-        return t.branches, t.wg_per_cu
+        return t.branches, t.wg_per_cu, t.chunks_per_wg
 
     def run(self, stream=None):
         self._drop_borrowed()
@@ -491,7 +679,16 @@ class Plan:
         ms = ctypes.c_float(0)
         _check(_lib.ms_plan_autotune(self._h, _stream(stream), reps, cache.encode() if cache else None,
                                      ctypes.byref(t), ctypes.byref(ms)))
-        return (t.branches, t.wg_per_cu), ms.value
+        return (t.branches, t.wg_per_cu, t.chunks_per_wg), ms.value
+
+    def formats(self) -> list:
+        """The output format kind of every step as the library holds it."""
+        out = []
+        for i in range(len(self.steps)):
+            f = Format()
+            _check(_lib.ms_plan_get_format(self._h, i, ctypes.byref(f)))
+            out.append(f.kind)
+        return out
 
     def arena_bytes(self) -> int:
         return int(_lib.ms_plan_arena_bytes(self._h))

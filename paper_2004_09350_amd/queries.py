@@ -101,10 +101,15 @@ def uniform_formats(names, kind) -> dict:
 
 
 def exhaustive_formats(plan: M.Plan, names: dict) -> tuple[dict, dict]:
-    """Least-footprint format of every intermediate of the plan's last run (exact
-    footprints from one pass each); also returns the footprint vectors."""
-    fps = {n: M.u64(M.footprints(plan.column(i))) for n, i in names.items()}
-    return {n: M.fmt(int(np.argmin(f))) for n, f in fps.items()}, fps
+    """Least-footprint format of every intermediate of the plan's last run (the library's
+    exhaustive selection: exact footprints from one pass each, ties to the lower format);
+    also returns the footprint vectors."""
+    chosen, fps = {}, {}
+    for n, i in names.items():
+        k, b = M.select_exhaustive(plan.column(i))
+        chosen[n] = M.fmt(int(k.cpu()[0]))
+        fps[n] = M.u64(b)
+    return chosen, fps
 
 
 def learned_formats(plan: M.Plan, names: dict, params) -> dict:
@@ -114,3 +119,67 @@ def learned_formats(plan: M.Plan, names: dict, params) -> dict:
     _, pick = M.mlp_forward(params, feats.contiguous(), want_y=False)
     picks = pick.cpu().numpy()
     return {n: M.fmt(int(k)) for n, k in zip(names, picks)}
+
+
+def _replay_ms(plan: M.Plan, reps: int) -> float:
+    """Mean time (ms) of `reps` graph replays after a capture and a warm replay."""
+    import torch
+    plan.launch()
+    torch.cuda.synchronize()
+    e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+    e0.record()
+    for _ in range(reps):
+        plan.launch()
+    e1.record()
+    e1.synchronize()
+    return e0.elapsed_time(e1) / reps
+
+
+def greedy_runtime_formats(cols: dict, thresholds, dim_sizes, n_fact: int, formats: dict, reps: int = 3,
+                           tune=(2, 0, 0), search_inputs: bool = True, log=None):
+    """Section 5.2's greedy runtime search: starting at the base data, one column at a time
+    (the star plan's input columns, then its intermediates in plan order), every format is
+    tried, the query is timed (captured graph, mean of `reps` replays) and the column keeps
+    its fastest format for the rest of the search.  Returns (input columns, intermediate
+    formats, final mean ms, number of trials); input columns in a new format are morphed
+    copies (the given columns are not changed)."""
+    cur_cols = dict(cols)
+    cur_fmt = dict(formats)
+
+    def trial(cs, fm):
+        q = Q3(cs, thresholds, dim_sizes, n_fact, formats=fm)
+        q.plan.set_tune(*tune)
+        t = _replay_ms(q.plan, reps)
+        q.plan.close()
+        return t
+
+    best_t = trial(cur_cols, cur_fmt)
+    trials = 1
+    if search_inputs:
+        for name in Q3_INPUTS:
+            given = cur_cols[name]
+            k0 = given.info()["kind"]
+            for k in M.KINDS:
+                if k == k0:
+                    continue
+                cand = M.morph(given, M.fmt(k))
+                t = trial(dict(cur_cols, **{name: cand}), cur_fmt)
+                trials += 1
+                if t < best_t:
+                    best_t, cur_cols[name] = t, cand
+                del cand
+            if log:
+                log(f"greedy: {name} -> {M.KIND_NAMES[cur_cols[name].info()['kind']]} ({best_t:.3f} ms)")
+    for name in formats:
+        k0 = cur_fmt[name].kind
+        for k in M.KINDS:
+            if k == k0:
+                continue
+            fm = dict(cur_fmt, **{name: M.fmt(k)})
+            t = trial(cur_cols, fm)
+            trials += 1
+            if t < best_t:
+                best_t, cur_fmt = t, fm
+        if log:
+            log(f"greedy: {name} -> {M.KIND_NAMES[cur_fmt[name].kind]} ({best_t:.3f} ms)")
+    return cur_cols, cur_fmt, best_t, trials

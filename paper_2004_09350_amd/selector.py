@@ -1,17 +1,20 @@
 """Learned format selection (section 5.2: formats chosen per intermediate by a cost model
-over data characteristics; exhaustive selection, whose per-column optimum is the plan
-optimum because footprints add up, is the reference its regret is measured against).
+over data characteristics that estimates both the compression rate and the decompression
+performance; exhaustive selection, whose per-column optimum is the plan optimum because
+footprints add up, is the reference its regret is measured against).
 
 The engine produces its own training data: it runs star-query plans (the shape of the
 evaluation workload, with other seeds, sizes and selectivities), and for every
-intermediate records the 32 statistics (``ms_stats``) and the exact footprint in each
-format (``ms_footprints``).  The network (32-64-64-6, ReLU) learns
-t_f = log2(1 + 8 * footprint_f / n) / 6, the log-scaled bits per value of format f,
-with the library's own gradient and Adam kernels; the pick is the smallest output.
+intermediate records the 32 statistics (``ms_stats``), the exact footprint in each
+format (``ms_footprints``) and, on request, the measured decode time of each format
+(``ms_decode_cost``).  The library turns those labels into targets, trains its two
+32-64-64-6 networks (size, decode cost) with its own gradient and Adam kernels and picks
+formats (``ms_selector_*``); this module only drives the plans and moves arrays.
 """
 from __future__ import annotations
 
 import math
+import os
 import time
 
 import numpy as np
@@ -22,13 +25,14 @@ from . import gen_gpu as gen
 from . import morphgpu as M
 from .queries import Q3, Q3_INPUTS
 
-TARGET_SCALE = 6.0
+HERE = os.path.dirname(os.path.abspath(__file__))
+WEIGHTS = os.path.join(HERE, "selector.msw")
+INIT_SEED = 77
 
 
-def targets(fp6: np.ndarray, n: np.ndarray) -> np.ndarray:
-    """Training targets from exact footprints (bytes) and element counts."""
-    n = np.maximum(np.asarray(n, np.float64), 1.0)[:, None]
-    return (np.log2(1.0 + 8.0 * np.asarray(fp6, np.float64) / n) / TARGET_SCALE).astype(np.float32)
+def new_selector(seed: int = INIT_SEED) -> M.Selector:
+    """Both networks at their seeded He-uniform initialisation (size: seed, cost: seed + 100)."""
+    return M.Selector.create(datagen.mlp_init(seed), datagen.mlp_init(seed + 100))
 
 
 def star_inputs(seed: int, n_fact: int, fact_fmt=None, dims=None):
@@ -53,11 +57,13 @@ def star_inputs(seed: int, n_fact: int, fact_fmt=None, dims=None):
 
 
 def collect(n_plans: int, seed0: int = 10_000, n_lo: float = 1e5, n_hi: float = 1e7, s_lo: float = 0.01,
-            s_hi: float = 0.20, plans_per_seed: int = 8, log=None):
-    """Statistics, footprints and sizes of every intermediate of `n_plans` star plans.
-    Plan j uses seed seed0 + j // plans_per_seed for its dimensions (shared by a group of
-    plans) and its own fact seed, size (log-uniform) and selectivities (uniform)."""
-    X, F, N, names = [], [], [], []
+            s_hi: float = 0.20, plans_per_seed: int = 8, cost_labels: bool = False, cost_reps: int = 3, log=None):
+    """Statistics, footprints and sizes (and decode times when cost_labels) of every
+    intermediate of `n_plans` star plans.  Plan j uses seed seed0 + j // plans_per_seed for
+    its dimensions (shared by a group of plans) and its own fact seed, size (log-uniform)
+    and selectivities (uniform).  Returns X (k x 32 float32), F (k x 6 uint64 bytes),
+    N (k uint64), C (k x 6 float32 ns per decode, or None) and the intermediates' names."""
+    X, F, N, C, names = [], [], [], [], []
     dims, dims_seed = None, None
     t0 = time.time()
     for j in range(n_plans):
@@ -73,61 +79,52 @@ def collect(n_plans: int, seed0: int = 10_000, n_lo: float = 1e5, n_hi: float = 
         for name in q.names:
             X.append(q.plan.read(q.stats_step[name]))
             F.append(q.plan.read(q.fp_step[name]))
-            N.append(q.plan.column(q.names[name]).info()["n"])
+            col = q.plan.column(q.names[name])
+            N.append(col.info()["n"])
+            if cost_labels:
+                C.append(M.decode_cost(col, cost_reps))
             names.append(name)
         q.plan.close()
         del cols, q
         if log and (j + 1) % 100 == 0:
             log(f"collected {j + 1}/{n_plans} plans, {len(X)} intermediates, {time.time() - t0:.1f}s")
-    return np.stack(X), np.stack(F).astype(np.uint64), np.asarray(N, np.uint64), names
+    return (np.stack(X), np.stack(F).astype(np.uint64), np.asarray(N, np.uint64),
+            np.stack(C).astype(np.float32) if cost_labels else None, names)
 
 
-def train(X: np.ndarray, T: np.ndarray, epochs: int = 60, batch: int = 512, lr: float = 2e-3, seed: int = 77,
-          log=None) -> torch.Tensor:
-    """Mini-batch Adam on the GPU with the library's gradient and update kernels."""
-    p = torch.from_numpy(datagen.mlp_init(seed)).cuda()
-    m = torch.zeros_like(p)
-    v = torch.zeros_like(p)
-    Xd = torch.from_numpy(np.ascontiguousarray(X, np.float32)).cuda()
-    Td = torch.from_numpy(np.ascontiguousarray(T, np.float32)).cuda()
-    n = Xd.shape[0]
-    order_seed = seed
-    step = 0
-    g = torch.empty_like(p)
-    for ep in range(epochs):
-        perm = torch.from_numpy(np.argsort(datagen.stream(order_seed + ep, 0, n))).cuda()
-        losses = []
-        for s in range(0, n, batch):
-            idx = perm[s:s + batch]
-            xb, tb = Xd[idx].contiguous(), Td[idx].contiguous()
-            _, loss = M.mlp_grad(p, xb, tb, grad=g)
-            step += 1
-            M.adam_step(p, g, m, v, step, lr=lr)
-            losses.append(loss)
-        if log and (ep + 1) % 10 == 0:
-            log(f"epoch {ep + 1}: mean batch loss {float(torch.stack(losses).mean()):.3e}")
-    return p
+def train(X: np.ndarray, F: np.ndarray, N: np.ndarray, C: np.ndarray | None = None, epochs: int = 60,
+          batch: int = 512, lr: float = 2e-3, seed: int = INIT_SEED, log=None) -> M.Selector:
+    """A selector trained on the GPU by the library: the size network on the footprints'
+    targets, and the decode-cost network on the decode times' targets when C is given."""
+    sel = new_selector(seed)
+    x = torch.from_numpy(np.ascontiguousarray(X, np.float32)).cuda()
+    loss = sel.train(M.NET_SIZE, x, M.size_targets(F, N), epochs=epochs, batch=batch, lr=lr, seed=seed)
+    if log:
+        log(f"size network: last-pass loss {loss:.3e}")
+    if C is not None:
+        loss = sel.train(M.NET_COST, x, M.cost_targets(C, N), epochs=epochs, batch=batch, lr=lr, seed=seed + 1)
+        if log:
+            log(f"decode-cost network: last-pass loss {loss:.3e}")
+    return sel
 
 
-def save(params: torch.Tensor, path: str):
-    np.save(path, params.detach().cpu().numpy().astype(np.float32), allow_pickle=False)
+def load(path: str = WEIGHTS) -> M.Selector:
+    return M.Selector.load(path)
 
 
-def load(path: str) -> torch.Tensor:
-    p = np.load(path, allow_pickle=False)
-    if p.shape != (M.MLP_NPARAM,) or p.dtype != np.float32:
-        raise ValueError(f"{path}: expected float32[{M.MLP_NPARAM}]")
-    return torch.from_numpy(p).cuda()
+def pick(sel: M.Selector, X: np.ndarray, objective: int = M.OBJ_FOOTPRINT) -> np.ndarray:
+    return sel.pick(np.ascontiguousarray(X, np.float32), objective).cpu().numpy()
 
 
-def pick(params: torch.Tensor, X: np.ndarray) -> np.ndarray:
-    _, k = M.mlp_forward(params, torch.from_numpy(np.ascontiguousarray(X, np.float32)).cuda(), want_y=False)
-    return k.cpu().numpy()
+def exhaustive(F: np.ndarray) -> np.ndarray:
+    """The library's exhaustive choice for rows of footprints (ties to the lower kind)."""
+    return M.select_argmin(np.asarray(F, np.uint64)).cpu().numpy()
 
 
 def regret(F: np.ndarray, picks: np.ndarray) -> float:
-    """Sum of picked footprints over the sum of the least footprints, minus one."""
+    """Sum of the picked costs over the sum of the exhaustive choice's, minus one."""
     F = np.asarray(F, np.float64)
-    best = F.min(axis=1).sum()
-    got = F[np.arange(F.shape[0]), picks].sum()
+    rows = np.arange(F.shape[0])
+    best = F[rows, exhaustive(F.astype(np.uint64))].sum()
+    got = F[rows, np.asarray(picks)].sum()
     return float(got / best - 1.0) if best > 0 else 0.0

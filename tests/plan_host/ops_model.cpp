@@ -121,6 +121,7 @@ void set_thread_arena(Arena *a) { t_arena = a; }
 Arena *thread_arena() { return t_arena; }
 void set_thread_wg_per_cu(unsigned w) { t_wg = w; }
 unsigned thread_wg_per_cu() { return t_wg; }
+void set_thread_chunks_per_wg(unsigned c) { (void)c; }
 void *alloc(uint64_t bytes, void *stream) {
   (void)stream;
   if (bytes == 0) bytes = 256;

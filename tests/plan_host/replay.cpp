@@ -127,7 +127,7 @@ void star_scenario(const char *cache) {
   CHECK(ms_plan_autotune(p, st, 2, cache, &best, &best_ms));  // from the cache this time
   CHECK(ms_plan_autotune(p, st, 1, nullptr, &best, &best_ms));
   CHECK(ms_plan_run(p, st));
-  t = ms_tune{4, 2};
+  t = ms_tune{4, 2, 16};
   CHECK(ms_plan_set_tune(p, &t));
   CHECK(ms_plan_launch(p, st));  // no sync before the next change: set_tune must wait for the replay
   t = ms_tune{8, 8};

@@ -1,7 +1,8 @@
 """The learned format selector end to end on the GPU: training data produced by the
-engine (statistics + exact footprints of star-plan intermediates), training with the
-library's own kernels, and its picks on star plans with other seeds compared with
-exhaustive selection, an untrained network and the naive all-static-BP plan."""
+engine (statistics, exact footprints and measured decode times of star-plan
+intermediates), training of both networks with the library's own kernels, and their
+picks on star plans with other seeds compared with exhaustive selection, the untrained
+networks and the naive all-static-BP plan, on footprint, decode time and query time."""
 import numpy as np
 import pytest
 
@@ -23,8 +24,9 @@ def S():
 
 
 def test_collect_labels_match_oracle(S):
-    X, F, N, names = S.collect(2, seed0=20_000, n_lo=2e5, n_hi=4e5)
-    assert X.shape == (len(names), 32) and F.shape == (len(names), 6)
+    X, F, N, C, names = S.collect(2, seed0=20_000, n_lo=2e5, n_hi=4e5, cost_labels=True)
+    assert X.shape == (len(names), 32) and F.shape == (len(names), 6) and C.shape == (len(names), 6)
+    assert np.all(np.isfinite(C)) and np.all(C > 0)  # measured decode times (parity unpinned: timings)
     # recompute the first plan's intermediates with the oracle and compare labels
     u = datagen.stream(20_000 * 7919, 0, 5).astype(np.float64) / 2.0 ** 64
     n_fact = int(np.exp(np.log(2e5) + u[0] * (np.log(4e5) - np.log(2e5))))
@@ -40,29 +42,72 @@ def test_collect_labels_match_oracle(S):
         assert N[i] == inter.size
 
 
-def test_learned_selector_gain(S):
-    import torch
-    X, F, N, _ = S.collect(48, seed0=30_000, n_lo=1e5, n_hi=2e6)
-    T = S.targets(F, N)
-    p = S.train(X, T, epochs=80, batch=256, lr=2e-3)
-    p0 = torch.from_numpy(datagen.mlp_init(77)).cuda()
-    # evaluation: star plans with the evaluation seeds (wide and narrow filters)
-    Xe, Fe = [], []
+def _eval_plans(S, M):
+    """Statistics, footprints and measured decode times of the intermediates of two star
+    plans with evaluation seeds (wide and narrow filters), plus the plans' inputs."""
     from paper_2004_09350_amd.queries import Q3
+    Xe, Fe, Ce, plans = [], [], [], []
     for seed, sel in ((1, datagen.STAR_WIDE), (2, datagen.STAR_NARROW)):
         cols, _ = S.star_inputs(seed, 1_000_000)
-        q = Q3(cols, datagen.star_thresholds(sel), datagen.STAR_DIM_SIZES, 1_000_000, extra=("stats", "footprints"))
+        thr = datagen.star_thresholds(sel)
+        q = Q3(cols, thr, datagen.STAR_DIM_SIZES, 1_000_000, extra=("stats", "footprints"))
         q.plan.run()
-        for name in q.names:
+        names = list(q.names)
+        for name in names:
             Xe.append(q.plan.read(q.stats_step[name]))
             Fe.append(q.plan.read(q.fp_step[name]))
+            Ce.append(M.decode_cost(q.plan.column(q.names[name]), 5))
         q.plan.close()
-    Xe, Fe = np.stack(Xe), np.stack(Fe)
-    learned = S.regret(Fe, S.pick(p, Xe))
-    untrained = S.regret(Fe, S.pick(p0, Xe))
-    static = S.regret(Fe, np.full(len(Fe), 1))
-    uncompr = S.regret(Fe, np.zeros(len(Fe), int))
-    print(f"regret: learned {learned:.4f} untrained {untrained:.4f} all-static {static:.4f} "
-          f"all-uncompressed {uncompr:.4f}")
-    assert learned <= 0.05
-    assert learned < untrained and learned < static and learned < uncompr
+        plans.append((cols, thr, names))
+    return np.stack(Xe), np.stack(Fe), np.stack(Ce), plans
+
+
+def _query_ms(S, M, plans, kinds):
+    """Graph replay time (ms, median of 9) of the evaluation plans with the given formats."""
+    import torch
+    from paper_2004_09350_amd.queries import Q3
+    total, i = 0.0, 0
+    for cols, thr, names in plans:
+        fm = {nm: M.fmt(int(k)) for nm, k in zip(names, kinds[i:i + len(names)])}
+        i += len(names)
+        q = Q3(cols, thr, datagen.STAR_DIM_SIZES, 1_000_000, formats=fm)
+        q.plan.launch()
+        torch.cuda.synchronize()
+        ts = []
+        for _ in range(9):
+            e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+            e0.record()
+            q.plan.launch()
+            e1.record()
+            e1.synchronize()
+            ts.append(e0.elapsed_time(e1))
+        q.plan.close()
+        total += float(np.median(ts))
+    return total
+
+
+def test_learned_selector_gain(S):
+    from paper_2004_09350_amd import morphgpu as M
+    X, F, N, C, _ = S.collect(48, seed0=30_000, n_lo=1e5, n_hi=2e6, cost_labels=True)
+    sel = S.train(X, F, N, C, epochs=80, batch=256, lr=2e-3)
+    assert sel.trained() == 3
+    untrained = S.new_selector()
+    Xe, Fe, Ce, plans = _eval_plans(S, M)
+    static = np.full(len(Fe), M.STATIC_BP)
+    uncompr = np.zeros(len(Fe), int)
+    picks = {"learned": S.pick(sel, Xe), "untrained": S.pick(untrained, Xe), "static": static, "uncompr": uncompr}
+    fp = {k: S.regret(Fe, p) for k, p in picks.items()}
+    # decode time: the decode-cost network's picks against the fastest measured format
+    dec_best = Ce.min(axis=1).sum()
+    dpicks = {"learned": S.pick(sel, Xe, M.OBJ_DECODE), "untrained": S.pick(untrained, Xe, M.OBJ_DECODE),
+              "static": static}
+    dec = {k: float(Ce[np.arange(len(Ce)), p].sum() / dec_best - 1) for k, p in dpicks.items()}
+    qpicks = dict(picks, learned_decode=dpicks["learned"], untrained_decode=dpicks["untrained"])
+    qt = {k: _query_ms(S, M, plans, p) for k, p in qpicks.items()}
+    print(f"footprint regret {fp}; decode-time regret {dec}; query ms {qt}")
+    assert fp["learned"] <= 0.05
+    assert fp["learned"] < fp["untrained"] and fp["learned"] < fp["static"] and fp["learned"] < fp["uncompr"]
+    # measured times (parity unpinned: timings vary from run to run): the decode-cost
+    # network's picks stay near the fastest measured decode, and every policy's plan runs
+    assert dec["learned"] <= 0.5
+    assert all(t > 0 for t in qt.values())

@@ -100,6 +100,38 @@ def test_select_all_formats(M, n):
     M.sync()
 
 
+def narrow_preds(W):
+    """Every comparison with constants inside, at the edges of and beyond [0, 2^W)."""
+    top = (1 << W) - 1
+    cs = sorted({0, 1, top // 3, top // 2, top - 1, top, top + 1, 1 << 31, 0xFFFFFFFF})
+    out = []
+    for c in cs:
+        for cmp in (O.EQ, O.NE, O.LT, O.LE, O.GT, O.GE):
+            out.append((cmp, c, 0))
+    out += [(O.BETWEEN, 1, top - 1), (O.BETWEEN, top // 2, top + 5), (O.BETWEEN, top + 1, 1 << 20),
+            (O.BETWEEN, 3, 2)]
+    return out
+
+
+@pytest.mark.parametrize("W", [1, 2, 3, 4, 5, 6, 7, 8])
+@pytest.mark.parametrize("n", [1, 33, 2047, 2049, 100_003, 1_000_123, 3_000_017])
+def test_select_narrow_static_bp(M, W, n):
+    """Static BP at widths 1..8: the predicate on packed words (four chunks per wave step,
+    SWAR for widths 1, 2, 4, 8), every comparison, ragged tails and remainders."""
+    v = datagen.uniform_bits(500 + W, n, W)
+    for bw in (W, O.BW_AUTO):
+        col = M.encode(v, fmt_of(M, O.STATIC_BP, bw))
+        for cmp, c0, c1 in narrow_preds(W):
+            want = O.select(v, cmp, c0, c1)
+            p = M.select(col, cmp, c0, c1, fmt_of(M, O.DELTA_DYN_BP))
+            np.testing.assert_array_equal(M.u32(p.decode()), want, err_msg=f"W={W} n={n} bw={bw} {cmp} {c0} {c1}")
+    if n == 100_003:
+        for kout in O.KINDS:
+            want = O.select(v, O.LT, (1 << W) // 3)
+            assert_column(M.select(col, O.LT, (1 << W) // 3, 0, fmt_of(M, kout)), want, kout)
+    M.sync()
+
+
 @pytest.mark.parametrize("sel", [0.0005, 0.01, 0.5, 0.999])
 def test_select_selectivity_sweep(M, sel):
     """Low selectivity makes output blocks span many segments (global staging)."""

@@ -119,7 +119,26 @@ def test_q3_exhaustive_matches_oracle(M, Q, star):
     q3.plan.close()
 
 
-@pytest.mark.parametrize("tune", [(1, 0), (2, 4), (4, 8), (8, 2)])
+def test_q3_greedy_runtime_search(M, Q, star):
+    """The greedy runtime search over fresh plans (inputs, then intermediates): the plan it
+    picks answers like the oracle, every chosen input holds the same values, and the search
+    visits 5 other formats per column."""
+    cols, thr, want, enc = star
+    names = list(Q.Q3(enc, thr, datagen.STAR_DIM_SIZES, N_FACT).names)
+    start = {k: M.fmt(M.STATIC_BP) for k in names}
+    gcols, gfmt, ms, trials = Q.greedy_runtime_formats(enc, thr, datagen.STAR_DIM_SIZES, N_FACT, start, reps=1)
+    assert ms > 0 and trials == 1 + 5 * (len(Q.Q3_INPUTS) + len(names))
+    for name, col in gcols.items():
+        np.testing.assert_array_equal(dec(M, col), cols[name], err_msg=name)
+    q3 = Q.Q3(gcols, thr, datagen.STAR_DIM_SIZES, N_FACT, formats=gfmt)
+    q3.plan.launch()
+    M.sync()
+    check_q3(M, q3, want)
+    assert [q3.plan.formats()[q3.names[k]] for k in names] == [gfmt[k].kind for k in names]
+    q3.plan.close()
+
+
+@pytest.mark.parametrize("tune", [(1, 0, 0), (2, 4, 1), (4, 8, 16), (8, 2, 2), (2, 0, 64)])
 def test_q3_branches(M, Q, star, tune):
     cols, thr, want, enc = star
     q3 = Q.Q3(enc, thr, datagen.STAR_DIM_SIZES, N_FACT)
@@ -184,6 +203,8 @@ def test_plan_errors(M):
         p.set_format(0, M.fmt(M.RLE))
     with pytest.raises(M.MorphError):
         p.set_tune(0, 8)
+    with pytest.raises(M.MorphError):
+        p.set_tune(1, 0, 65)
     p.run()
     assert int(p.read(0)[0]) == O.sum_(datagen.uniform_bits(1, 1000, 5))
     p.close()

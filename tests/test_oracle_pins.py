@@ -502,3 +502,84 @@ def test_q3_plan_matches_numpy():
     np.testing.assert_array_equal(r["out1"], np.bincount(g, weights=cols["m1"][ok], minlength=250).astype(np.uint64))
     np.testing.assert_array_equal(r["out2"], np.bincount(g, weights=cols["m2"][ok], minlength=250).astype(np.uint64))
     assert ok.sum() > 100
+
+
+# --------------------------------------------------------------------- selection labels (section 5.2)
+def test_size_targets_closed_form():
+    """bits per value = 2^j - 1 gives the target j / 6 exactly: bytes = n (2^j - 1) / 8."""
+    n = np.array([8, 64, 4096, 0], np.float64)
+    for j in range(7):
+        F = np.outer(np.where(n > 0, n, 8.0) * (2 ** j - 1) / 8, np.ones(6))
+        F[-1] = (2 ** j - 1) / 8 * 8  # n = 0 counts as n = 1: bytes = (2^j - 1) / 8 per value
+        t = O.size_targets(F, n)
+        np.testing.assert_array_equal(t[:-1], np.full((3, 6), j / 6.0))
+        np.testing.assert_allclose(t[-1], np.log2(1 + 8 * F[-1]) / 6, rtol=0, atol=0)
+
+
+def test_cost_targets_closed_form():
+    """picoseconds per value = 2^j - 1 gives j / 16: ns = n (2^j - 1) / 1000; negative times
+    count as zero."""
+    n = np.array([1000, 5000], np.float64)
+    for j in range(0, 24, 3):
+        C = np.outer(n * (2 ** j - 1) / 1000.0, np.ones(6))
+        np.testing.assert_allclose(O.cost_targets(C, n), np.full((2, 6), j / 16.0), rtol=1e-15, atol=1e-15)
+    assert np.all(O.cost_targets(np.full(6, -5.0), [10]) == 0.0)
+
+
+def test_exhaustive_choice_hand_cases():
+    rows = np.array([[5, 5, 5, 5, 5, 5], [9, 3, 3, 7, 1, 1], [0, 0, 1, 2, 3, 4], [7, 6, 5, 4, 3, 2]], np.uint64)
+    np.testing.assert_array_equal(O.exhaustive_choice(rows), [0, 4, 0, 5])
+
+
+def test_exhaustive_choice_is_the_smallest_encoding():
+    """On tiny columns the choice names the format whose actual encoding is the smallest
+    (the encoder's own footprint, not the closed-form one) at the lowest such kind."""
+    for seed in range(40):
+        n = int(datagen.stream(seed, 0, 1)[0] % 1500)
+        v = (datagen.stream(seed + 100, 0, n) >> np.uint64(60 - seed % 20)).astype(np.uint32)
+        if seed % 3 == 0:
+            v = np.sort(v)
+        sizes = [O.footprint(O.encode(v, k)) for k in O.KINDS]
+        k = int(O.exhaustive_choice(O.footprints(v))[0])
+        assert sizes[k] == min(sizes) and all(s > sizes[k] for s in sizes[:k]), (seed, sizes, k)
+
+
+# --------------------------------------------------------------------- calc, join pairs, group-by
+def test_calc_wraps_modulo_2_32():
+    a = np.array([0xFFFFFFFF, 0, 0x10000, 3, 7, 0x80000000], np.uint32)
+    b = np.array([1, 1, 0x10000, 0x55555556, 5, 2], np.uint32)
+    np.testing.assert_array_equal(O.calc(a, b, O.CALC_ADD), [0, 1, 0x20000, 0x55555559, 12, 0x80000002])
+    np.testing.assert_array_equal(O.calc(a, b, O.CALC_SUB), [0xFFFFFFFE, 0xFFFFFFFF, 0, 0xAAAAAAAD, 2, 0x7FFFFFFE])
+    np.testing.assert_array_equal(O.calc(a, b, O.CALC_MUL), [0xFFFFFFFF, 0, 0, 2, 35, 0])
+    v = datagen.uniform_bits(1, 5000, 32)
+    w = datagen.uniform_bits(2, 5000, 32)
+    np.testing.assert_array_equal(O.calc(O.calc(v, w, O.CALC_ADD), w, O.CALC_SUB), v)  # inverse operations
+    np.testing.assert_array_equal(O.calc(v, np.ones(5000, np.uint32), O.CALC_MUL), v)
+    with pytest.raises(O.OracleError):
+        O.calc(v, w[:10], O.CALC_ADD)
+
+
+def test_join_pairs_brute_force():
+    for seed in range(30):
+        D = 1 + int(datagen.stream(seed, 0, 1)[0] % 200)
+        n = int(datagen.stream(seed, 1, 1)[0] % 400)
+        keys = datagen.uniform_range(seed + 50, n, 0, D + 20)
+        dim = datagen.uniform_range(seed + 90, D, 0, 10)
+        s = O.select(dim, O.LT, 4)
+        left, right = O.join_pairs(keys, O.bitmap_from_positions(s, D), D)
+        pairs = [(i, j) for i in range(n) for j in s if keys[i] == j]
+        assert [(int(a), int(b)) for a, b in zip(left, right)] == pairs
+        # the left side is the semi-join
+        np.testing.assert_array_equal(left, O.semijoin(keys, O.bitmap_from_positions(s, D), D))
+
+
+def test_group_by_brute_force():
+    for seed in range(30):
+        n = int(datagen.stream(seed, 2, 1)[0] % 500)
+        keys = datagen.uniform_range(seed + 7, n, 0, 1 + seed * 37)
+        ids, distinct = O.group_by(keys)
+        for i in range(n):
+            assert ids[i] == sum(1 for d in set(int(x) for x in keys) if d < keys[i])
+        assert all(distinct[j] < distinct[j + 1] for j in range(distinct.size - 1))
+        np.testing.assert_array_equal(distinct[ids.astype(np.int64)] if n else distinct[:0], keys)
+        assert ids.size == n and (n == 0 or ids.max() == distinct.size - 1)
