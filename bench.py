@@ -602,8 +602,15 @@ def run_star(args, M, gen, torch, log):
                     fm = {k: M.fmt(int(kk)) for k, kk in zip(names, kinds[pol])}
                     q = queries.Q3(plain_cols if pol == "plain" else cols, thr, datagen.STAR_DIM_SIZES, n,
                                    formats=fm)
-                te = cold_times(torch, q.plan.run, max(2, args.steps // 2), flush)
-                tune, _ = q.plan.autotune(reps=2, cache=cache)  # right after the eager runs
+                # eager runs and graph runs on separate plan objects (see the executor notes)
+                qcols = [c for c in q.plan.inputs]
+                mk = lambda: queries.Q3(dict(zip(queries.Q3_INPUTS, qcols)), thr, datagen.STAR_DIM_SIZES, n,
+                                        formats={k: M.fmt(int(q.plan.steps[q.names[k]].out.kind)) for k in names})
+                qe = mk()
+                te = cold_times(torch, qe.plan.run, max(2, args.steps // 2), flush)
+                qe.plan.close()
+                del qe
+                tune, _ = q.plan.autotune(reps=2, cache=cache)
                 q.plan.launch()
                 torch.cuda.synchronize()
                 tg = cold_times(torch, q.plan.launch, args.steps, flush)
@@ -627,7 +634,11 @@ def run_star(args, M, gen, torch, log):
                     t_sum += tgm
                     t_all += tg
                     if roof is None:
-                        roof, dom = plan_roofline(M, q.plan, alg, "star")
+                        qr = mk()
+                        qr.plan.set_tune(*tune)
+                        roof, dom = plan_roofline(M, qr.plan, alg, "star")
+                        qr.plan.close()
+                        del qr
                 if pol == "greedy":
                     row["policies"][pol].update(
                         search_s=round(t_search, 1), trials=n_trials,
@@ -780,19 +791,25 @@ def run_batch(args, M, gen, torch, log):
     M.sync()
     rows = sum(sp["n"] for sp in spec)
     log(f"batch: {T} tasks, {rows} rows, inputs ready in {time.time() - t0:.1f}s")
-    plan = M.Plan(steps, inputs)
     reps = max(1, args.steps)
-    te1 = time_eager(torch, plan, reps)
-    plan.set_tune(8, 8)
-    te8 = time_eager(torch, plan, reps)
+    # eager runs and graph runs on separate plan objects (see the executor notes)
+    pe = M.Plan(steps, inputs)
+    te1 = time_eager(torch, pe, reps)
+    pe.set_tune(8, 8)
+    te8 = time_eager(torch, pe, reps)
+    pe.close()
     log(f"eager one stream {te1 * 1e3:.2f} ms, eager 8 streams {te8 * 1e3:.2f} ms")
+    plan = M.Plan(steps, inputs)
     cache = os.path.join(tempfile.gettempdir(), "ms_plan_tune_cache.txt")
     best, best_ms = plan.autotune(reps=2, cache=cache)
     tg = time_graph(torch, plan, reps)
-    arena = plan.arena_bytes()  # read before plan_roofline's eager run drops the captured graph
+    arena = plan.arena_bytes()
     log(f"autotuned {best} ({best_ms:.2f} ms in tuning), graph {tg * 1e3:.2f} ms")
     ue, alg = plan_account(M, plan, inputs)
-    roof, dom = plan_roofline(M, plan, alg, "batch")
+    pr = M.Plan(steps, inputs)
+    pr.set_tune(*best)
+    roof, dom = plan_roofline(M, pr, alg, "batch")
+    pr.close()
     res = base_line(args, "uncompressed-equivalent GB/s of 512 mixed column-operator tasks in one captured graph",
                     round(ue / tg / 1e9, 2), "GB/s", tg,
                     f"batch: {T} tasks, rows log-uniform in [1e4, 5e7] ({rows} rows), operator "
@@ -851,12 +868,16 @@ def run_q1(args, M, gen, torch, log):
     n = args.rows or 1_000_000
     A = M.encode(gen.uniform_bits(1, n, 10), M.fmt(M.STATIC_BP, 10))
     B = M.encode(gen.uniform_bits(2, n, 20), M.fmt(M.STATIC_BP, 20))
-    plan = queries.q1_plan(A, B, 103)
     reps = max(10, args.steps)
+    pe = queries.q1_plan(A, B, 103)  # eager runs and graph runs on separate plan objects
+    te = time_eager(torch, pe, reps)
+    pe.close()
+    plan = queries.q1_plan(A, B, 103)
     tg = time_graph(torch, plan, reps)
-    te = time_eager(torch, plan, reps)
     ue, alg = plan_account(M, plan, [A, B])
-    roof, dom = plan_roofline(M, plan, alg, "q1")
+    pr = queries.q1_plan(A, B, 103)
+    roof, dom = plan_roofline(M, pr, alg, "q1")
+    pr.close()
     res = base_line(args, "uncompressed-equivalent GB/s of Q1 (select -> project -> sum, captured graph)",
                     round(ue / tg / 1e9, 2), "GB/s", tg,
                     f"Q1: {n} rows, A uniform 10-bit static BP, B uniform 20-bit static BP, positions of A < 103 "

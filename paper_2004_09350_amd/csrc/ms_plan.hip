@@ -86,6 +86,15 @@ uint64_t fnv(uint64_t h, const void *p, size_t n) {
 
 }  // namespace
 
+// Events that fork a run onto the branch streams, order steps across branches and join
+// the branches back.  Eager runs use the plan's own set; every capture gets a fresh set
+// that lives and dies with the captured graph, so no event is ever recorded both in a
+// capture and outside one.
+struct EventSet {
+  hipEvent_t fork = nullptr;
+  std::vector<hipEvent_t> join, step;
+};
+
 struct ms_plan {
   std::vector<ms_step> steps;
   std::vector<const ms_column *> inputs;
@@ -100,8 +109,8 @@ struct ms_plan {
   void *arena_stream = nullptr;
   hipStream_t cap = nullptr;              // capture origin (captures need a non-null stream)
   std::vector<hipStream_t> br;            // branch streams
-  std::vector<hipEvent_t> step_ev, join_ev;
-  hipEvent_t fork_ev = nullptr;
+  EventSet eager_ev;                      // events of eager runs
+  EventSet graph_ev;                      // events recorded in the captured graph
 };
 
 namespace {
@@ -120,6 +129,35 @@ void assign_branches(ms_plan *p) {
   }
 }
 
+void destroy_events(EventSet &ev) {
+  if (ev.fork) (void)hipEventDestroy(ev.fork);
+  for (auto e : ev.join) (void)hipEventDestroy(e);
+  for (auto e : ev.step) (void)hipEventDestroy(e);
+  ev = EventSet();
+}
+
+// Sizes an event set for the plan's steps and branches.
+ms_status ensure_events(ms_plan *p, EventSet &ev) {
+  auto make = [](hipEvent_t &e) { return hipEventCreateWithFlags(&e, hipEventDisableTiming); };
+  if (!ev.fork) {
+    hipError_t e = make(ev.fork);
+    if (e != hipSuccess) return hip_fail(e, "event create");
+  }
+  while (ev.join.size() < p->tune.branches) {
+    hipEvent_t x;
+    hipError_t e = make(x);
+    if (e != hipSuccess) return hip_fail(e, "event create");
+    ev.join.push_back(x);
+  }
+  while (ev.step.size() < p->steps.size()) {
+    hipEvent_t x;
+    hipError_t e = make(x);
+    if (e != hipSuccess) return hip_fail(e, "event create");
+    ev.step.push_back(x);
+  }
+  return MS_OK;
+}
+
 ms_status ensure_streams(ms_plan *p) {
   if (!p->cap) {
     hipError_t e = hipStreamCreateWithFlags(&p->cap, hipStreamNonBlocking);
@@ -130,22 +168,8 @@ ms_status ensure_streams(ms_plan *p) {
     hipError_t e = hipStreamCreateWithFlags(&s, hipStreamNonBlocking);
     if (e != hipSuccess) return hip_fail(e, "stream create");
     p->br.push_back(s);
-    hipEvent_t ev;
-    e = hipEventCreateWithFlags(&ev, hipEventDisableTiming);
-    if (e != hipSuccess) return hip_fail(e, "event create");
-    p->join_ev.push_back(ev);
   }
-  if (!p->fork_ev) {
-    hipError_t e = hipEventCreateWithFlags(&p->fork_ev, hipEventDisableTiming);
-    if (e != hipSuccess) return hip_fail(e, "event create");
-  }
-  while (p->step_ev.size() < p->steps.size()) {
-    hipEvent_t ev;
-    hipError_t e = hipEventCreateWithFlags(&ev, hipEventDisableTiming);
-    if (e != hipSuccess) return hip_fail(e, "event create");
-    p->step_ev.push_back(ev);
-  }
-  return MS_OK;
+  return ensure_events(p, p->eager_ev);
 }
 
 const ms_column *column_of(const ms_plan *p, const std::vector<Result> &r, int32_t ref) {
@@ -188,8 +212,8 @@ ms_status exec_step(ms_plan *p, size_t i, void *s, std::vector<Result> &r) {
   }
 }
 
-// All steps, forked from and joined back into `origin`.
-ms_status run_steps(ms_plan *p, hipStream_t origin, std::vector<Result> &r) {
+// All steps, forked from and joined back into `origin`, ordered across branches by `ev`.
+ms_status run_steps(ms_plan *p, hipStream_t origin, std::vector<Result> &r, EventSet &ev) {
   r.assign(p->steps.size(), Result());
   const uint32_t B = p->tune.branches;
   rt::set_thread_wg_per_cu(p->tune.wg_per_cu);
@@ -199,23 +223,23 @@ ms_status run_steps(ms_plan *p, hipStream_t origin, std::vector<Result> &r) {
   if (B == 1) {
     for (size_t i = 0; i < p->steps.size() && st == MS_OK; i++) st = exec_step(p, i, origin, r);
   } else {
-    e = hipEventRecord(p->fork_ev, origin);
-    for (uint32_t b = 0; b < B && e == hipSuccess; b++) e = hipStreamWaitEvent(p->br[b], p->fork_ev, 0);
+    e = hipEventRecord(ev.fork, origin);
+    for (uint32_t b = 0; b < B && e == hipSuccess; b++) e = hipStreamWaitEvent(p->br[b], ev.fork, 0);
     for (size_t i = 0; i < p->steps.size() && st == MS_OK && e == hipSuccess; i++) {
       const ms_step &s = p->steps[i];
       const int b = p->branch_of[i];
       const char *ok = operand_kinds(s.op);
       const int32_t refs[2] = {ok[0] != '-' ? s.a : -1, ok[1] != '-' ? s.b : -1};
       for (int32_t ref : refs)
-        if (ref >= 0 && p->branch_of[ref] != b && e == hipSuccess) e = hipStreamWaitEvent(p->br[b], p->step_ev[ref], 0);
+        if (ref >= 0 && p->branch_of[ref] != b && e == hipSuccess) e = hipStreamWaitEvent(p->br[b], ev.step[ref], 0);
       if (e != hipSuccess) break;
       st = exec_step(p, i, p->br[b], r);
-      if (st == MS_OK) e = hipEventRecord(p->step_ev[i], p->br[b]);
+      if (st == MS_OK) e = hipEventRecord(ev.step[i], p->br[b]);
     }
     // always join every branch back, also after an error (a capture must end joined)
     for (uint32_t b = 0; b < B; b++) {
-      hipError_t e2 = hipEventRecord(p->join_ev[b], p->br[b]);
-      if (e2 == hipSuccess) e2 = hipStreamWaitEvent(origin, p->join_ev[b], 0);
+      hipError_t e2 = hipEventRecord(ev.join[b], p->br[b]);
+      if (e2 == hipSuccess) e2 = hipStreamWaitEvent(origin, ev.join[b], 0);
       if (e == hipSuccess) e = e2;
     }
   }
@@ -233,6 +257,7 @@ void drop_graph(ms_plan *p) {
   if (p->graph) (void)hipGraphDestroy(p->graph);
   p->exec = nullptr;
   p->graph = nullptr;
+  destroy_events(p->graph_ev);  // after the graph that recorded them
   for (auto &x : p->graph_res)
     if (x.col) ms_column_free(x.col);  // arena columns: frees only the handle
   p->graph_res.clear();
@@ -242,14 +267,17 @@ void drop_graph(ms_plan *p) {
   if (p->last_graph) p->last_graph = false;
 }
 
-// One capture of the plan on the plan's capture stream with arena `a`.
-ms_status capture(ms_plan *p, rt::Arena *a, std::vector<Result> &r, hipGraph_t *g) {
+// One capture of the plan on the plan's capture stream with arena `a`, recording the
+// events of `ev` (which must not be used outside this capture's graph).
+ms_status capture(ms_plan *p, rt::Arena *a, std::vector<Result> &r, hipGraph_t *g, EventSet &ev) {
   *g = nullptr;
+  ms_status st = ensure_events(p, ev);
+  if (st != MS_OK) return st;
   hipError_t e = hipStreamBeginCapture(p->cap, hipStreamCaptureModeThreadLocal);
   if (e != hipSuccess) return hip_fail(e, "begin capture");
   rt::set_thread_arena(a);
   prof_suspend(true);  // no timing events inside a graph
-  ms_status st = run_steps(p, p->cap, r);
+  st = run_steps(p, p->cap, r, ev);
   prof_suspend(false);
   rt::set_thread_arena(nullptr);
   e = hipStreamEndCapture(p->cap, g);
@@ -318,9 +346,7 @@ ms_status ms_plan_destroy(ms_plan *p) {
   drop_graph(p);
   free_results(p->eager);
   for (auto s : p->br) (void)hipStreamDestroy(s);
-  for (auto e : p->step_ev) (void)hipEventDestroy(e);
-  for (auto e : p->join_ev) (void)hipEventDestroy(e);
-  if (p->fork_ev) (void)hipEventDestroy(p->fork_ev);
+  destroy_events(p->eager_ev);
   if (p->cap) (void)hipStreamDestroy(p->cap);
   delete p;
   return MS_OK;
@@ -378,7 +404,7 @@ ms_status ms_plan_run(ms_plan *p, void *stream) {
     for (auto b : p->br) (void)hipStreamSynchronize(b);
     free_results(p->eager);
   }
-  st = run_steps(p, s, p->eager);
+  st = run_steps(p, s, p->eager, p->eager_ev);
   p->last_graph = false;
   return st;
 }
@@ -389,15 +415,21 @@ ms_status ms_plan_launch(ms_plan *p, void *stream) {
   if (!p->exec) {
     ms_status st = ensure_streams(p);
     if (st != MS_OK) return st;
-    // 1) size the arena with a capture that is never instantiated
+    // nothing of an earlier eager run or replay is in flight on the plan's streams when
+    // a capture starts
+    hipError_t se = hipDeviceSynchronize();
+    if (se != hipSuccess) return hip_fail(se, "device sync");
+    // 1) size the arena with a capture that is never instantiated (its own events)
     rt::Arena m;
     m.measure = true;
     std::vector<Result> tmp;
     hipGraph_t g = nullptr;
-    st = capture(p, &m, tmp, &g);
+    EventSet mev;
+    st = capture(p, &m, tmp, &g, mev);
     for (auto &x : tmp)
       if (x.col) ms_column_free(x.col);
     if (g) (void)hipGraphDestroy(g);
+    destroy_events(mev);
     if (st != MS_OK) return st;
     // 2) back it and capture for real
     p->arena_bytes = m.used + 256;
@@ -409,7 +441,7 @@ ms_status ms_plan_launch(ms_plan *p, void *stream) {
     rt::Arena a;
     a.base = static_cast<char *>(p->arena);
     a.size = p->arena_bytes;
-    st = capture(p, &a, p->graph_res, &p->graph);
+    st = capture(p, &a, p->graph_res, &p->graph, p->graph_ev);
     if (st != MS_OK) {
       drop_graph(p);
       return st;

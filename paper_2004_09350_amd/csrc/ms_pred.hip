@@ -358,11 +358,69 @@ __global__ __launch_bounds__(kWG) void k_pred(PredArgs a) {
 }
 
 
+// Semi-join against a bitmap larger than the 256-thread kernel's LDS part: one workgroup of
+// 1024 threads per CU keeps the first kWideLdsBits bits (142 KB) in LDS and probes only
+// the keys above them through the caches.  Its four quarters do exactly the work of four
+// consecutive workgroups of k_pred<1> (segments 4b .. 4b+3 of the same G, four waves each),
+// so the emit phase sees the same segments and counts.  Keys in any format but RLE.
+constexpr unsigned kWideWG = 1024;
+constexpr unsigned kWideLdsWords = 36352;
+constexpr unsigned long long kWideLdsBits = 32ull * kWideLdsWords;
+
+__global__ __launch_bounds__(kWideWG) void k_semijoin_wide(PredArgs a, unsigned G) {
+  __shared__ unsigned bm[kWideLdsWords];
+  __shared__ unsigned s_cnt[kWideWG / 64], s_or[kWideWG / 64];
+  const InCol in = load_in(a.in);
+  const unsigned lane = lane_id(), w = wave_id(), q = w >> 2, w4 = w & 3u;
+  const unsigned seg = 4u * blockIdx.x + q;
+  const unsigned long long C = (in.n + kBlk - 1) / kBlk;
+  unsigned long long cb = 0, ce = 0;
+  if (seg < G) segment(C, seg, G, cb, ce);
+  const unsigned long long domain = a.domain;
+  const unsigned *bitmap = a.bitmap;
+  unsigned char *bitmask = a.bitmask;
+  const unsigned long long lds_bits = min(domain, kWideLdsBits);
+  const unsigned nw = (unsigned)((lds_bits + 31) / 32);
+  for (unsigned t = threadIdx.x; t < nw; t += kWideWG) bm[t] = bitmap[t];
+  __syncthreads();
+  unsigned cnt = 0, orv = 0;
+  stream_chunks(in, cb, ce, w4, lane, nullptr, a.in.hdr, [&](unsigned long long c, const unsigned (&v)[8]) {
+    const unsigned long long idx0 = c * kBlk + 8ull * lane;
+    const unsigned valid = chunk_valid(c, lane, in.n);
+    unsigned mask = 0;
+#pragma unroll
+    for (int i = 0; i < 8; i++) {
+      const unsigned x = v[i];
+      if ((unsigned long long)x < domain) {
+        const unsigned word = (unsigned long long)x < lds_bits ? bm[x >> 5] : bitmap[x >> 5];
+        if ((word >> (x & 31)) & 1u) mask |= 1u << i;
+      }
+    }
+    mask &= valid;
+    bitmask[c * 64 + lane] = (unsigned char)mask;
+    cnt += __popc(mask);
+    if (mask) orv |= (unsigned)idx0 | (31u - __clz(mask));
+  });
+  cnt = wave_add(cnt);
+  orv = wave_or(orv);
+  if (lane == 0) {
+    s_cnt[w] = cnt;
+    s_or[w] = orv;
+  }
+  __syncthreads();
+  if (w4 == 0 && lane == 0 && seg < G) {
+    a.seg_count[seg] = s_cnt[w] + s_cnt[w + 1] + s_cnt[w + 2] + s_cnt[w + 3];
+    a.seg_or[seg] = s_or[w] | s_or[w + 1] | s_or[w + 2] | s_or[w + 3];
+  }
+}
+
 hipError_t launch_pred(const PredArgs &a, unsigned G, void *s) {
   // the semi-join probes (the first kLdsBitmapBits bits of) its bitmap in LDS
   const size_t shm = a.mode == 1 ? kRingBytes : ring_shm(a.in);
   if (a.mode == 0)
     MS_LAUNCH_SHM("k_pred<0>", k_pred<0>, G, kWG, shm, s, a);
+  else if (a.mode == 1 && a.in.kind != RLE && a.domain > kLdsBitmapBits)
+    MS_LAUNCH(k_semijoin_wide, (G + 3) / 4, kWideWG, s, a, G);
   else if (a.mode == 1)
     MS_LAUNCH_SHM("k_pred<1>", k_pred<1>, G, kWG, shm, s, a);
   else

@@ -49,7 +49,19 @@ struct ihipEvent_t {
   unsigned long long seq = 0;
   std::map<hipStream_t, unsigned long long> covers;
   unsigned long long when = 0;  // eager: queue position
+  bool in_capture = false, outside = false;  // ever recorded inside / outside a capture
 };
+
+namespace {
+// The executor keeps capture events and eager events apart; an event used both ways is
+// reported (the runtime's handling of such reuse is not something the executor relies on).
+void check_event_use(hipEvent_t e) {
+  if (e->in_capture && e->outside) {
+    std::fprintf(stderr, "model: event %p recorded both inside and outside a stream capture\n", (void *)e);
+    std::abort();
+  }
+}
+}  // namespace
 struct hipGraphExec {
   std::vector<std::function<void()>> work;
 };
@@ -127,12 +139,15 @@ hipError_t hipEventRecord(hipEvent_t e, hipStream_t s) {
     e->stream = s;
     e->seq = s->seq;
     e->covers = s->covers;
+    e->in_capture = true;
   } else {
     e->graph = nullptr;
     e->nodes.clear();
     e->stream = s;
     e->when = g_clock;
+    e->outside = true;
   }
+  check_event_use(e);
   return hipSuccess;
 }
 hipError_t hipStreamWaitEvent(hipStream_t s, hipEvent_t e, unsigned) {

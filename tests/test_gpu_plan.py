@@ -172,15 +172,15 @@ def test_autotune_and_cache(M, Q, tmp_path):
     cache = str(tmp_path / "tune.txt")
     plan = Q.q1_plan(A, B, 103)
     best, ms = plan.autotune(reps=2, cache=cache)
-    assert best[0] in (1, 2, 4, 8) and best[1] in (0, 2, 4, 8, 16) and ms > 0
+    assert best[0] in (1, 2, 4, 8) and best[1] in (0, 2, 4, 8, 16) and best[2] in (0, 1, 2, 8, 16) and ms > 0
     assert plan.tune() == best
-    lines = open(cache).read().split()
-    assert len(lines) == 4 and (int(lines[1]), int(lines[2])) == best
+    lines = open(cache).read().split()  # signature, branches, workgroups per CU, chunks per workgroup, ms
+    assert len(lines) == 5 and (int(lines[1]), int(lines[2]), int(lines[3])) == best
     plan.launch()
     assert int(plan.read(2)[0]) == want["sum"]
     plan2 = Q.q1_plan(A, B, 103)
     best2, ms2 = plan2.autotune(reps=2, cache=cache)  # from the cache, no timing
-    assert best2 == best and abs(ms2 - float(lines[3])) < 1e-3
+    assert best2 == best and abs(ms2 - float(lines[4])) < 1e-3
     plan2.run()
     assert int(plan2.read(2)[0]) == want["sum"]
     plan.close()
