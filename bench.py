@@ -54,7 +54,10 @@ def parse():
                          "mixed tasks, one graph vs one launch sequence per task; q1: the simple "
                          "select-project-sum query")
     ap.add_argument("--no-sweep", action="store_true", help="star: skip the operator/format sweep")
-    ap.add_argument("--no-greedy", action="store_true", help="star: skip the greedy runtime search policy")
+    ap.add_argument("--greedy", action="store_true",
+                    help="star: add the greedy runtime search policy (hundreds of full-size plan captures)")
+    ap.add_argument("--star-autotune", action="store_true",
+                    help="star: autotune every policy's plan at full size instead of the fixed launch shape")
     ap.add_argument("--sweep-steps", type=int, default=2)
     ap.add_argument("--steps", type=int, default=5)
     ap.add_argument("--warmup", type=int, default=1)
@@ -505,6 +508,11 @@ def time_eager(torch, plan, reps):
 # BP (the paper's base-data compression) and choose the intermediates' formats.
 POLICIES = ("plain", "uncompr_inter", "static", "exhaustive", "learned", "learned_decode", "greedy")
 FLUSH_BYTES = 2 << 30  # written between timed runs: evicts the 256 MB MALL and the L2s
+# Launch shape of the full-size star plans (two branches, each operator's default grid and
+# chunks per workgroup): re-capturing a full-size star plan many times in one process (the
+# autotuner's trials, the greedy search) is kept out of the default run; --star-autotune
+# and --greedy turn it on.
+STAR_TUNE = (2, 0, 0)
 
 
 def cold_times(torch, fn, reps, flush):
@@ -572,6 +580,7 @@ def run_star(args, M, gen, torch, log):
             f"{time.time() - t0:.1f}s")
         for sname, sel_s in settings:
             thr = datagen.star_thresholds(sel_s)
+            log(f"  {sname}: probe run (statistics and footprints of every intermediate)")
             probe = queries.Q3(cols, thr, datagen.STAR_DIM_SIZES, n, extra=("stats", "footprints"))
             probe.plan.run()
             names = list(probe.names)
@@ -583,11 +592,13 @@ def run_star(args, M, gen, torch, log):
                      "exhaustive": selector.exhaustive(fps), "learned": selector.pick(sel, feats),
                      "learned_decode": selector.pick(sel, feats, M.OBJ_DECODE)}
             kinds["plain"] = kinds["uncompr_inter"]
+            log(f"  {sname}: formats picked")
             row = dict(seed=seed, setting=sname, rows_final=0, policies={})
             for pol in POLICIES:
-                if pol == "greedy" and args.no_greedy:
+                if pol == "greedy" and not args.greedy:
                     continue
                 greedy_inputs, t_search = {}, 0.0
+                log(f"  {sname}: policy {pol}")
                 if pol == "greedy":
                     # the paper's greedy runtime search from plain uncompressed execution: base
                     # columns first, then the intermediates in plan order
@@ -610,7 +621,12 @@ def run_star(args, M, gen, torch, log):
                 te = cold_times(torch, qe.plan.run, max(2, args.steps // 2), flush)
                 qe.plan.close()
                 del qe
-                tune, _ = q.plan.autotune(reps=2, cache=cache)
+                if args.star_autotune:
+                    log(f"  {sname}: {pol} autotune")
+                    tune, _ = q.plan.autotune(reps=2, cache=cache)
+                else:
+                    q.plan.set_tune(*STAR_TUNE)
+                    tune = q.plan.tune()
                 q.plan.launch()
                 torch.cuda.synchronize()
                 tg = cold_times(torch, q.plan.launch, args.steps, flush)
@@ -671,7 +687,9 @@ def run_star(args, M, gen, torch, log):
                     "wide and narrow filters", {"rows": n, "selector": wsrc})
     res.update(ms_per_step_median=round(float(np.median(t_all)) * 1e3, 3), roofline=roof, dominant_kernel=dom,
                runs=results, copy_bandwidth_gbs=copy_bw, source_sha=source_sha(),
-               protocol="each timed run preceded by a 2 GiB device write (not timed); HIP events per run")
+               protocol="each timed run preceded by a 2 GiB device write (not timed); HIP events per run",
+               launch_shape=("autotuned per plan" if args.star_autotune else
+                             f"fixed {list(STAR_TUNE)} (branches, wg/CU, chunks/wg)"))
     if not args.no_cpu_baseline:
         res["cpu_baseline"] = cpu_baseline_star(min(n, args.cpu_rows or 40_000_000))
     return res

@@ -406,6 +406,12 @@ ms_status ms_plan_run(ms_plan *p, void *stream) {
   }
   st = run_steps(p, s, p->eager, p->eager_ev);
   p->last_graph = false;
+  if (st != MS_OK) {  // no partial results survive a failed run
+    (void)hipStreamSynchronize(s);
+    for (auto b : p->br) (void)hipStreamSynchronize(b);
+    free_results(p->eager);
+    p->eager.clear();
+  }
   return st;
 }
 

@@ -15,7 +15,8 @@ import numpy as np
 import torch
 
 HERE = os.path.dirname(os.path.abspath(__file__))
-LIB_PATH = os.path.join(HERE, "libmorphgpu.so")
+# MS_LIBMORPHGPU selects another build of the library (e.g. one with host-side sanitizers)
+LIB_PATH = os.environ.get("MS_LIBMORPHGPU") or os.path.join(HERE, "libmorphgpu.so")
 
 UNCOMPR, STATIC_BP, DYN_BP, DELTA_DYN_BP, FOR_DYN_BP, RLE = range(6)
 KINDS = (UNCOMPR, STATIC_BP, DYN_BP, DELTA_DYN_BP, FOR_DYN_BP, RLE)

@@ -268,3 +268,33 @@ const char *hipGetErrorString(hipError_t e) {
   std::snprintf(buf, sizeof(buf), "model error %d", e);
   return buf;
 }
+
+// ----------------------------------------------------------- calls of the column library's host unit
+hipError_t hipGetDevice(int *device) {
+  *device = 0;
+  return hipSuccess;
+}
+hipError_t hipGetDeviceProperties(hipDeviceProp_t *prop, int) {
+  prop->multiProcessorCount = 256;
+  return hipSuccess;
+}
+hipError_t hipGetSymbolAddress(void **ptr, const void *symbol) {
+  *ptr = const_cast<void *>(symbol);
+  return hipSuccess;
+}
+hipError_t hipMallocAsync(void **ptr, size_t bytes, hipStream_t s) {
+  if (s && s->graph) return hipErrorStreamCaptureUnsupported;
+  *ptr = std::calloc(1, bytes ? bytes : 1);
+  return *ptr ? hipSuccess : hipErrorInvalidValue;
+}
+hipError_t hipFreeAsync(void *ptr, hipStream_t s) {
+  if (s && s->graph) return hipErrorStreamCaptureUnsupported;
+  model::submit(nullptr, [ptr]() { std::free(ptr); });  // after the work queued before it
+  return hipSuccess;
+}
+hipError_t hipMemcpyAsync(void *dst, const void *src, size_t bytes, hipMemcpyKind, hipStream_t s) {
+  model::submit(s, [dst, src, bytes]() { std::memcpy(dst, src, bytes); });
+  return hipSuccess;
+}
+hipError_t hipGetLastError(void) { return hipSuccess; }
+

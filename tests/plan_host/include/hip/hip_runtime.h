@@ -49,3 +49,19 @@ hipError_t hipGraphDestroy(hipGraph_t g);
 hipError_t hipDeviceSynchronize(void);
 hipError_t hipMemcpy(void *dst, const void *src, size_t bytes, hipMemcpyKind kind);
 const char *hipGetErrorString(hipError_t e);
+
+// What the column library's host unit (csrc/ms_api.hip) needs besides the executor's calls:
+// its one device-side array becomes a host array.
+#define __device__
+#define __align__(n) alignas(n)
+#define HIP_SYMBOL(x) (reinterpret_cast<const void *>(&(x)))
+struct hipDeviceProp_t {
+  int multiProcessorCount;
+};
+hipError_t hipGetDevice(int *device);
+hipError_t hipGetDeviceProperties(hipDeviceProp_t *prop, int device);
+hipError_t hipGetSymbolAddress(void **ptr, const void *symbol);
+hipError_t hipMallocAsync(void **ptr, size_t bytes, hipStream_t s);
+hipError_t hipFreeAsync(void *ptr, hipStream_t s);
+hipError_t hipMemcpyAsync(void *dst, const void *src, size_t bytes, hipMemcpyKind kind, hipStream_t s);
+hipError_t hipGetLastError(void);
