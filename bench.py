@@ -41,6 +41,7 @@ ROOT = os.path.dirname(os.path.abspath(__file__))
 sys.path.insert(0, ROOT)
 
 HBM_PEAK_GBS = 8000.0
+LDS_BITMAP_BITS = 1 << 18  # semi-join bitmaps up to this many bits sit whole in a workgroup's dynamic LDS
 DISTS = ("U4", "U12", "U24", "U32", "SORTED", "RUNS")
 SELECTIVITIES = (0.01, 0.10, 0.50)
 
@@ -417,7 +418,11 @@ def plan_account(M, plan, inputs, log=None):
         elif op in (M.OP_SELECT, M.OP_SEMIJOIN):
             a = inf(s.a)
             ue_total += 4 * (a["n"] + out["n"])
-            add("k_pred<0>" if op == M.OP_SELECT else "k_pred<1>", a["footprint"])
+            if op == M.OP_SELECT:
+                kpred = "k_pred<0>"
+            else:  # bitmaps beyond the workgroup's dynamic LDS go to the 1024-thread wide-LDS kernel
+                kpred = "k_semijoin_wide" if s.param > LDS_BITMAP_BITS and a["kind"] != M.RLE else "k_pred<1>"
+            add(kpred, a["footprint"])
             add("k_emit", out["footprint"])
         elif op == M.OP_BITMAP:
             a = inf(s.a)

@@ -83,15 +83,19 @@ typedef void (*ms_free_fn)(void *ptr, uint64_t bytes, void *stream, void *ctx);
 ms_status ms_init(ms_alloc_fn alloc, ms_free_fn free_fn, void *ctx);
 const char *ms_last_error(void);
 
-/* Column construction.  ms_column_encode compresses n device values into fmt
+/* Column construction (section 4.1: a column is one buffer holding its first
+ * floor(n/bs) values in its format and the n mod bs rest uncompressed, with the sizes of
+ * both parts kept as metadata).  ms_column_encode compresses n device values into fmt
  * (static BP with an explicit width raises MS_ERR_VALUE_TOO_WIDE through ms_sync
  * when a main-part value needs more bits).  The result has the canonical layout:
  * blocks in order, directory offsets = running sums of 16*w_k words. */
 ms_status ms_column_encode(const uint32_t *dev_vals, uint64_t n, ms_format fmt, void *stream, ms_column **out);
-/* Wrap n uncompressed device values without copying; the memory stays owned by the
- * caller and must outlive the column.  dev_vals must be 16-byte aligned. */
+/* Wrap n uncompressed device values without copying (uncompressed is one of the formats,
+ * section 4.1); the memory stays owned by the caller and must outlive the column.
+ * dev_vals must be 16-byte aligned. */
 ms_status ms_column_wrap_uncompr(const uint32_t *dev_vals, uint64_t n, void *stream, ms_column **out);
-/* Decode into dev_out (room for the column's element count). */
+/* Decode into dev_out (room for the column's element count): the decompression half of
+ * section 3.2's morph into the uncompressed format. */
 ms_status ms_column_decode(const ms_column *col, uint32_t *dev_out, void *stream);
 ms_status ms_column_free(ms_column *col);
 
@@ -109,10 +113,12 @@ typedef struct {
   uint32_t or_all;          /* OR of all values */
   uint32_t sorted;          /* 1 when known strictly increasing (position lists) */
 } ms_column_info;
-/* Synchronises `stream`, then reports the column's layout and footprint. */
+/* Synchronises `stream`, then reports the column's layout and footprint (the metadata of
+ * section 4.1: sizes of the compressed main part and the remainder, plus format fields). */
 ms_status ms_column_info_get(const ms_column *col, void *stream, ms_column_info *out);
 
-/* Sections for inspection and parity checks; copied to host after a sync. */
+/* Sections of the column buffer of section 4.1, for inspection and parity checks; copied
+ * to host after a sync. */
 typedef enum {
   MS_SEC_WIDTHS = 0, MS_SEC_OFFSETS = 1, MS_SEC_BASES = 2, MS_SEC_PAYLOAD = 3, MS_SEC_REM = 4,
   MS_SEC_RVALUES = 5, MS_SEC_RSTARTS = 6
@@ -123,7 +129,9 @@ typedef enum {
 ms_status ms_column_read_section(const ms_column *col, ms_section sec, void *host_dst, uint64_t bytes,
                                  void *stream, uint64_t *copied);
 /* Rewrite the column into an exactly sized buffer with the canonical layout (DynBP
- * payload blocks contiguous and in order).  Synchronises `stream`. */
+ * payload blocks contiguous and in order; section 4.1's continuous buffer).  Operator
+ * outputs are allocated for their worst case; this returns the unused capacity.
+ * Synchronises `stream`. */
 ms_status ms_column_shrink(ms_column *col, void *stream);
 
 /* Format change, section 3.2 "direct morphing": out = encode_fmt(decode(in)). */
@@ -133,8 +141,10 @@ ms_status ms_morph(const ms_column *in, ms_format fmt, void *stream, ms_column *
 ms_status ms_select(const ms_column *in, ms_cmp cmp, uint32_t c0, uint32_t c1, ms_format fmt, void *stream,
                     ms_column **out);
 /* Bitmap with bit p set for every position p (domain bits, 32-bit words, bit p in word
- * p/32 at position p%32).  dev_bitmap must hold ceil(domain/32) words; it is fully
- * written.  A position >= domain raises MS_ERR_OUT_OF_RANGE. */
+ * p/32 at position p%32): the build side of the semi-join below, i.e. the qualifying
+ * dimension rows of one filter of the star-schema plans of section 5.2 (section 4.2 keeps
+ * to the operators those plans need).  dev_bitmap must hold ceil(domain/32) words; it is
+ * fully written.  A position >= domain raises MS_ERR_OUT_OF_RANGE. */
 ms_status ms_bitmap_from_positions(const ms_column *pos, uint64_t domain, uint32_t *dev_bitmap, void *stream);
 /* semi-join of a foreign-key column against a dimension bitmap (the star plans of
  * section 5.2): ascending i with keys_i < domain and bit keys_i set. */
@@ -143,8 +153,10 @@ ms_status ms_semijoin(const ms_column *keys, const uint32_t *dev_bitmap, uint64_
 /* project (section 4.2): out_j = data[pos_j] in pos's order; a position >= |data|
  * raises MS_ERR_OUT_OF_RANGE (that element reads 0). */
 ms_status ms_project(const ms_column *data, const ms_column *pos, ms_format fmt, void *stream, ms_column **out);
-/* intersect of two strictly increasing position lists; unsorted input raises
- * MS_ERR_NOT_SORTED.  `domain` bounds every position (positions < domain). */
+/* intersect of two strictly increasing position lists: combines the fact-table rows that
+ * pass the filters of two dimensions in the star-schema plans of section 5.2 (the
+ * conjunction of their semi-joins); unsorted input raises MS_ERR_NOT_SORTED.  `domain`
+ * bounds every position (positions < domain). */
 ms_status ms_intersect(const ms_column *a, const ms_column *b, uint64_t domain, ms_format fmt, void *stream,
                        ms_column **out);
 /* sum (section 5.1): *dev_result = sum of all values mod 2^64. */

@@ -243,6 +243,19 @@ __device__ __forceinline__ void pred_rle_direct(const InCol &in, unsigned long l
   }
 }
 
+// Whether the RLE runs of chunks [cb, ce) average at least kRleDirectRun rows: then the
+// per-run walk above does less work than decoding every row (the chunk stream below
+// handles one row per value, whatever the run lengths).
+constexpr unsigned long long kRleDirectRun = 16;
+__device__ __forceinline__ bool rle_long_runs(const InCol &in, unsigned long long cb, unsigned long long ce,
+                                              unsigned lane) {
+  if (ce <= cb || in.runs == 0) return false;
+  const unsigned long long r0 = cb * kBlk, r1 = min(ce * kBlk, in.n);
+  if (r1 <= r0) return false;
+  const unsigned long long a = rle_find_wave(in, r0, lane, 0), b = rle_find_wave(in, r1 - 1, lane, a);
+  return r1 - r0 >= kRleDirectRun * (b - a + 1);
+}
+
 // ---------------------------------------------------------------------------------------------
 // Compaction phase 1: predicate -> one bit per row, count and OR per segment.
 // mode 0: range predicate ((v - lo) <= span) != neg, emits positions
@@ -280,7 +293,7 @@ __global__ __launch_bounds__(kWG) void k_pred(PredArgs a) {
   }
   unsigned long long c_rest = cb;  // chunks [cb, c_rest) done by the narrow path
   if constexpr (MODE == 0) {
-    if (in.kind == RLE) {  // a contiguous quarter of the segment per wave
+    if (in.kind == RLE && rle_long_runs(in, cb, ce, lane)) {  // a contiguous quarter of the segment per wave
       const unsigned long long nseg = ce - cb;
       pred_rle_direct(in, cb + nseg * w / kWaves, cb + nseg * (w + 1) / kWaves, lane, ring + w * kRing * kBlk, lo,
                       span, neg, bitmask, cnt, orv);
