@@ -828,6 +828,16 @@ def run_batch(args, M, gen, torch, log):
     tg = time_graph(torch, plan, reps)
     arena = plan.arena_bytes()
     log(f"autotuned {best} ({best_ms:.2f} ms in tuning), graph {tg * 1e3:.2f} ms")
+    # batched persistent launches (one launch per kernel kind and phase of each plan level)
+    pb = M.Plan(steps, inputs)
+    pb.set_tune(1, best[1], best[2], 1)
+    tbe = time_eager(torch, pb, reps)
+    pb.close()
+    pb = M.Plan(steps, inputs)
+    pb.set_tune(1, best[1], best[2], 1)
+    tbg = time_graph(torch, pb, reps)
+    pb.close()
+    log(f"batched persistent launches: eager {tbe * 1e3:.2f} ms, graph {tbg * 1e3:.2f} ms")
     ue, alg = plan_account(M, plan, inputs)
     pr = M.Plan(steps, inputs)
     pr.set_tune(*best)
@@ -840,7 +850,10 @@ def run_batch(args, M, gen, torch, log):
                     {"tasks": T, "rows_total": rows})
     res.update(graph_ms=round(tg * 1e3, 3), eager_one_stream_ms=round(te1 * 1e3, 3),
                eager_8_streams_ms=round(te8 * 1e3, 3), speedup_vs_one_launch_sequence_per_task=round(te1 / tg, 3),
-               tune={"branches": best[0], "wg_per_cu": best[1], "chunks_per_wg": best[2]}, arena_gb=round(arena / 1e9, 2),
+               tune={"branches": best[0], "wg_per_cu": best[1], "chunks_per_wg": best[2], "batch": best[3]},
+               batched_graph_ms=round(tbg * 1e3, 3), batched_eager_ms=round(tbe * 1e3, 3),
+               speedup_batched_graph_vs_one_launch_sequence_per_task=round(te1 / tbg, 3),
+               arena_gb=round(arena / 1e9, 2),
                roofline=roof, dominant_kernel=dom, source_sha=source_sha())
     if not args.no_cpu_baseline:
         res["cpu_baseline"] = cpu_baseline_batch(spec, cap=args.cpu_rows or 1_000_000, max_tasks=len(spec))

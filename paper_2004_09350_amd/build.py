@@ -20,7 +20,7 @@ _PER_KIND = [(src, [f"-DMS_OK={k}"]) for src in ("ms_project.hip", "ms_morph.hip
 LIBS = {
     "libmorphgpu.so": _PER_KIND + [("ms_kernels.hip", []), ("ms_api.hip", []), ("ms_plan.hip", []),
                                    ("ms_selector.hip", []), ("ms_pred.hip", []),
-                                   ("ms_ops2.hip", [])],
+                                   ("ms_ops2.hip", []), ("ms_batch.hip", [])],
     "libmsgen.so": [("datagen.hip", [])],
 }
 JOBS = max(1, min(16, int(os.environ.get("MAX_JOBS", os.cpu_count() or 1))))

@@ -11,6 +11,7 @@
 #include <vector>
 
 #include "../../include/morphgpu.h"
+#include "ms_batch.h"
 #include "ms_kernels.h"
 #include "ms_runtime.h"
 
@@ -76,6 +77,7 @@ void *dev_alloc(uint64_t bytes, void *stream) {
 void dev_free(void *p, uint64_t bytes, void *stream) {
   if (!p || t_arena) return;
   if (bytes == 0) bytes = 256;
+  if (batch::defer_free(p, bytes, stream)) return;  // its users are recorded, not yet issued
   if (g_free)
     g_free(p, bytes, stream, g_ctx);
   else

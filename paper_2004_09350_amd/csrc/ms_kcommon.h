@@ -16,6 +16,34 @@ __device__ __forceinline__ void segment(unsigned long long C, unsigned s, unsign
   ce = C * (s + 1) / G;
 }
 
+// A batched persistent launch (see BatchQueue): every workgroup takes tickets until they
+// run out and runs `body(task args, segment, segments of that task)` for each.  Tasks come
+// in decreasing size (longest first), so the big tasks' segments start first and the small
+// ones fill in behind them.  No workgroup waits for another: a workgroup leaves once the
+// tickets are gone, and every body is a complete workgroup program (its barriers are
+// reached by all of the workgroup's threads).
+template <class Args, class Body>
+__device__ __forceinline__ void batch_run(const Args *__restrict__ tasks, const BatchQueue &q, Body &&body) {
+  __shared__ unsigned s_ticket;
+  const unsigned total = q.seg_prefix[q.n_tasks];
+  for (;;) {
+    if (threadIdx.x == 0) s_ticket = atomicAdd(q.ticket, 1u);
+    __syncthreads();
+    const unsigned t = __builtin_amdgcn_readfirstlane(s_ticket);
+    __syncthreads();  // every thread holds t before the next ticket replaces it
+    if (t >= total) break;
+    unsigned lo = 0, hi = q.n_tasks;  // the task: the last i with seg_prefix[i] <= t
+    while (hi - lo > 1) {
+      const unsigned mid = (lo + hi) >> 1;
+      if (q.seg_prefix[mid] <= t) lo = mid;
+      else hi = mid;
+    }
+    const Args a = tasks[lo];
+    body(a, t - q.seg_prefix[lo], q.seg_prefix[lo + 1] - q.seg_prefix[lo]);
+    __syncthreads();  // the body's LDS is free before the next ticket's body starts
+  }
+}
+
 // Workgroup reductions (256 threads).
 __device__ __forceinline__ unsigned long long wg_add64(unsigned long long x, unsigned long long *sh) {
   x = wave_add64(x);

@@ -44,6 +44,50 @@ struct EmitArgs {
   unsigned *partials;
 };
 
+// Batched persistent launches: one launch runs the same kernel for many operators of a plan
+// level.  Task i (in decreasing size) has seg_prefix[i+1] - seg_prefix[i] segments, the
+// workgroups of its ordinary launch; workgroups take tickets t = 0, 1, ... from *ticket
+// (zeroed before the launch), ticket t being segment t - seg_prefix[i] of the last task i
+// with seg_prefix[i] <= t.
+struct BatchQueue {
+  const unsigned *seg_prefix;  // n_tasks + 1 entries, seg_prefix[0] = 0
+  unsigned n_tasks;
+  unsigned *ticket;
+};
+struct SumArgs {
+  ColView in;
+  unsigned long long *partials;
+};
+struct SumFinishArgs {
+  const unsigned long long *partials;
+  unsigned G;
+  unsigned long long *result;
+};
+struct GroupSumArgs {
+  ColView g, v;
+  unsigned groups;
+  unsigned long long *partials;
+};
+struct GroupSumFinishArgs {
+  const unsigned long long *partials;
+  unsigned G, groups, lds;
+  unsigned long long *out;
+};
+struct FillArgs {
+  unsigned *p32;               // one of p32, p64
+  unsigned long long *p64;
+  unsigned long long n, v;
+};
+// Kernels with a batched variant.
+enum BatchKind : unsigned {
+  BK_PRED0, BK_PRED1, BK_PRED2, BK_EMIT, BK_EMIT_FIX, BK_FINISH, BK_SUM, BK_SUM_FINISH, BK_GROUP_SUM,
+  BK_GROUP_SUM_FINISH, BK_FILL, BK_COUNT
+};
+// Launch of kind's batched kernel over tasks (device array of that kind's argument struct).
+hipError_t launch_batch(unsigned kind, const void *tasks, const BatchQueue &q, unsigned grid, size_t shm, void *s);
+hipError_t launch_pred_batch(unsigned mode, const PredArgs *tasks, const BatchQueue &q, unsigned grid, size_t shm,
+                             void *s);
+
 hipError_t init_err_word();  // once, at library initialisation (the current device)
 unsigned read_and_clear_err(void *stream);
 void prof_enable(bool on);

@@ -27,7 +27,7 @@ namespace ms {
 // ---------------------------------------------------------------------------------------------
 // Finish: one workgroup after a column-producing kernel.  Reduces the per-workgroup
 // {OR of all values, OR of the main part} and writes the header.
-__global__ __launch_bounds__(kWG) void k_finish(FinishArgs a) {
+__device__ __forceinline__ void finish_body(const FinishArgs &a) {
   __shared__ unsigned red[kWaves];
   __shared__ unsigned long long s_n;
   unsigned ao = 0, mo = 0;
@@ -61,6 +61,11 @@ __global__ __launch_bounds__(kWG) void k_finish(FinishArgs a) {
     if (a.out.kind != RLE) a.out.hdr->runs = 0;
     a.out.hdr->sorted = a.sorted;
   }
+}
+
+__global__ __launch_bounds__(kWG) void k_finish(FinishArgs a) { finish_body(a); }
+__global__ __launch_bounds__(kWG) void k_finish_batch(const FinishArgs *tasks, BatchQueue q) {
+  batch_run(tasks, q, [](const FinishArgs &a, unsigned, unsigned) { finish_body(a); });
 }
 
 // Narrowing of an auto-width static BP column whose main part needs fewer bits than
@@ -382,14 +387,14 @@ __device__ __forceinline__ void owned_blocks(unsigned long long Ow, unsigned lon
 // inside the loop.
 constexpr unsigned kEmitRing = 2 * kBlk;
 
-__global__ __launch_bounds__(kWG) void k_emit(EmitArgs a) {
+__device__ __forceinline__ void emit_body(const EmitArgs &a, const unsigned seg, const unsigned G) {
   __shared__ __attribute__((aligned(16))) unsigned ring_all[kWaves * kEmitRing];
   __shared__ __attribute__((aligned(16))) unsigned lds_all[kWaves * kBlk];
   __shared__ unsigned s_wcnt[kWaves];
   __shared__ unsigned long long red[kWaves];
   __shared__ unsigned redo[kWaves];
   const InCol in = load_in(a.in);
-  const unsigned lane = lane_id(), w = wave_id(), G = gridDim.x, seg = blockIdx.x;
+  const unsigned lane = lane_id(), w = wave_id();
   const unsigned long long C = (in.n + kBlk - 1) / kBlk;
   unsigned long long cb, ce;
   segment(C, seg, G, cb, ce);
@@ -608,11 +613,16 @@ __global__ __launch_bounds__(kWG) void k_emit(EmitArgs a) {
   }
 }
 
+__global__ __launch_bounds__(kWG) void k_emit(EmitArgs a) { emit_body(a, blockIdx.x, gridDim.x); }
+__global__ __launch_bounds__(kWG) void k_emit_batch(const EmitArgs *tasks, BatchQueue q) {
+  batch_run(tasks, q, [](const EmitArgs &a, unsigned seg, unsigned G) { emit_body(a, seg, G); });
+}
+
 // Compaction phase 3 (block formats): a block that started before a wave's output range
 // is packed from the global stage by the wave whose range holds its last element.
-__global__ __launch_bounds__(kWG) void k_emit_fix(EmitArgs a) {
+__device__ __forceinline__ void emit_fix_body(const EmitArgs &a, const unsigned seg) {
   __shared__ __attribute__((aligned(16))) unsigned lds_all[kWaves * kBlk];
-  const unsigned lane = lane_id(), w = wave_id(), seg = blockIdx.x;
+  const unsigned lane = lane_id(), w = wave_id();
   // the emit phase recorded the output count and width in the header, and each wave's range
   const unsigned long long N = a.out.hdr->n;
   const unsigned Wp = (a.out.kind == STATIC_BP) ? a.out.hdr->sbp_width : a.out.width;
@@ -638,18 +648,24 @@ __global__ __launch_bounds__(kWG) void k_emit_fix(EmitArgs a) {
   encode_out_block(o, k, x, lane, lds_all + w * kBlk, om);
 }
 
+__global__ __launch_bounds__(kWG) void k_emit_fix(EmitArgs a) { emit_fix_body(a, blockIdx.x); }
+__global__ __launch_bounds__(kWG) void k_emit_fix_batch(const EmitArgs *tasks, BatchQueue q) {
+  batch_run(tasks, q, [](const EmitArgs &a, unsigned seg, unsigned) { emit_fix_body(a, seg); });
+}
+
 // ---------------------------------------------------------------------------------------------
 // Sum and group-sum.
-__global__ __launch_bounds__(kWG) void k_sum(ColView inv, unsigned long long *partials) {
+__device__ __forceinline__ void sum_body(const ColView &inv, unsigned long long *partials, const unsigned seg,
+                                         const unsigned G) {
   extern __shared__ __attribute__((aligned(16))) unsigned ring[];  // ring_shm() bytes
   __shared__ unsigned long long red[kWaves];
   const InCol in = load_in(inv);
-  const unsigned lane = lane_id(), w = wave_id(), G = gridDim.x;
+  const unsigned lane = lane_id(), w = wave_id();
   unsigned long long s = 0;
   if (in.kind == RLE) {
     // sum over runs: value * run length (section 2.2)
     unsigned long long rb, re;
-    segment(in.runs, blockIdx.x, G, rb, re);
+    segment(in.runs, seg, G, rb, re);
     // eight runs per thread per round, all loads issued before the products
     constexpr unsigned kU = 8;
     for (unsigned long long r = rb + threadIdx.x; r < re; r += kU * kWG) {
@@ -670,7 +686,7 @@ __global__ __launch_bounds__(kWG) void k_sum(ColView inv, unsigned long long *pa
   } else {
     const unsigned long long C = (in.n + kBlk - 1) / kBlk;
     unsigned long long cb, ce;
-    segment(C, blockIdx.x, G, cb, ce);
+    segment(C, seg, G, cb, ce);
     stream_chunks(in, cb, ce, w, lane, ring + w * kRing * kBlk, inv.hdr, [&](unsigned long long c, const unsigned (&v)[8]) {
       const unsigned valid = chunk_valid(c, lane, in.n);
       unsigned long long t = 0;
@@ -680,11 +696,18 @@ __global__ __launch_bounds__(kWG) void k_sum(ColView inv, unsigned long long *pa
     });
   }
   s = wg_add64(s, red);
-  if (threadIdx.x == 0) partials[blockIdx.x] = s;
+  if (threadIdx.x == 0) partials[seg] = s;
 }
 
-__global__ __launch_bounds__(kWG) void k_sum_finish(const unsigned long long *partials, unsigned G,
-                                                    unsigned long long *result) {
+__global__ __launch_bounds__(kWG) void k_sum(ColView inv, unsigned long long *partials) {
+  sum_body(inv, partials, blockIdx.x, gridDim.x);
+}
+__global__ __launch_bounds__(kWG) void k_sum_batch(const SumArgs *tasks, BatchQueue q) {
+  batch_run(tasks, q, [](const SumArgs &a, unsigned seg, unsigned G) { sum_body(a.in, a.partials, seg, G); });
+}
+
+__device__ __forceinline__ void sum_finish_body(const unsigned long long *partials, unsigned G,
+                                                unsigned long long *result) {
   __shared__ unsigned long long red[kWaves];
   unsigned long long t = 0;
   for (unsigned i = threadIdx.x; i < G; i += kWG) t += partials[i];
@@ -692,23 +715,31 @@ __global__ __launch_bounds__(kWG) void k_sum_finish(const unsigned long long *pa
   if (threadIdx.x == 0) *result = t;
 }
 
+__global__ __launch_bounds__(kWG) void k_sum_finish(const unsigned long long *partials, unsigned G,
+                                                    unsigned long long *result) {
+  sum_finish_body(partials, G, result);
+}
+__global__ __launch_bounds__(kWG) void k_sum_finish_batch(const SumFinishArgs *tasks, BatchQueue q) {
+  batch_run(tasks, q, [](const SumFinishArgs &a, unsigned, unsigned) { sum_finish_body(a.partials, a.G, a.result); });
+}
+
 constexpr unsigned kMaxLdsGroups = 4096;
 
-__global__ __launch_bounds__(kWG) void k_group_sum(ColView gv, ColView vv, unsigned G_groups,
-                                                   unsigned long long *partials) {
+__device__ __forceinline__ void group_sum_body(const ColView &gv, const ColView &vv, unsigned G_groups,
+                                               unsigned long long *partials, const unsigned seg, const unsigned G) {
   __shared__ unsigned long long hist[kMaxLdsGroups];
   __shared__ __attribute__((aligned(16))) unsigned lds_all[2 * kWaves * kBlk];
   const InCol ig = load_in(gv);
   const InCol iv = load_in(vv);
-  const unsigned lane = lane_id(), w = wave_id(), G = gridDim.x;
-  if (ig.n != iv.n && blockIdx.x == 0 && threadIdx.x == 0) raise_err(E_LENGTH);
+  const unsigned lane = lane_id(), w = wave_id();
+  if (ig.n != iv.n && seg == 0 && threadIdx.x == 0) raise_err(E_LENGTH);
   const unsigned long long n = min(ig.n, iv.n);
   const bool use_lds = G_groups <= kMaxLdsGroups;
   for (unsigned i = threadIdx.x; i < kMaxLdsGroups; i += kWG) hist[i] = 0;
   __syncthreads();
   const unsigned long long C = (n + kBlk - 1) / kBlk;
   unsigned long long cb, ce;
-  segment(C, blockIdx.x, G, cb, ce);
+  segment(C, seg, G, cb, ce);
   unsigned *ldg = lds_all + w * kBlk, *ldv = lds_all + (kWaves + w) * kBlk;
   bool bad = false;
   unsigned long long c = cb + w;
@@ -747,18 +778,29 @@ __global__ __launch_bounds__(kWG) void k_group_sum(ColView gv, ColView vv, unsig
   __syncthreads();
   if (use_lds) {
     for (unsigned q = threadIdx.x; q < G_groups; q += kWG)
-      partials[(unsigned long long)blockIdx.x * G_groups + q] = hist[q];
+      partials[(unsigned long long)seg * G_groups + q] = hist[q];
   }
+}
+
+__global__ __launch_bounds__(kWG) void k_group_sum(ColView gv, ColView vv, unsigned G_groups,
+                                                   unsigned long long *partials) {
+  group_sum_body(gv, vv, G_groups, partials, blockIdx.x, gridDim.x);
+}
+__global__ __launch_bounds__(kWG) void k_group_sum_batch(const GroupSumArgs *tasks, BatchQueue q) {
+  batch_run(tasks, q, [](const GroupSumArgs &a, unsigned seg, unsigned G) {
+    group_sum_body(a.g, a.v, a.groups, a.partials, seg, G);
+  });
 }
 
 // One workgroup per group: the sum of that group's per-workgroup partials (LDS
 // histograms), else a copy of the global sums.
-__global__ __launch_bounds__(kWG) void k_group_sum_finish(const unsigned long long *partials, unsigned G,
-                                                          unsigned G_groups, unsigned lds, unsigned long long *out) {
+__device__ __forceinline__ void group_sum_finish_body(const unsigned long long *partials, unsigned G,
+                                                      unsigned G_groups, unsigned lds, unsigned long long *out,
+                                                      const unsigned seg) {
   __shared__ unsigned long long red[kWaves];
-  const unsigned q = blockIdx.x;
+  const unsigned q = seg;
   if (!lds) {  // the partials are the sums themselves: one group per thread
-    const unsigned long long i = (unsigned long long)blockIdx.x * kWG + threadIdx.x;
+    const unsigned long long i = (unsigned long long)seg * kWG + threadIdx.x;
     if (i < G_groups) out[i] = partials[i];
     return;
   }
@@ -766,6 +808,16 @@ __global__ __launch_bounds__(kWG) void k_group_sum_finish(const unsigned long lo
   for (unsigned b = threadIdx.x; b < G; b += kWG) t += partials[(unsigned long long)b * G_groups + q];
   t = wg_add64(t, red);
   if (threadIdx.x == 0) out[q] = t;
+}
+
+__global__ __launch_bounds__(kWG) void k_group_sum_finish(const unsigned long long *partials, unsigned G,
+                                                          unsigned G_groups, unsigned lds, unsigned long long *out) {
+  group_sum_finish_body(partials, G, G_groups, lds, out, blockIdx.x);
+}
+__global__ __launch_bounds__(kWG) void k_group_sum_finish_batch(const GroupSumFinishArgs *tasks, BatchQueue q) {
+  batch_run(tasks, q, [](const GroupSumFinishArgs &a, unsigned seg, unsigned) {
+    group_sum_finish_body(a.partials, a.G, a.groups, a.lds, a.out, seg);
+  });
 }
 
 __global__ void k_set_hdr(ColHdr *h, unsigned long long n, unsigned long long runs, unsigned width,
@@ -790,6 +842,16 @@ __global__ void k_fill_u64(unsigned long long *p, unsigned long long n, unsigned
   for (unsigned long long i = (unsigned long long)blockIdx.x * blockDim.x + threadIdx.x; i < n;
        i += (unsigned long long)gridDim.x * blockDim.x)
     p[i] = v;
+}
+
+// Fills of a batch: segment seg of G covers words seg, seg + G*256, ... of its array.
+__global__ __launch_bounds__(kWG) void k_fill_batch(const FillArgs *tasks, BatchQueue q) {
+  batch_run(tasks, q, [](const FillArgs &a, unsigned seg, unsigned G) {
+    for (unsigned long long i = (unsigned long long)seg * kWG + threadIdx.x; i < a.n; i += (unsigned long long)G * kWG) {
+      if (a.p32) a.p32[i] = (unsigned)a.v;
+      else a.p64[i] = a.v;
+    }
+  });
 }
 
 // Bitmap from positions: bit p of the (zeroed) bitmap for every position p.  With
@@ -1020,6 +1082,7 @@ hipError_t launch_set_hdr(ColHdr *h, unsigned long long n, unsigned long long ru
   return hipGetLastError();
 }
 hipError_t launch_finish(const FinishArgs &a, void *s) {
+  if (batch::recording()) return batch::record_task(BK_FINISH, &a, sizeof(a), 1, 0);
   MS_LAUNCH(k_finish, 1, kWG, s, a);
   return hipGetLastError();
 }
@@ -1085,36 +1148,86 @@ hipError_t launch_project(const ColView &pos, const ColView &data, const ColView
 #undef MS_L
 }
 hipError_t launch_emit(const EmitArgs &a, unsigned G, void *s) {
-  MS_LAUNCH(k_emit, G, kWG, s, a);
   const unsigned k = a.out.kind;
-  if (k == STATIC_BP || k == DYN_BP || k == DELTA_DYN_BP || k == FOR_DYN_BP) MS_LAUNCH(k_emit_fix, G, kWG, s, a);
+  const bool fix = k == STATIC_BP || k == DYN_BP || k == DELTA_DYN_BP || k == FOR_DYN_BP;
+  if (batch::recording()) {
+    hipError_t e = batch::record_task(BK_EMIT, &a, sizeof(a), G, 0);
+    if (e == hipSuccess && fix) e = batch::record_task(BK_EMIT_FIX, &a, sizeof(a), G, 0);
+    return e;
+  }
+  MS_LAUNCH(k_emit, G, kWG, s, a);
+  if (fix) MS_LAUNCH(k_emit_fix, G, kWG, s, a);
   return hipGetLastError();
 }
 hipError_t launch_sum(const ColView &in, unsigned long long *result, unsigned G, unsigned long long *partials,
                       void *s) {
+  if (batch::recording()) {
+    const SumArgs sa{in, partials};
+    const SumFinishArgs sf{partials, G, result};
+    hipError_t e = batch::record_task(BK_SUM, &sa, sizeof(sa), G, ring_shm(in));
+    return e == hipSuccess ? batch::record_task(BK_SUM_FINISH, &sf, sizeof(sf), 1, 0) : e;
+  }
   MS_LAUNCH_SHM("k_sum", k_sum, G, kWG, ring_shm(in), s, in, partials);
   MS_LAUNCH(k_sum_finish, 1, kWG, s, partials, G, result);
   return hipGetLastError();
 }
 hipError_t launch_group_sum(const ColView &g, const ColView &v, unsigned groups, unsigned long long *out, unsigned G,
                             unsigned long long *partials, void *s) {
-  MS_LAUNCH(k_group_sum, G, kWG, s, g, v, groups, partials);
   const unsigned lds = groups <= kMaxLdsGroups ? 1u : 0u;
+  if (batch::recording()) {
+    const GroupSumArgs ga{g, v, groups, partials};
+    const GroupSumFinishArgs gf{partials, G, groups, lds, out};
+    hipError_t e = batch::record_task(BK_GROUP_SUM, &ga, sizeof(ga), G, 0);
+    if (e == hipSuccess && groups > 0)
+      e = batch::record_task(BK_GROUP_SUM_FINISH, &gf, sizeof(gf), lds ? groups : (groups + kWG - 1) / kWG, 0);
+    return e;
+  }
+  MS_LAUNCH(k_group_sum, G, kWG, s, g, v, groups, partials);
   if (groups > 0) MS_LAUNCH(k_group_sum_finish, lds ? groups : (groups + kWG - 1) / kWG, kWG, s, partials, G, groups, lds, out);
   return hipGetLastError();
 }
 hipError_t launch_fill_u32(unsigned *p, unsigned long long n, unsigned v, void *s) {
   if (n == 0) return hipSuccess;
   const unsigned blocks = (unsigned)std::min<unsigned long long>((n + 255) / 256, 2048ull);
+  if (batch::recording()) {
+    const FillArgs f{p, nullptr, n, v};
+    return batch::record_task(BK_FILL, &f, sizeof(f), blocks, 0);
+  }
   MS_LAUNCH(k_fill_u32, blocks, 256, s, p, n, v);
   return hipGetLastError();
 }
 hipError_t launch_fill_u64(unsigned long long *p, unsigned long long n, unsigned long long v, void *s) {
   if (n == 0) return hipSuccess;
   const unsigned blocks = (unsigned)std::min<unsigned long long>((n + 255) / 256, 2048ull);
+  if (batch::recording()) {
+    const FillArgs f{nullptr, p, n, v};
+    return batch::record_task(BK_FILL, &f, sizeof(f), blocks, 0);
+  }
   MS_LAUNCH(k_fill_u64, blocks, 256, s, p, n, v);
   return hipGetLastError();
 }
+hipError_t launch_batch(unsigned kind, const void *tasks, const BatchQueue &q, unsigned grid, size_t shm, void *s) {
+  switch (kind) {
+    case BK_PRED0:
+    case BK_PRED1:
+    case BK_PRED2: return launch_pred_batch(kind - BK_PRED0, static_cast<const PredArgs *>(tasks), q, grid, shm, s);
+    case BK_EMIT: MS_LAUNCH(k_emit_batch, grid, kWG, s, static_cast<const EmitArgs *>(tasks), q); break;
+    case BK_EMIT_FIX: MS_LAUNCH(k_emit_fix_batch, grid, kWG, s, static_cast<const EmitArgs *>(tasks), q); break;
+    case BK_FINISH: MS_LAUNCH(k_finish_batch, grid, kWG, s, static_cast<const FinishArgs *>(tasks), q); break;
+    case BK_SUM:
+      MS_LAUNCH_SHM("k_sum_batch", k_sum_batch, grid, kWG, shm, s, static_cast<const SumArgs *>(tasks), q);
+      break;
+    case BK_SUM_FINISH: MS_LAUNCH(k_sum_finish_batch, grid, kWG, s, static_cast<const SumFinishArgs *>(tasks), q); break;
+    case BK_GROUP_SUM: MS_LAUNCH(k_group_sum_batch, grid, kWG, s, static_cast<const GroupSumArgs *>(tasks), q); break;
+    case BK_GROUP_SUM_FINISH:
+      MS_LAUNCH(k_group_sum_finish_batch, grid, kWG, s, static_cast<const GroupSumFinishArgs *>(tasks), q);
+      break;
+    case BK_FILL: MS_LAUNCH(k_fill_batch, grid, kWG, s, static_cast<const FillArgs *>(tasks), q); break;
+    default: return hipErrorInvalidValue;
+  }
+  return hipGetLastError();
+}
+
 hipError_t launch_bitmap(const ColView &pos, unsigned long long domain, unsigned *bitmap, unsigned *ends,
                          unsigned *first, unsigned *last, unsigned G, void *s) {
   MS_LAUNCH(k_bitmap, G, kWG, s, pos, domain, bitmap, first, last, ends);

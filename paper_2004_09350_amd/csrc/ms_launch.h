@@ -5,6 +5,7 @@
 #pragma once
 #include <hip/hip_runtime.h>
 
+#include "ms_batch.h"
 #include "ms_device.h"
 #include "ms_kernels.h"
 
@@ -30,18 +31,24 @@ constexpr size_t kRingBytes = sizeof(unsigned) * kWaves * kRing * kBlk;
 constexpr unsigned long long kLdsBitmapBits = 32ull * kWaves * kRing * kBlk;
 inline size_t ring_shm(const ColView &c) { return c.kind == RLE ? kRingBytes : 0; }
 
-#define MS_LAUNCH_NAMED(name, kern, grid, block, stream, ...)                     \
-  do {                                                                            \
-    ProfScope ps_(name, stream);                                                  \
-    hipLaunchKernelGGL(kern, dim3(grid), dim3(block), 0, S(stream), __VA_ARGS__); \
+// While the thread records a batch (ms_batch.h) the launch is held back as a closure over
+// copies of its arguments and issued by the flush.
+#define MS_LAUNCH_SHM(name, kern, grid, block, shm, stream, ...)                          \
+  do {                                                                                    \
+    if (::ms::batch::recording()) {                                                       \
+      ::ms::batch::record_launch([=]() {                                                  \
+        ProfScope ps_(name, stream);                                                      \
+        hipLaunchKernelGGL(kern, dim3(grid), dim3(block), shm, S(stream), __VA_ARGS__);   \
+        return hipGetLastError();                                                         \
+      });                                                                                 \
+    } else {                                                                              \
+      ProfScope ps_(name, stream);                                                        \
+      hipLaunchKernelGGL(kern, dim3(grid), dim3(block), shm, S(stream), __VA_ARGS__);     \
+    }                                                                                     \
   } while (0)
+#define MS_LAUNCH_NAMED(name, kern, grid, block, stream, ...) \
+  MS_LAUNCH_SHM(name, kern, grid, block, 0, stream, __VA_ARGS__)
 #define MS_LAUNCH(kern, grid, block, stream, ...) MS_LAUNCH_NAMED(#kern, kern, grid, block, stream, __VA_ARGS__)
-// named, with dynamic LDS of shm bytes
-#define MS_LAUNCH_SHM(name, kern, grid, block, shm, stream, ...)                    \
-  do {                                                                              \
-    ProfScope ps_(name, stream);                                                    \
-    hipLaunchKernelGGL(kern, dim3(grid), dim3(block), shm, S(stream), __VA_ARGS__); \
-  } while (0)
 
 // The device error word: init_err_word allocates it and points every unit's copy of
 // g_err_word at it (each unit registers its setter from a static initialiser).

@@ -12,6 +12,7 @@
 #include <vector>
 
 #include "../../include/morphgpu.h"
+#include "ms_batch.h"
 #include "ms_kernels.h"
 #include "ms_runtime.h"
 
@@ -98,7 +99,7 @@ struct EventSet {
 struct ms_plan {
   std::vector<ms_step> steps;
   std::vector<const ms_column *> inputs;
-  ms_tune tune{1, 0, 0};
+  ms_tune tune{1, 0, 0, 0};
   std::vector<int> branch_of;
   std::vector<Result> eager, graph_res;
   bool last_graph = false;
@@ -111,6 +112,7 @@ struct ms_plan {
   std::vector<hipStream_t> br;            // branch streams
   EventSet eager_ev;                      // events of eager runs
   EventSet graph_ev;                      // events recorded in the captured graph
+  std::vector<batch::Upload> uploads;     // batched task tables: kept until a sync (eager) or copied after a capture
 };
 
 namespace {
@@ -212,6 +214,34 @@ ms_status exec_step(ms_plan *p, size_t i, void *s, std::vector<Result> &r) {
   }
 }
 
+// Batched: level by level on `origin`; the operators of a level (steps whose operands all
+// come from earlier levels) are recorded and issued as batched launches.
+ms_status run_levels(ms_plan *p, hipStream_t origin, std::vector<Result> &r) {
+  const size_t n = p->steps.size();
+  std::vector<uint32_t> level(n, 0);
+  uint32_t levels = 0;
+  for (size_t i = 0; i < n; i++) {
+    const ms_step &s = p->steps[i];
+    const char *ok = operand_kinds(s.op);
+    const int32_t refs[2] = {ok[0] != '-' ? s.a : -1, ok[1] != '-' ? s.b : -1};
+    for (int32_t ref : refs)
+      if (ref >= 0) level[i] = std::max(level[i], level[ref] + 1);
+    levels = std::max(levels, level[i] + 1);
+  }
+  ms_status st = MS_OK;
+  for (uint32_t l = 0; l < levels && st == MS_OK; l++) {
+    batch::begin();
+    for (size_t i = 0; i < n && st == MS_OK; i++) {
+      if (level[i] != l) continue;
+      batch::next_op();
+      st = exec_step(p, i, origin, r);
+    }
+    const hipError_t e = batch::flush(origin, p->uploads);  // also after an error: frees run, recording stops
+    if (st == MS_OK && e != hipSuccess) st = hip_fail(e, "batched launch");
+  }
+  return st;
+}
+
 // All steps, forked from and joined back into `origin`, ordered across branches by `ev`.
 ms_status run_steps(ms_plan *p, hipStream_t origin, std::vector<Result> &r, EventSet &ev) {
   r.assign(p->steps.size(), Result());
@@ -220,7 +250,9 @@ ms_status run_steps(ms_plan *p, hipStream_t origin, std::vector<Result> &r, Even
   rt::set_thread_chunks_per_wg(p->tune.chunks_per_wg);
   ms_status st = MS_OK;
   hipError_t e = hipSuccess;
-  if (B == 1) {
+  if (p->tune.batch) {
+    st = run_levels(p, origin, r);
+  } else if (B == 1) {
     for (size_t i = 0; i < p->steps.size() && st == MS_OK; i++) st = exec_step(p, i, origin, r);
   } else {
     e = hipEventRecord(ev.fork, origin);
@@ -253,6 +285,7 @@ void drop_graph(ms_plan *p) {
   // Replays may still be queued on any stream the caller launched them on: wait for the
   // device before the executable graph, its kernel arguments and the arena go away.
   if (p->exec || p->graph || p->arena || !p->graph_res.empty()) (void)hipDeviceSynchronize();
+  p->uploads.clear();
   if (p->exec) (void)hipGraphExecDestroy(p->exec);
   if (p->graph) (void)hipGraphDestroy(p->graph);
   p->exec = nullptr;
@@ -379,8 +412,10 @@ ms_status ms_plan_set_tune(ms_plan *p, const ms_tune *t) {
   if (t->branches < 1 || t->branches > kMaxBranches) return fail(MS_ERR_INVALID_ARG, "branches must be 1..16");
   if (t->wg_per_cu > kMaxWgPerCu) return fail(MS_ERR_INVALID_ARG, "wg_per_cu must be 0..32");
   if (t->chunks_per_wg > kMaxChunksPerWg) return fail(MS_ERR_INVALID_ARG, "chunks_per_wg must be 0..64");
+  if (t->batch > 1) return fail(MS_ERR_INVALID_ARG, "batch must be 0 or 1");
+  if (t->batch && t->branches != 1) return fail(MS_ERR_INVALID_ARG, "batched launches run on one branch");
   if (t->branches != p->tune.branches || t->wg_per_cu != p->tune.wg_per_cu ||
-      t->chunks_per_wg != p->tune.chunks_per_wg) {
+      t->chunks_per_wg != p->tune.chunks_per_wg || t->batch != p->tune.batch) {
     drop_graph(p);
     p->tune = *t;
     assign_branches(p);
@@ -399,10 +434,11 @@ ms_status ms_plan_run(ms_plan *p, void *stream) {
   ms_status st = ensure_streams(p);
   if (st != MS_OK) return st;
   hipStream_t s = reinterpret_cast<hipStream_t>(stream);
-  if (!p->eager.empty()) {
+  if (!p->eager.empty() || !p->uploads.empty()) {
     (void)hipStreamSynchronize(s);
     for (auto b : p->br) (void)hipStreamSynchronize(b);
     free_results(p->eager);
+    p->uploads.clear();
   }
   st = run_steps(p, s, p->eager, p->eager_ev);
   p->last_graph = false;
@@ -411,6 +447,7 @@ ms_status ms_plan_run(ms_plan *p, void *stream) {
     for (auto b : p->br) (void)hipStreamSynchronize(b);
     free_results(p->eager);
     p->eager.clear();
+    p->uploads.clear();
   }
   return st;
 }
@@ -425,6 +462,7 @@ ms_status ms_plan_launch(ms_plan *p, void *stream) {
     // a capture starts
     hipError_t se = hipDeviceSynchronize();
     if (se != hipSuccess) return hip_fail(se, "device sync");
+    p->uploads.clear();
     // 1) size the arena with a capture that is never instantiated (its own events)
     rt::Arena m;
     m.measure = true;
@@ -452,6 +490,15 @@ ms_status ms_plan_launch(ms_plan *p, void *stream) {
       drop_graph(p);
       return st;
     }
+    // task tables of batched launches: into the arena once the capture has ended
+    for (const batch::Upload &u : p->uploads) {
+      e = hipMemcpy(u.dev, u.host.data(), u.host.size(), hipMemcpyHostToDevice);
+      if (e != hipSuccess) {
+        drop_graph(p);
+        return hip_fail(e, "batch table copy");
+      }
+    }
+    p->uploads.clear();
     e = hipGraphInstantiate(&p->exec, p->graph, nullptr, nullptr, 0);
     if (e != hipSuccess) {
       drop_graph(p);
@@ -512,14 +559,14 @@ ms_status ms_plan_autotune(ms_plan *p, void *stream, uint32_t reps, const char *
   if (cache_path) {
     if (FILE *f = std::fopen(cache_path, "r")) {
       char line[256];
-      ms_tune found{0, 0, 0};
+      ms_tune found{0, 0, 0, 0};
       float fms = 0.f;
       while (std::fgets(line, sizeof(line), f)) {
         char k[64];
-        unsigned b = 0, w = 0, c = 0;
+        unsigned b = 0, w = 0, c = 0, bat = 0;
         float t = 0.f;
-        if (std::sscanf(line, "%63s %u %u %u %f", k, &b, &w, &c, &t) == 5 && std::strcmp(k, sig) == 0) {
-          found = ms_tune{b, w, c};
+        if (std::sscanf(line, "%63s %u %u %u %u %f", k, &b, &w, &c, &bat, &t) == 6 && std::strcmp(k, sig) == 0) {
+          found = ms_tune{b, w, c, bat};
           fms = t;
         }
       }
@@ -533,14 +580,15 @@ ms_status ms_plan_autotune(ms_plan *p, void *stream, uint32_t reps, const char *
       }
     }
   }
-  // branches x workgroups per CU, then chunks per workgroup at the best of those
+  // branches x workgroups per CU, then chunks per workgroup at the best of those, then the
+  // batched level-by-level launches at that grid
   static const uint32_t kBranches[] = {1, 2, 4, 8};
   static const uint32_t kWg[] = {0, 2, 4, 8, 16};  // 0: each operator's default
   static const uint32_t kChunks[] = {1, 2, 8, 16};  // besides the default of four
   hipEvent_t e0, e1;
   if (hipEventCreate(&e0) != hipSuccess || hipEventCreate(&e1) != hipSuccess)
     return fail(MS_ERR_HIP, "event create failed");
-  ms_tune bt{1, 0, 0};
+  ms_tune bt{1, 0, 0, 0};
   float bms = 1e30f;
   ms_status st = MS_OK;
   auto trial = [&](const ms_tune &t) {
@@ -554,10 +602,11 @@ ms_status ms_plan_autotune(ms_plan *p, void *stream, uint32_t reps, const char *
   };
   for (uint32_t b : kBranches)
     for (uint32_t w : kWg)
-      if (st == MS_OK) trial(ms_tune{b, w, 0});
+      if (st == MS_OK) trial(ms_tune{b, w, 0, 0});
   const ms_tune base = bt;
   for (uint32_t c : kChunks)
-    if (st == MS_OK) trial(ms_tune{base.branches, base.wg_per_cu, c});
+    if (st == MS_OK) trial(ms_tune{base.branches, base.wg_per_cu, c, 0});
+  if (st == MS_OK) trial(ms_tune{1, bt.wg_per_cu, bt.chunks_per_wg, 1});
   (void)hipEventDestroy(e0);
   (void)hipEventDestroy(e1);
   if (st != MS_OK) return st;
@@ -565,7 +614,7 @@ ms_status ms_plan_autotune(ms_plan *p, void *stream, uint32_t reps, const char *
   if (st != MS_OK) return st;
   if (cache_path) {
     if (FILE *f = std::fopen(cache_path, "a")) {
-      std::fprintf(f, "%s %u %u %u %.4f\n", sig, bt.branches, bt.wg_per_cu, bt.chunks_per_wg, bms);
+      std::fprintf(f, "%s %u %u %u %u %.4f\n", sig, bt.branches, bt.wg_per_cu, bt.chunks_per_wg, bt.batch, bms);
       std::fclose(f);
     }
   }

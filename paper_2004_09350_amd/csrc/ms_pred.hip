@@ -262,15 +262,15 @@ __device__ __forceinline__ bool rle_long_runs(const InCol &in, unsigned long lon
 // mode 1: bitmap predicate v < domain && bit(v), emits positions (semi-join)
 // mode 2: bitmap predicate on values, emits values, checks strict increase (intersect)
 template <unsigned MODE>
-__global__ __launch_bounds__(kWG) void k_pred(PredArgs a) {
+__device__ __forceinline__ void pred_body(const PredArgs &a, const unsigned seg, const unsigned G) {
   extern __shared__ __attribute__((aligned(16))) unsigned ring[];  // ring_shm() bytes
   __shared__ unsigned long long red[kWaves];
   __shared__ unsigned redo[kWaves];
   const InCol in = load_in(a.in);
-  const unsigned lane = lane_id(), w = wave_id(), G = gridDim.x;
+  const unsigned lane = lane_id(), w = wave_id();
   const unsigned long long C = (in.n + kBlk - 1) / kBlk;
   unsigned long long cb, ce;
-  segment(C, blockIdx.x, G, cb, ce);
+  segment(C, seg, G, cb, ce);
   unsigned cnt = 0, orv = 0;
   bool unsorted = false;
   constexpr unsigned mode = MODE;
@@ -365,9 +365,20 @@ __global__ __launch_bounds__(kWG) void k_pred(PredArgs a) {
   const unsigned long long t = wg_add64(cnt, red);
   orv = wg_or(orv, redo);
   if (threadIdx.x == 0) {
-    a.seg_count[blockIdx.x] = (unsigned)t;
-    a.seg_or[blockIdx.x] = orv;
+    a.seg_count[seg] = (unsigned)t;
+    a.seg_or[seg] = orv;
   }
+}
+
+template <unsigned MODE>
+__global__ __launch_bounds__(kWG) void k_pred(PredArgs a) {
+  pred_body<MODE>(a, blockIdx.x, gridDim.x);
+}
+
+// The same for a batch of operators (one plan level): workgroups take (task, segment) tickets.
+template <unsigned MODE>
+__global__ __launch_bounds__(kWG) void k_pred_batch(const PredArgs *tasks, BatchQueue q) {
+  batch_run(tasks, q, [](const PredArgs &a, unsigned seg, unsigned G) { pred_body<MODE>(a, seg, G); });
 }
 
 
@@ -430,6 +441,8 @@ __global__ __launch_bounds__(kWideWG) void k_semijoin_wide(PredArgs a, unsigned 
 hipError_t launch_pred(const PredArgs &a, unsigned G, void *s) {
   // the semi-join probes (the first kLdsBitmapBits bits of) its bitmap in LDS
   const size_t shm = a.mode == 1 ? kRingBytes : ring_shm(a.in);
+  const bool wide = a.mode == 1 && a.in.kind != RLE && a.domain > kLdsBitmapBits;
+  if (!wide && batch::recording()) return batch::record_task(BK_PRED0 + a.mode, &a, sizeof(a), G, shm);
   if (a.mode == 0)
     MS_LAUNCH_SHM("k_pred<0>", k_pred<0>, G, kWG, shm, s, a);
   else if (a.mode == 1 && a.in.kind != RLE && a.domain > kLdsBitmapBits)
@@ -438,6 +451,17 @@ hipError_t launch_pred(const PredArgs &a, unsigned G, void *s) {
     MS_LAUNCH_SHM("k_pred<1>", k_pred<1>, G, kWG, shm, s, a);
   else
     MS_LAUNCH_SHM("k_pred<2>", k_pred<2>, G, kWG, shm, s, a);
+  return hipGetLastError();
+}
+
+hipError_t launch_pred_batch(unsigned mode, const PredArgs *tasks, const BatchQueue &q, unsigned grid, size_t shm,
+                             void *s) {
+  if (mode == 0)
+    MS_LAUNCH_SHM("k_pred_batch<0>", k_pred_batch<0>, grid, kWG, shm, s, tasks, q);
+  else if (mode == 1)
+    MS_LAUNCH_SHM("k_pred_batch<1>", k_pred_batch<1>, grid, kWG, shm, s, tasks, q);
+  else
+    MS_LAUNCH_SHM("k_pred_batch<2>", k_pred_batch<2>, grid, kWG, shm, s, tasks, q);
   return hipGetLastError();
 }
 }  // namespace ms

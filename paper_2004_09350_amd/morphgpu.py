@@ -70,7 +70,8 @@ class Step(ctypes.Structure):
 
 
 class Tune(ctypes.Structure):
-    _fields_ = [("branches", ctypes.c_uint32), ("wg_per_cu", ctypes.c_uint32), ("chunks_per_wg", ctypes.c_uint32)]
+    _fields_ = [("branches", ctypes.c_uint32), ("wg_per_cu", ctypes.c_uint32), ("chunks_per_wg", ctypes.c_uint32),
+                ("batch", ctypes.c_uint32)]
 
 
 _sigs = {
@@ -652,15 +653,17 @@ class Plan:
         _check(_lib.ms_plan_set_format(self._h, i, f))
         self.steps[i].out = f
 
-    def set_tune(self, branches: int, wg_per_cu: int, chunks_per_wg: int = 0):
+    def set_tune(self, branches: int, wg_per_cu: int, chunks_per_wg: int = 0, batch: int = 0):
+        """Launch shape (see ms_tune): batch=1 runs the plan level by level with batched
+        persistent launches (branches must be 1)."""
         self._drop_borrowed()
-        t = Tune(branches, wg_per_cu, chunks_per_wg)
+        t = Tune(branches, wg_per_cu, chunks_per_wg, batch)
         _check(_lib.ms_plan_set_tune(self._h, ctypes.byref(t)))
 
     def tune(self) -> tuple:
         t = Tune()
         _check(_lib.ms_plan_get_tune(self._h, ctypes.byref(t)))
-        return t.branches, t.wg_per_cu, t.chunks_per_wg
+        return t.branches, t.wg_per_cu, t.chunks_per_wg, t.batch
 
     def run(self, stream=None):
         self._drop_borrowed()
@@ -680,7 +683,7 @@ class Plan:
         ms = ctypes.c_float(0)
         _check(_lib.ms_plan_autotune(self._h, _stream(stream), reps, cache.encode() if cache else None,
                                      ctypes.byref(t), ctypes.byref(ms)))
-        return (t.branches, t.wg_per_cu, t.chunks_per_wg), ms.value
+        return (t.branches, t.wg_per_cu, t.chunks_per_wg, t.batch), ms.value
 
     def formats(self) -> list:
         """The output format kind of every step as the library holds it."""

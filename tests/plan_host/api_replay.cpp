@@ -5,8 +5,9 @@
 // Sequence, per output-format policy of the star plan: a probe plan with statistics and
 // footprint steps run eagerly and read back; a separate plan run eagerly twice and
 // destroyed; a plan autotuned through the tune cache, launched and replayed, its results
-// inspected, re-tuned to one branch and run eagerly, then destroyed; input columns morphed
-// into every format and plans over them launched and destroyed.
+// inspected, re-tuned to one branch and run eagerly, then destroyed; a plan with batched
+// persistent launches run eagerly twice, captured and replayed; input columns morphed into
+// every format and plans over them launched and destroyed.
 #include <hip/hip_runtime.h>
 
 #include <cstdint>
@@ -165,6 +166,18 @@ void policy(const uint32_t kinds[15], const std::vector<ms_column *> &in, hipStr
   read_results(p, st, s);
   inspect_columns(p, st, s);
   CHECK(ms_plan_destroy(p));
+  // batched persistent launches level by level: eager, then captured and replayed
+  ms_plan *pb = make(st, in);
+  ms_tune bt{1, best.wg_per_cu, best.chunks_per_wg, 1};
+  CHECK(ms_plan_set_tune(pb, &bt));
+  CHECK(ms_plan_run(pb, s));
+  read_results(pb, st, s);
+  CHECK(ms_plan_run(pb, s));
+  CHECK(ms_plan_launch(pb, s));
+  for (int r = 0; r < 2; r++) CHECK(ms_plan_launch(pb, s));
+  read_results(pb, st, s);
+  inspect_columns(pb, st, s);
+  CHECK(ms_plan_destroy(pb));
   // the profiled eager run on one branch
   ms_plan *pr = make(st, in);
   ms_tune one{1, best.wg_per_cu, best.chunks_per_wg};

@@ -10,6 +10,7 @@ enum {
   hipSuccess = 0,
   hipErrorInvalidValue = 1,
   hipErrorInvalidSymbol = 13,
+  hipErrorOutOfMemory = 2,
   hipErrorInvalidResourceHandle = 400,
   hipErrorNotReady = 600,
   hipErrorStreamCaptureUnsupported = 900,

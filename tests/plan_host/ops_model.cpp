@@ -14,6 +14,7 @@
 #include <string>
 
 #include "../../include/morphgpu.h"
+#include "../../paper_2004_09350_amd/csrc/ms_batch.h"
 #include "../../paper_2004_09350_amd/csrc/ms_kernels.h"
 #include "../../paper_2004_09350_amd/csrc/ms_runtime.h"
 #include "model.h"
@@ -149,6 +150,17 @@ uint64_t column_rows_cap(const ms_column *c) { return c->n; }
 }  // namespace rt
 void prof_suspend(bool on) { t_prof_suspended = on; }
 bool prof_suspended() { return t_prof_suspended; }
+}  // namespace ms
+
+// The executor's batched mode: operators here queue their work directly, so nothing is
+// recorded and a flush has nothing to issue.
+namespace ms {
+namespace batch {
+bool recording() { return false; }
+void begin() {}
+void next_op() {}
+hipError_t flush(void *, std::vector<Upload> &) { return hipSuccess; }
+}  // namespace batch
 }  // namespace ms
 
 void model_fail_arena_alloc(int index) {

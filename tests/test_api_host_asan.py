@@ -7,7 +7,9 @@ what each kernel writes over the extents its contract gives.  Allocator callback
 stream order, as a caching allocator does.  The replay encodes the star workload's inputs,
 runs the probe plan with statistics and footprint steps, and for every output-format policy
 runs a plan eagerly, autotunes another through the tune cache, replays and inspects its
-graph, re-tunes a third to one branch; then plans over inputs morphed into every format.
+graph, re-tunes a third to one branch, runs and replays a fourth with batched persistent
+launches (the recorder, task tables, tickets); then plans over inputs morphed into every
+format.
 Any out-of-bounds access, use after free, leak or undefined behaviour fails the test."""
 import os
 import shutil
@@ -28,7 +30,8 @@ def replay(tmp_path_factory):
     exe = str(d / "api_replay")
     cmd = ["g++", "-std=c++17", "-g", "-O1", "-fno-omit-frame-pointer", "-fsanitize=address,undefined",
            "-fno-sanitize-recover=undefined", "-I", os.path.join(HERE, "include"), "-I", HERE,
-           "-x", "c++", os.path.join(CSRC, "ms_api.hip"), os.path.join(CSRC, "ms_plan.hip"), "-x", "none",
+           "-x", "c++", os.path.join(CSRC, "ms_api.hip"), os.path.join(CSRC, "ms_plan.hip"),
+           os.path.join(CSRC, "ms_batch.hip"), "-x", "none",
            os.path.join(HERE, "hip_model.cpp"), os.path.join(HERE, "kernels_model.cpp"),
            os.path.join(HERE, "api_replay.cpp"), "-o", exe]
     subprocess.run(cmd, check=True, capture_output=True, text=True)

@@ -2,7 +2,9 @@
 (select, semi-join, project, intersect, sum, group-sum, morph), every input and output
 format, every value distribution and sizes log-uniform over three decades, run eagerly,
 as a captured graph with the autotuned launch shape (replayed several times with other
-work in between) and with one launch sequence per task on eight branches.  Every column
+work in between), with one launch sequence per task on eight branches, and with batched
+persistent launches (one launch per kernel and phase for each of the plan's levels, eager
+and as a replayed graph).  Every column
 result is compared block by block with the oracle's encoding of the expected values."""
 import math
 
@@ -115,4 +117,16 @@ def test_mixed_batch_eager_graph_and_branches(M, tmp_path):
     plan.run()
     M.sync()
     check(M, plan, expect)
+    # batched persistent launches: the plan's three levels, one launch per kernel and phase
+    for tune in ((1, 0, 0, 1), (1, 2, 8, 1)):
+        plan.set_tune(*tune)
+        plan.run()
+        M.sync()
+        check(M, plan, expect)
+        for rep in range(3):
+            plan.launch()
+            M.sync()
+            check(M, plan, expect)
+            M.morph(other, M.fmt(M.DYN_BP))
+            M.sync()
     plan.close()

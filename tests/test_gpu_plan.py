@@ -138,8 +138,11 @@ def test_q3_greedy_runtime_search(M, Q, star):
     q3.plan.close()
 
 
-@pytest.mark.parametrize("tune", [(1, 0, 0), (2, 4, 1), (4, 8, 16), (8, 2, 2), (2, 0, 64)])
+@pytest.mark.parametrize("tune", [(1, 0, 0, 0), (2, 4, 1, 0), (4, 8, 16, 0), (8, 2, 2, 0), (2, 0, 64, 0), (1, 0, 0, 1),
+                                  (1, 8, 2, 1), (1, 2, 16, 1)])
 def test_q3_branches(M, Q, star, tune):
+    """Every launch shape, the batched level-by-level launches (batch = 1) included: an
+    eager run and graph replays give the oracle's answers and intermediates."""
     cols, thr, want, enc = star
     q3 = Q.Q3(enc, thr, datagen.STAR_DIM_SIZES, N_FACT)
     q3.plan.set_tune(*tune)
@@ -173,14 +176,15 @@ def test_autotune_and_cache(M, Q, tmp_path):
     plan = Q.q1_plan(A, B, 103)
     best, ms = plan.autotune(reps=2, cache=cache)
     assert best[0] in (1, 2, 4, 8) and best[1] in (0, 2, 4, 8, 16) and best[2] in (0, 1, 2, 8, 16) and ms > 0
+    assert best[3] in (0, 1) and (best[3] == 0 or best[0] == 1)
     assert plan.tune() == best
-    lines = open(cache).read().split()  # signature, branches, workgroups per CU, chunks per workgroup, ms
-    assert len(lines) == 5 and (int(lines[1]), int(lines[2]), int(lines[3])) == best
+    lines = open(cache).read().split()  # signature, branches, workgroups per CU, chunks per workgroup, batch, ms
+    assert len(lines) == 6 and tuple(int(x) for x in lines[1:5]) == best
     plan.launch()
     assert int(plan.read(2)[0]) == want["sum"]
     plan2 = Q.q1_plan(A, B, 103)
     best2, ms2 = plan2.autotune(reps=2, cache=cache)  # from the cache, no timing
-    assert best2 == best and abs(ms2 - float(lines[4])) < 1e-3
+    assert best2 == best and abs(ms2 - float(lines[5])) < 1e-3
     plan2.run()
     assert int(plan2.read(2)[0]) == want["sum"]
     plan.close()
@@ -205,6 +209,10 @@ def test_plan_errors(M):
         p.set_tune(0, 8)
     with pytest.raises(M.MorphError):
         p.set_tune(1, 0, 65)
+    with pytest.raises(M.MorphError):  # batched launches run on one branch
+        p.set_tune(2, 0, 0, 1)
+    with pytest.raises(M.MorphError):
+        p.set_tune(1, 0, 0, 2)
     p.run()
     assert int(p.read(0)[0]) == O.sum_(datagen.uniform_bits(1, 1000, 5))
     p.close()

@@ -14,7 +14,7 @@ def test_selector_struct_layout():
 def test_plan_step_layout():
     import ctypes
     from paper_2004_09350_amd import morphgpu as M
-    assert ctypes.sizeof(M.Step) == 40 and ctypes.sizeof(M.Tune) == 12
+    assert ctypes.sizeof(M.Step) == 40 and ctypes.sizeof(M.Tune) == 16
     s = M.step(M.OP_SELECT, a=M.inp(2), cmp=M.LT, c0=103, out=M.fmt(M.DELTA_DYN_BP))
     assert (s.op, s.a, s.cmp, s.c0, s.out.kind) == (M.OP_SELECT, -3, M.LT, 103, M.DELTA_DYN_BP)
 
