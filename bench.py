@@ -830,11 +830,11 @@ def run_batch(args, M, gen, torch, log):
     log(f"autotuned {best} ({best_ms:.2f} ms in tuning), graph {tg * 1e3:.2f} ms")
     # batched persistent launches (one launch per kernel kind and phase of each plan level)
     pb = M.Plan(steps, inputs)
-    pb.set_tune(1, best[1], best[2], 1)
+    pb.set_tune(best[0], best[1], best[2], 1)
     tbe = time_eager(torch, pb, reps)
     pb.close()
     pb = M.Plan(steps, inputs)
-    pb.set_tune(1, best[1], best[2], 1)
+    pb.set_tune(best[0], best[1], best[2], 1)
     tbg = time_graph(torch, pb, reps)
     pb.close()
     log(f"batched persistent launches: eager {tbe * 1e3:.2f} ms, graph {tbg * 1e3:.2f} ms")

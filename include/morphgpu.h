@@ -361,12 +361,12 @@ typedef struct {
  * compute unit (1..32, or 0 for each operator's default: 4, and 3 for project) and the
  * chunks of 512 values per workgroup that size the grid below that cap (1..64, or 0 for
  * the default of 4): grid = min(ceil(chunks / chunks_per_wg), CUs x wg_per_cu).
- * batch = 1 runs the plan level by level on one stream (branches must be 1): the
- * operators of a level (steps whose operands all come from earlier levels) share one
- * persistent launch per kernel and phase for select, semi-join and intersect (predicate,
- * emit, fix-up, finish), sum and group-sum (and the fills they need); a launch's
- * workgroups take (operator, segment) tickets, largest operator first.  Other kernels of
- * the level are issued one by one in the same phase order. */
+ * batch = 1 runs the plan level by level: the operators of a level (steps whose operands
+ * all come from earlier levels) share one persistent launch per kernel and phase for
+ * select, semi-join and intersect (predicate, emit, fix-up, finish), sum and group-sum
+ * (and the fills they need); a launch's workgroups take (operator, segment) tickets,
+ * largest operator first.  The level's other kernels are issued in the same phase order,
+ * spread over the branches. */
 typedef struct {
   uint32_t branches;
   uint32_t wg_per_cu;
@@ -406,8 +406,8 @@ ms_status ms_plan_read_result(const ms_plan *plan, uint32_t step, void *host_dst
 uint64_t ms_plan_arena_bytes(const ms_plan *plan);
 /* Autotuner: times ms_plan_launch for every (branches in {1, 2, 4, 8}, wg_per_cu in {0, 2,
  * 4, 8, 16}) candidate over `reps` replays, then chunks_per_wg in {1, 2, 8, 16} at the best
- * of those, then the batched level-by-level launches (batch = 1, one branch) at the best
- * grid, and keeps the fastest.  With cache_path, a tune recorded there for the same
+ * of those, then the batched level-by-level launches (batch = 1) at the best shape, and
+ * keeps the fastest.  With cache_path, a tune recorded there for the same
  * plan signature (steps and input shapes) is applied without timing, and new results are
  * appended.  best (may be NULL) receives the tune; best_ms (may be NULL) its time. */
 ms_status ms_plan_autotune(ms_plan *plan, void *stream, uint32_t reps, const char *cache_path, ms_tune *best,

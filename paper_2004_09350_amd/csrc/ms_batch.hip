@@ -19,7 +19,7 @@ namespace {
 struct Entry {
   unsigned phase = 0;
   int kind = -1;  // BatchKind, or -1 for a recorded plain launch
-  std::function<hipError_t()> launch;
+  std::function<hipError_t(void *)> launch;
   std::vector<unsigned char> args;
   unsigned segs = 0;
   size_t shm = 0;
@@ -56,7 +56,7 @@ hipError_t record_task(unsigned kind, const void *args, size_t bytes, unsigned s
   return hipSuccess;
 }
 
-void record_launch(std::function<hipError_t()> launch) {
+void record_launch(std::function<hipError_t(void *)> launch) {
   Entry e;
   e.phase = t_rec->phase++;
   e.launch = std::move(launch);
@@ -78,7 +78,9 @@ void next_op() {
   if (t_rec) t_rec->phase = 0;
 }
 
-hipError_t flush(void *stream, std::vector<Upload> &uploads) {
+hipError_t flush(const Streams &st, std::vector<Upload> &uploads) {
+  void *const stream = st.origin;
+  const bool fan = st.n_branches > 1;
   Recorder *r = t_rec;
   t_rec = nullptr;  // from here on launches and frees are issued at once
   if (!r) return hipSuccess;
@@ -89,8 +91,26 @@ hipError_t flush(void *stream, std::vector<Upload> &uploads) {
   const unsigned wg = rt::thread_wg_per_cu() ? rt::thread_wg_per_cu() : kBatchWgPerCu;
   const uint64_t cap = (uint64_t)rt::cus() * wg;
   for (unsigned ph = 0; ph < phases && e == hipSuccess; ph++) {
+    // the phase's launches (plain ones and one per batched kind) go round-robin over the
+    // branches, which fork from the origin here and join it at the end of the phase
+    unsigned count = 0;
+    std::vector<bool> kinds(BK_COUNT, false);
+    for (const Entry &x : r->entries) {
+      if (x.phase != ph) continue;
+      if (x.kind < 0) count++;
+      else if (!kinds[x.kind]) kinds[x.kind] = true, count++;
+    }
+    const unsigned nb = fan ? std::min(count, st.n_branches) : 1u;  // branches with work in this phase
+    const bool forked = nb > 1;
+    if (forked) {
+      e = hipEventRecord(st.fork, reinterpret_cast<hipStream_t>(stream));
+      for (unsigned b = 0; b < nb && e == hipSuccess; b++)
+        e = hipStreamWaitEvent(reinterpret_cast<hipStream_t>(st.branches[b]), st.fork, 0);
+    }
+    unsigned rr = 0;
+    auto next_stream = [&]() { return forked ? st.branches[rr++ % nb] : stream; };
     for (const Entry &x : r->entries)
-      if (x.phase == ph && x.kind < 0 && e == hipSuccess) e = x.launch();
+      if (x.phase == ph && x.kind < 0 && e == hipSuccess) e = x.launch(next_stream());
     for (unsigned kind = 0; kind < BK_COUNT && e == hipSuccess; kind++) {
       std::vector<const Entry *> tasks;
       for (const Entry &x : r->entries)
@@ -117,25 +137,32 @@ hipError_t flush(void *stream, std::vector<Upload> &uploads) {
         break;
       }
       prefix[n] = (unsigned)total;
-      char *dev = static_cast<char *>(rt::alloc(bytes, stream));
+      void *const ks = next_stream();
+      char *dev = static_cast<char *>(rt::alloc(bytes, ks));
       if (!dev) {
         e = hipErrorOutOfMemory;
         break;
       }
       up.dev = dev;
       if (!arena) {  // eager: copy now, keep the host bytes until the caller synchronises
-        e = hipMemcpyAsync(dev, up.host.data(), off_ticket, hipMemcpyHostToDevice,
-                           reinterpret_cast<hipStream_t>(stream));
+        e = hipMemcpyAsync(dev, up.host.data(), off_ticket, hipMemcpyHostToDevice, reinterpret_cast<hipStream_t>(ks));
         uploads.push_back(std::move(up));
       } else if (!arena->measure) {  // capture: the caller copies once the capture has ended
         uploads.push_back(std::move(up));
       }
       unsigned *ticket = reinterpret_cast<unsigned *>(dev + off_ticket);
-      if (e == hipSuccess) e = launch_fill_u32(ticket, 1, 0u, stream);
+      if (e == hipSuccess) e = launch_fill_u32(ticket, 1, 0u, ks);
       const BatchQueue q{reinterpret_cast<const unsigned *>(dev + off_prefix), (unsigned)n, ticket};
       const unsigned grid = (unsigned)std::max<uint64_t>(1, std::min<uint64_t>(total, cap));
-      if (e == hipSuccess) e = launch_batch(kind, dev, q, grid, shm, stream);
-      rt::free(dev, bytes, stream);
+      if (e == hipSuccess) e = launch_batch(kind, dev, q, grid, shm, ks);
+      rt::free(dev, bytes, ks);
+    }
+    if (forked) {  // always join back (a capture must end joined)
+      for (unsigned b = 0; b < nb; b++) {
+        hipError_t e2 = hipEventRecord(st.join[b], reinterpret_cast<hipStream_t>(st.branches[b]));
+        if (e2 == hipSuccess) e2 = hipStreamWaitEvent(reinterpret_cast<hipStream_t>(stream), st.join[b], 0);
+        if (e == hipSuccess) e = e2;
+      }
     }
   }
   for (const Free &f : r->frees) rt::free(f.p, f.bytes, f.stream);

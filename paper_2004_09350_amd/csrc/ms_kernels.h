@@ -78,15 +78,35 @@ struct FillArgs {
   unsigned long long *p64;
   unsigned long long n, v;
 };
-// Kernels with a batched variant.
+struct MorphArgs {
+  ColView in, out;
+  unsigned auto_w;
+  unsigned *partials;
+};
+struct ProjectArgs {
+  ColView pos, data, out;
+  unsigned auto_w;
+  unsigned *partials;
+};
+struct NarrowArgs {
+  FinishArgs f;
+  unsigned *tmp;
+};
+// Kernels with a batched variant (morph and project: one kind per output kind 0..4).
 enum BatchKind : unsigned {
   BK_PRED0, BK_PRED1, BK_PRED2, BK_EMIT, BK_EMIT_FIX, BK_FINISH, BK_SUM, BK_SUM_FINISH, BK_GROUP_SUM,
-  BK_GROUP_SUM_FINISH, BK_FILL, BK_COUNT
+  BK_GROUP_SUM_FINISH, BK_FILL, BK_NARROW, BK_NARROW_COPY, BK_MORPH0, BK_PROJECT0 = BK_MORPH0 + 5,
+  BK_PROJECT_RLE0 = BK_PROJECT0 + 5, BK_COUNT = BK_PROJECT_RLE0 + 5
 };
 // Launch of kind's batched kernel over tasks (device array of that kind's argument struct).
 hipError_t launch_batch(unsigned kind, const void *tasks, const BatchQueue &q, unsigned grid, size_t shm, void *s);
 hipError_t launch_pred_batch(unsigned mode, const PredArgs *tasks, const BatchQueue &q, unsigned grid, size_t shm,
                              void *s);
+template <unsigned OK>
+hipError_t launch_morph_batch_ok(const MorphArgs *tasks, const BatchQueue &q, unsigned grid, size_t shm, void *s);
+template <unsigned OK>
+hipError_t launch_project_batch_ok(const ProjectArgs *tasks, bool data_rle, const BatchQueue &q, unsigned grid,
+                                   size_t shm, void *s);
 
 hipError_t init_err_word();  // once, at library initialisation (the current device)
 unsigned read_and_clear_err(void *stream);

@@ -83,7 +83,7 @@ __device__ __forceinline__ bool narrow_plan(const FinishArgs &a, unsigned long l
   return Wf <= 32 && Wt < Wf && n_main > 0;
 }
 
-__global__ __launch_bounds__(kWG) void k_narrow(FinishArgs a, unsigned *tmp) {
+__device__ __forceinline__ void narrow_body(const FinishArgs &a, unsigned *tmp, const unsigned seg, const unsigned G) {
   __shared__ __attribute__((aligned(16))) unsigned lds_all[kWaves * kBlk];
   __shared__ unsigned red[kWaves];
   unsigned long long n_main;
@@ -92,8 +92,7 @@ __global__ __launch_bounds__(kWG) void k_narrow(FinishArgs a, unsigned *tmp) {
   const unsigned lane = lane_id(), w = wave_id();
   unsigned *lds = lds_all + w * kBlk;
   const unsigned long long C = (n_main + kBlk - 1) / kBlk;
-  for (unsigned long long c = (unsigned long long)blockIdx.x * kWaves + w; c < C;
-       c += (unsigned long long)gridDim.x * kWaves) {
+  for (unsigned long long c = (unsigned long long)seg * kWaves + w; c < C; c += (unsigned long long)G * kWaves) {
     unsigned v[8];
     unpack8_rt(Wf, a.out.payload + c * 16ull * Wf, lane, v);
     const unsigned long long idx0 = c * kBlk + 8ull * lane;
@@ -103,15 +102,26 @@ __global__ __launch_bounds__(kWG) void k_narrow(FinishArgs a, unsigned *tmp) {
   }
 }
 
-__global__ __launch_bounds__(kWG) void k_narrow_copy(FinishArgs a, const unsigned *tmp) {
+__device__ __forceinline__ void narrow_copy_body(const FinishArgs &a, const unsigned *tmp, const unsigned seg,
+                                                 const unsigned G) {
   __shared__ unsigned red[kWaves];
   unsigned long long n_main;
   unsigned Wf, Wt;
   if (!narrow_plan(a, n_main, Wf, Wt, red)) return;
   const unsigned long long words = n_main * Wt / 32;  // n_main is a multiple of 32
-  for (unsigned long long q = (unsigned long long)blockIdx.x * kWG + threadIdx.x; q < words;
-       q += (unsigned long long)gridDim.x * kWG)
+  for (unsigned long long q = (unsigned long long)seg * kWG + threadIdx.x; q < words; q += (unsigned long long)G * kWG)
     a.out.payload[q] = tmp[q];
+}
+
+__global__ __launch_bounds__(kWG) void k_narrow(FinishArgs a, unsigned *tmp) { narrow_body(a, tmp, blockIdx.x, gridDim.x); }
+__global__ __launch_bounds__(kWG) void k_narrow_copy(FinishArgs a, const unsigned *tmp) {
+  narrow_copy_body(a, tmp, blockIdx.x, gridDim.x);
+}
+__global__ __launch_bounds__(kWG) void k_narrow_batch(const NarrowArgs *tasks, BatchQueue q) {
+  batch_run(tasks, q, [](const NarrowArgs &a, unsigned seg, unsigned G) { narrow_body(a.f, a.tmp, seg, G); });
+}
+__global__ __launch_bounds__(kWG) void k_narrow_copy_batch(const NarrowArgs *tasks, BatchQueue q) {
+  batch_run(tasks, q, [](const NarrowArgs &a, unsigned seg, unsigned G) { narrow_copy_body(a.f, a.tmp, seg, G); });
 }
 
 // ---------------------------------------------------------------------------------------------
@@ -1087,6 +1097,11 @@ hipError_t launch_finish(const FinishArgs &a, void *s) {
   return hipGetLastError();
 }
 hipError_t launch_narrow(const FinishArgs &a, unsigned *tmp, unsigned G, void *s) {
+  if (batch::recording()) {
+    const NarrowArgs na{a, tmp};
+    hipError_t e = batch::record_task(BK_NARROW, &na, sizeof(na), G, 0);
+    return e == hipSuccess ? batch::record_task(BK_NARROW_COPY, &na, sizeof(na), G, 0) : e;
+  }
   MS_LAUNCH(k_narrow, G, kWG, s, a, tmp);
   MS_LAUNCH(k_narrow_copy, G, kWG, s, a, tmp);
   return hipGetLastError();
@@ -1223,7 +1238,33 @@ hipError_t launch_batch(unsigned kind, const void *tasks, const BatchQueue &q, u
       MS_LAUNCH(k_group_sum_finish_batch, grid, kWG, s, static_cast<const GroupSumFinishArgs *>(tasks), q);
       break;
     case BK_FILL: MS_LAUNCH(k_fill_batch, grid, kWG, s, static_cast<const FillArgs *>(tasks), q); break;
-    default: return hipErrorInvalidValue;
+    case BK_NARROW: MS_LAUNCH(k_narrow_batch, grid, kWG, s, static_cast<const NarrowArgs *>(tasks), q); break;
+    case BK_NARROW_COPY: MS_LAUNCH(k_narrow_copy_batch, grid, kWG, s, static_cast<const NarrowArgs *>(tasks), q); break;
+    default: {
+      const unsigned ok = (kind - BK_MORPH0) % 5;
+      const MorphArgs *m = static_cast<const MorphArgs *>(tasks);
+      const ProjectArgs *pj = static_cast<const ProjectArgs *>(tasks);
+      const bool rle = kind >= BK_PROJECT_RLE0;
+      if (kind >= BK_MORPH0 && kind < BK_PROJECT0) {
+        switch (ok) {
+          case UNCOMPR: return launch_morph_batch_ok<UNCOMPR>(m, q, grid, shm, s);
+          case STATIC_BP: return launch_morph_batch_ok<STATIC_BP>(m, q, grid, shm, s);
+          case DYN_BP: return launch_morph_batch_ok<DYN_BP>(m, q, grid, shm, s);
+          case DELTA_DYN_BP: return launch_morph_batch_ok<DELTA_DYN_BP>(m, q, grid, shm, s);
+          default: return launch_morph_batch_ok<FOR_DYN_BP>(m, q, grid, shm, s);
+        }
+      }
+      if (kind >= BK_PROJECT0 && kind < BK_COUNT) {
+        switch (ok) {
+          case UNCOMPR: return launch_project_batch_ok<UNCOMPR>(pj, rle, q, grid, shm, s);
+          case STATIC_BP: return launch_project_batch_ok<STATIC_BP>(pj, rle, q, grid, shm, s);
+          case DYN_BP: return launch_project_batch_ok<DYN_BP>(pj, rle, q, grid, shm, s);
+          case DELTA_DYN_BP: return launch_project_batch_ok<DELTA_DYN_BP>(pj, rle, q, grid, shm, s);
+          default: return launch_project_batch_ok<FOR_DYN_BP>(pj, rle, q, grid, shm, s);
+        }
+      }
+      return hipErrorInvalidValue;
+    }
   }
   return hipGetLastError();
 }

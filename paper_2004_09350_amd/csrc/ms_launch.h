@@ -32,13 +32,13 @@ constexpr unsigned long long kLdsBitmapBits = 32ull * kWaves * kRing * kBlk;
 inline size_t ring_shm(const ColView &c) { return c.kind == RLE ? kRingBytes : 0; }
 
 // While the thread records a batch (ms_batch.h) the launch is held back as a closure over
-// copies of its arguments and issued by the flush.
+// copies of its arguments and issued by the flush, on the stream the flush gives it.
 #define MS_LAUNCH_SHM(name, kern, grid, block, shm, stream, ...)                          \
   do {                                                                                    \
     if (::ms::batch::recording()) {                                                       \
-      ::ms::batch::record_launch([=]() {                                                  \
-        ProfScope ps_(name, stream);                                                      \
-        hipLaunchKernelGGL(kern, dim3(grid), dim3(block), shm, S(stream), __VA_ARGS__);   \
+      ::ms::batch::record_launch([=](void *st_) {                                         \
+        ProfScope ps_(name, st_);                                                         \
+        hipLaunchKernelGGL(kern, dim3(grid), dim3(block), shm, S(st_), __VA_ARGS__);      \
         return hipGetLastError();                                                         \
       });                                                                                 \
     } else {                                                                              \

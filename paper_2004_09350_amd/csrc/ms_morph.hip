@@ -14,19 +14,20 @@ namespace ms {
 // ---------------------------------------------------------------------------------------------
 // Morph (and encode): out = encode_fmt(decode(in)), count known.
 template <unsigned OK>
-__global__ __launch_bounds__(kWG) void k_morph(ColView inv, ColView outv, unsigned auto_w, unsigned *partials) {
+__device__ __forceinline__ void morph_body(const ColView &inv, const ColView &outv, unsigned auto_w, unsigned *partials,
+                                           const unsigned seg, const unsigned G) {
   extern __shared__ __attribute__((aligned(16))) unsigned ring[];  // ring_shm() bytes
   __shared__ __attribute__((aligned(16))) unsigned lds_all[kWaves * kBlk];
   __shared__ unsigned red[kWaves];
   const InCol in = load_in(inv);
-  const unsigned lane = lane_id(), w = wave_id(), G = gridDim.x;
+  const unsigned lane = lane_id(), w = wave_id();
   unsigned Wp = outv.width;
   if (outv.kind == STATIC_BP && auto_w) Wp = bw(inv.hdr->or_all);
   const OutCol o = make_out(outv, in.n, Wp);
-  if (blockIdx.x == 0 && threadIdx.x == 0) outv.hdr->sbp_width = Wp;
+  if (seg == 0 && threadIdx.x == 0) outv.hdr->sbp_width = Wp;
   const unsigned long long C = (in.n + kBlk - 1) / kBlk;
   unsigned long long cb, ce;
-  segment(C, blockIdx.x, G, cb, ce);
+  segment(C, seg, G, cb, ce);
   unsigned or_all = 0, or_main = 0;
   unsigned *lds = lds_all + w * kBlk;
   stream_chunks(in, cb, ce, w, lane, ring + w * kRing * kBlk, inv.hdr, [&](unsigned long long c, const unsigned (&v)[8]) {
@@ -35,9 +36,20 @@ __global__ __launch_bounds__(kWG) void k_morph(ColView inv, ColView outv, unsign
   or_all = wg_or(or_all, red);
   or_main = wg_or(or_main, red);
   if (threadIdx.x == 0) {
-    partials[2 * blockIdx.x] = or_all;
-    partials[2 * blockIdx.x + 1] = or_main;
+    partials[2 * seg] = or_all;
+    partials[2 * seg + 1] = or_main;
   }
+}
+
+template <unsigned OK>
+__global__ __launch_bounds__(kWG) void k_morph(ColView inv, ColView outv, unsigned auto_w, unsigned *partials) {
+  morph_body<OK>(inv, outv, auto_w, partials, blockIdx.x, gridDim.x);
+}
+template <unsigned OK>
+__global__ __launch_bounds__(kWG) void k_morph_batch(const MorphArgs *tasks, BatchQueue q) {
+  batch_run(tasks, q, [](const MorphArgs &a, unsigned seg, unsigned G) {
+    morph_body<OK>(a.in, a.out, a.auto_w, a.partials, seg, G);
+  });
 }
 
 // calc (section 4.2's element-wise arithmetic): out_i = a_i op b_i modulo 2^32 (op 0 add,
@@ -140,7 +152,20 @@ hipError_t launch_morph_ok<MS_OK>(const ColView &in, const ColView &out, unsigne
                                   unsigned *partials, void *s) {
   static const char *const names[] = {"k_morph<UNCOMPR>", "k_morph<STATIC_BP>", "k_morph<DYN_BP>",
                                       "k_morph<DELTA_DYN_BP>", "k_morph<FOR_DYN_BP>"};
+  if (batch::recording()) {
+    const MorphArgs m{in, out, auto_w, partials};
+    return batch::record_task(BK_MORPH0 + MS_OK, &m, sizeof(m), G, ring_shm(in));
+  }
   MS_LAUNCH_SHM(names[MS_OK], k_morph<MS_OK>, G, kWG, ring_shm(in), s, in, out, auto_w, partials);
+  return hipGetLastError();
+}
+
+template <>
+hipError_t launch_morph_batch_ok<MS_OK>(const MorphArgs *tasks, const BatchQueue &q, unsigned grid, size_t shm,
+                                        void *s) {
+  static const char *const names[] = {"k_morph_batch<UNCOMPR>", "k_morph_batch<STATIC_BP>", "k_morph_batch<DYN_BP>",
+                                      "k_morph_batch<DELTA_DYN_BP>", "k_morph_batch<FOR_DYN_BP>"};
+  MS_LAUNCH_SHM(names[MS_OK], k_morph_batch<MS_OK>, grid, kWG, shm, s, tasks, q);
   return hipGetLastError();
 }
 

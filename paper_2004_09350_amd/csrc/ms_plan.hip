@@ -214,9 +214,10 @@ ms_status exec_step(ms_plan *p, size_t i, void *s, std::vector<Result> &r) {
   }
 }
 
-// Batched: level by level on `origin`; the operators of a level (steps whose operands all
-// come from earlier levels) are recorded and issued as batched launches.
-ms_status run_levels(ms_plan *p, hipStream_t origin, std::vector<Result> &r) {
+// Batched: level by level; the operators of a level (steps whose operands all come from
+// earlier levels) are recorded and issued as batched launches on `origin`, their other
+// kernels spread over the branch streams.
+ms_status run_levels(ms_plan *p, hipStream_t origin, std::vector<Result> &r, EventSet &ev) {
   const size_t n = p->steps.size();
   std::vector<uint32_t> level(n, 0);
   uint32_t levels = 0;
@@ -229,6 +230,12 @@ ms_status run_levels(ms_plan *p, hipStream_t origin, std::vector<Result> &r) {
     levels = std::max(levels, level[i] + 1);
   }
   ms_status st = MS_OK;
+  batch::Streams bs;
+  bs.origin = origin;
+  bs.branches = reinterpret_cast<void *const *>(p->br.data());
+  bs.n_branches = p->tune.branches;
+  bs.fork = ev.fork;
+  bs.join = ev.join.data();
   for (uint32_t l = 0; l < levels && st == MS_OK; l++) {
     batch::begin();
     for (size_t i = 0; i < n && st == MS_OK; i++) {
@@ -236,7 +243,7 @@ ms_status run_levels(ms_plan *p, hipStream_t origin, std::vector<Result> &r) {
       batch::next_op();
       st = exec_step(p, i, origin, r);
     }
-    const hipError_t e = batch::flush(origin, p->uploads);  // also after an error: frees run, recording stops
+    const hipError_t e = batch::flush(bs, p->uploads);  // also after an error: frees run, recording stops
     if (st == MS_OK && e != hipSuccess) st = hip_fail(e, "batched launch");
   }
   return st;
@@ -251,7 +258,7 @@ ms_status run_steps(ms_plan *p, hipStream_t origin, std::vector<Result> &r, Even
   ms_status st = MS_OK;
   hipError_t e = hipSuccess;
   if (p->tune.batch) {
-    st = run_levels(p, origin, r);
+    st = run_levels(p, origin, r, ev);
   } else if (B == 1) {
     for (size_t i = 0; i < p->steps.size() && st == MS_OK; i++) st = exec_step(p, i, origin, r);
   } else {
@@ -413,7 +420,6 @@ ms_status ms_plan_set_tune(ms_plan *p, const ms_tune *t) {
   if (t->wg_per_cu > kMaxWgPerCu) return fail(MS_ERR_INVALID_ARG, "wg_per_cu must be 0..32");
   if (t->chunks_per_wg > kMaxChunksPerWg) return fail(MS_ERR_INVALID_ARG, "chunks_per_wg must be 0..64");
   if (t->batch > 1) return fail(MS_ERR_INVALID_ARG, "batch must be 0 or 1");
-  if (t->batch && t->branches != 1) return fail(MS_ERR_INVALID_ARG, "batched launches run on one branch");
   if (t->branches != p->tune.branches || t->wg_per_cu != p->tune.wg_per_cu ||
       t->chunks_per_wg != p->tune.chunks_per_wg || t->batch != p->tune.batch) {
     drop_graph(p);
@@ -606,7 +612,7 @@ ms_status ms_plan_autotune(ms_plan *p, void *stream, uint32_t reps, const char *
   const ms_tune base = bt;
   for (uint32_t c : kChunks)
     if (st == MS_OK) trial(ms_tune{base.branches, base.wg_per_cu, c, 0});
-  if (st == MS_OK) trial(ms_tune{1, bt.wg_per_cu, bt.chunks_per_wg, 1});
+  if (st == MS_OK) trial(ms_tune{bt.branches, bt.wg_per_cu, bt.chunks_per_wg, 1});
   (void)hipEventDestroy(e0);
   (void)hipEventDestroy(e1);
   if (st != MS_OK) return st;

@@ -167,17 +167,19 @@ void policy(const uint32_t kinds[15], const std::vector<ms_column *> &in, hipStr
   inspect_columns(p, st, s);
   CHECK(ms_plan_destroy(p));
   // batched persistent launches level by level: eager, then captured and replayed
-  ms_plan *pb = make(st, in);
-  ms_tune bt{1, best.wg_per_cu, best.chunks_per_wg, 1};
-  CHECK(ms_plan_set_tune(pb, &bt));
-  CHECK(ms_plan_run(pb, s));
-  read_results(pb, st, s);
-  CHECK(ms_plan_run(pb, s));
-  CHECK(ms_plan_launch(pb, s));
-  for (int r = 0; r < 2; r++) CHECK(ms_plan_launch(pb, s));
-  read_results(pb, st, s);
-  inspect_columns(pb, st, s);
-  CHECK(ms_plan_destroy(pb));
+  for (uint32_t b : {1u, 4u}) {  // the plain launches of a phase on one stream, then on four branches
+    ms_plan *pb = make(st, in);
+    ms_tune bt{b, best.wg_per_cu, best.chunks_per_wg, 1};
+    CHECK(ms_plan_set_tune(pb, &bt));
+    CHECK(ms_plan_run(pb, s));
+    read_results(pb, st, s);
+    CHECK(ms_plan_run(pb, s));
+    CHECK(ms_plan_launch(pb, s));
+    for (int r = 0; r < 2; r++) CHECK(ms_plan_launch(pb, s));
+    read_results(pb, st, s);
+    inspect_columns(pb, st, s);
+    CHECK(ms_plan_destroy(pb));
+  }
   // the profiled eager run on one branch
   ms_plan *pr = make(st, in);
   ms_tune one{1, best.wg_per_cu, best.chunks_per_wg};

@@ -13,6 +13,7 @@
 //     either while a replay is queued is a use after free.
 #include <hip/hip_runtime.h>
 
+#include <algorithm>
 #include <cstdio>
 #include <cstdlib>
 #include <cstring>
@@ -164,7 +165,8 @@ hipError_t hipStreamWaitEvent(hipStream_t s, hipEvent_t e, unsigned) {
       s->covers.clear();
       e->graph->joined.insert(s);
     } else {
-      for (hipGraphNode *n : e->nodes) s->last.push_back(n);
+      for (hipGraphNode *n : e->nodes)
+        if (std::find(s->last.begin(), s->last.end(), n) == s->last.end()) s->last.push_back(n);
     }
     auto &c = s->covers[e->stream];
     if (e->seq > c) c = e->seq;

@@ -45,8 +45,8 @@ thread_local bool t_prof_suspended = false;
 template <class F>
 hipError_t issue(void *s, F work) {
   if (batch::recording()) {
-    batch::record_launch([s, work]() {
-      model::submit(S(s), work);
+    batch::record_launch([work](void *st) {  // issued by the flush on the stream it picks
+      model::submit(S(st), work);
       return hipSuccess;
     });
     return hipSuccess;

@@ -159,7 +159,7 @@ namespace batch {
 bool recording() { return false; }
 void begin() {}
 void next_op() {}
-hipError_t flush(void *, std::vector<Upload> &) { return hipSuccess; }
+hipError_t flush(const Streams &, std::vector<Upload> &) { return hipSuccess; }
 }  // namespace batch
 }  // namespace ms
 

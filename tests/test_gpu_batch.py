@@ -118,7 +118,7 @@ def test_mixed_batch_eager_graph_and_branches(M, tmp_path):
     M.sync()
     check(M, plan, expect)
     # batched persistent launches: the plan's three levels, one launch per kernel and phase
-    for tune in ((1, 0, 0, 1), (1, 2, 8, 1)):
+    for tune in ((1, 0, 0, 1), (4, 2, 8, 1)):
         plan.set_tune(*tune)
         plan.run()
         M.sync()

@@ -139,7 +139,7 @@ def test_q3_greedy_runtime_search(M, Q, star):
 
 
 @pytest.mark.parametrize("tune", [(1, 0, 0, 0), (2, 4, 1, 0), (4, 8, 16, 0), (8, 2, 2, 0), (2, 0, 64, 0), (1, 0, 0, 1),
-                                  (1, 8, 2, 1), (1, 2, 16, 1)])
+                                  (1, 8, 2, 1), (4, 2, 16, 1), (8, 0, 1, 1)])
 def test_q3_branches(M, Q, star, tune):
     """Every launch shape, the batched level-by-level launches (batch = 1) included: an
     eager run and graph replays give the oracle's answers and intermediates."""
@@ -176,7 +176,7 @@ def test_autotune_and_cache(M, Q, tmp_path):
     plan = Q.q1_plan(A, B, 103)
     best, ms = plan.autotune(reps=2, cache=cache)
     assert best[0] in (1, 2, 4, 8) and best[1] in (0, 2, 4, 8, 16) and best[2] in (0, 1, 2, 8, 16) and ms > 0
-    assert best[3] in (0, 1) and (best[3] == 0 or best[0] == 1)
+    assert best[3] in (0, 1)
     assert plan.tune() == best
     lines = open(cache).read().split()  # signature, branches, workgroups per CU, chunks per workgroup, batch, ms
     assert len(lines) == 6 and tuple(int(x) for x in lines[1:5]) == best
@@ -209,8 +209,6 @@ def test_plan_errors(M):
         p.set_tune(0, 8)
     with pytest.raises(M.MorphError):
         p.set_tune(1, 0, 65)
-    with pytest.raises(M.MorphError):  # batched launches run on one branch
-        p.set_tune(2, 0, 0, 1)
     with pytest.raises(M.MorphError):
         p.set_tune(1, 0, 0, 2)
     p.run()
