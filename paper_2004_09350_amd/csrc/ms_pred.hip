@@ -383,12 +383,12 @@ __global__ __launch_bounds__(kWG) void k_pred_batch(const PredArgs *tasks, Batch
 
 
 // Semi-join against a bitmap larger than the 256-thread kernel's LDS part: one workgroup of
-// 1024 threads per CU keeps the first kWideLdsBits bits (142 KB) in LDS and probes only
-// the keys above them through the caches.  Its four quarters do exactly the work of four
+// 1024 threads per CU keeps the first kWideLdsBits bits (nearly all of the 160 KB a
+// workgroup may hold) in LDS and probes only the keys above them through the caches.  Its four quarters do exactly the work of four
 // consecutive workgroups of k_pred<1> (segments 4b .. 4b+3 of the same G, four waves each),
 // so the emit phase sees the same segments and counts.  Keys in any format but RLE.
 constexpr unsigned kWideWG = 1024;
-constexpr unsigned kWideLdsWords = 36352;
+constexpr unsigned kWideLdsWords = 40896;
 constexpr unsigned long long kWideLdsBits = 32ull * kWideLdsWords;
 
 __global__ __launch_bounds__(kWideWG) void k_semijoin_wide(PredArgs a, unsigned G) {

@@ -212,7 +212,7 @@ def test_semijoin_and_bitmap(M):
     del rng
 
 
-@pytest.mark.parametrize("D", [2_500, 262_144, 262_145, 1_163_264, 1_163_265, 2_000_000])
+@pytest.mark.parametrize("D", [2_500, 262_144, 262_145, 1_308_672, 1_308_673, 2_000_000])
 def test_semijoin_small_domains(M, D):
     """Bitmaps built from select outputs (recorded as increasing), domains that fit the
     probe's LDS or exceed it (probed partly in LDS), and keys in and out of the domain."""
