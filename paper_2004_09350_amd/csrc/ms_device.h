@@ -82,6 +82,9 @@ struct OpOr {
 struct OpMin {
   __device__ unsigned operator()(unsigned a, unsigned b) const { return a < b ? a : b; }
 };
+struct OpMax {
+  __device__ unsigned operator()(unsigned a, unsigned b) const { return a > b ? a : b; }
+};
 // Reductions, as wave-uniform values.
 template <class Op>
 __device__ __forceinline__ unsigned wave_reduce(unsigned x, unsigned ident, Op op) {
@@ -95,6 +98,7 @@ __device__ __forceinline__ unsigned wave_reduce(unsigned x, unsigned ident, Op o
 __device__ __forceinline__ unsigned wave_or(unsigned x) { return wave_reduce(x, 0u, OpOr()); }
 __device__ __forceinline__ unsigned wave_min(unsigned x) { return wave_reduce(x, 0xFFFFFFFFu, OpMin()); }
 __device__ __forceinline__ unsigned wave_add(unsigned x) { return wave_reduce(x, 0u, OpAdd()); }
+__device__ __forceinline__ unsigned wave_max(unsigned x) { return wave_reduce(x, 0u, OpMax()); }
 __device__ __forceinline__ unsigned long long wave_add64(unsigned long long x) {
 #pragma unroll
   for (int d = 32; d >= 1; d >>= 1) x += __shfl_xor(x, d);
@@ -113,6 +117,23 @@ __device__ __forceinline__ unsigned lane_prev(unsigned x) {
   const unsigned e15 = __builtin_amdgcn_readlane(x, 15), e31 = __builtin_amdgcn_readlane(x, 31);
   const unsigned e47 = __builtin_amdgcn_readlane(x, 47);
   return l == 16 ? e15 : l == 32 ? e31 : l == 48 ? e47 : y;
+}
+// if_set where bit `lane` of the wave-uniform mask w is set, else if_clear: one VALU select
+// whose lane condition is w itself (held in a scalar register pair).
+__device__ __forceinline__ unsigned lane_bit_select(unsigned long long w, unsigned if_set, unsigned if_clear) {
+  unsigned r;
+  asm("v_cndmask_b32_e64 %0, %1, %2, %3" : "=v"(r) : "v"(if_clear), "v"(if_set), "s"(w));
+  return r;
+}
+// Set bits of the wave-uniform mask w in lanes below this one, plus acc.
+__device__ __forceinline__ unsigned lanes_below(unsigned long long w, unsigned acc) {
+  return __builtin_amdgcn_mbcnt_hi((unsigned)(w >> 32), __builtin_amdgcn_mbcnt_lo((unsigned)w, acc));
+}
+// OR of the indices (0..63) of the set bits of w.
+__device__ __forceinline__ unsigned bit_index_or(unsigned long long w) {
+  return ((w & 0xAAAAAAAAAAAAAAAAull) ? 1u : 0u) | ((w & 0xCCCCCCCCCCCCCCCCull) ? 2u : 0u) |
+         ((w & 0xF0F0F0F0F0F0F0F0ull) ? 4u : 0u) | ((w & 0xFF00FF00FF00FF00ull) ? 8u : 0u) |
+         ((w & 0xFFFF0000FFFF0000ull) ? 16u : 0u) | ((w & 0xFFFFFFFF00000000ull) ? 32u : 0u);
 }
 // The value of lane 63 / lane 0, wave-uniform.
 __device__ __forceinline__ unsigned lane_last(unsigned x) { return __builtin_amdgcn_readlane(x, 63); }

@@ -396,9 +396,10 @@ __device__ __forceinline__ void owned_blocks(unsigned long long Ow, unsigned lon
 // in its LDS and packing each block as soon as it is complete.  No workgroup barrier
 // inside the loop.
 constexpr unsigned kEmitRing = 2 * kBlk;
+constexpr unsigned kEmitRingStride = kEmitRing + 64;  // the ring, then one spare word per lane
 
 __device__ __forceinline__ void emit_body(const EmitArgs &a, const unsigned seg, const unsigned G) {
-  __shared__ __attribute__((aligned(16))) unsigned ring_all[kWaves * kEmitRing];
+  __shared__ __attribute__((aligned(16))) unsigned ring_all[kWaves * kEmitRingStride];
   __shared__ __attribute__((aligned(16))) unsigned lds_all[kWaves * kBlk];
   __shared__ unsigned s_wcnt[kWaves];
   __shared__ unsigned long long red[kWaves];
@@ -436,6 +437,13 @@ __device__ __forceinline__ void emit_body(const EmitArgs &a, const unsigned seg,
   unsigned cnt = 0;
   {
     unsigned long long c = cw0;
+    for (; c + 64 <= cw1; c += 64) {  // eight loads in flight
+      unsigned long long x[8];
+#pragma unroll
+      for (int j = 0; j < 8; j++) x[j] = bm64[(c + 8 * j) * 8 + lane];
+#pragma unroll
+      for (int j = 0; j < 8; j++) cnt += __popcll(x[j]);
+    }
     for (; c + 8 <= cw1; c += 8) cnt += __popcll(bm64[c * 8 + lane]);
     for (; c < cw1; c++) cnt += __popc((unsigned)a.bitmask[c * 64 + lane]);
   }
@@ -456,10 +464,62 @@ __device__ __forceinline__ void emit_body(const EmitArgs &a, const unsigned seg,
   // Output indices are below 2^32 (columns hold fewer than 2^32 values): 32-bit from here.
   const unsigned n_main_o = (unsigned)o.n_main, A32 = (unsigned)A, B32 = (unsigned)B, Nb32 = (unsigned)Nb;
   const unsigned cap32 = (unsigned)min(a.out.n_cap, 0xFFFFFFFFull);
-  unsigned *ring = ring_all + w * kEmitRing;
+  unsigned *ring = ring_all + w * kEmitRingStride;
   unsigned *lds = lds_all + w * kBlk;
   unsigned g_done = A32;          // owned outputs below g_done are packed
   unsigned g = (unsigned)Ow;      // next output index of this wave
+  // OR of the positions written by the row-plane fast path, kept as the OR of the planes'
+  // first rows and of their words (wave-uniform): the OR of base + j over the set bits j of
+  // a word is base | (OR of those j), and the OR of the j distributes over words.
+  unsigned or_base = 0;
+  unsigned long long or_words = 0;
+
+  // One output element outside the fast paths: output index gl, value val.
+  auto store_one = [&](unsigned gl, unsigned val) {
+    if (gl < n_main_o) or_main |= val;
+    if (gl >= cap32) {
+      raise_err(E_INVALID);
+    } else if (kind == UNCOMPR) {
+      a.out.payload[gl] = val;
+    } else if (kind == RLE) {
+      a.out.rvalues[gl] = val;
+      a.out.rstarts[gl] = gl;
+    } else if (gl >= Nb32) {
+      a.out.rem[gl - Nb32] = val;           // DynBP-family remainder
+    } else if (gl < A32 || gl >= B32) {
+      a.stage_g[gl] = val;                  // block shared with a neighbouring wave
+    } else {
+      ring[(gl - A32) & (kEmitRing - 1)] = val;
+    }
+  };
+  // Pack every owned block that is complete below output g (the last block of the output
+  // may be partial).
+  auto pack_ready = [&]() {
+    if (!blocky || B32 <= A32) return;
+    const unsigned have_end = min(g, B32);
+    if (g_done >= have_end || (unsigned)blk_end(g_done / kBlk, Nb) > have_end) return;
+    wave_sync();
+    while (g_done < have_end) {
+      const unsigned bend = (unsigned)blk_end(g_done / kBlk, Nb);
+      if (bend > have_end) break;
+      const unsigned len = bend - g_done;
+      const unsigned *src = ring + ((g_done - A32) & (kEmitRing - 1));
+      unsigned x[8];
+      const unsigned l0 = 8u * lane;
+      if (l0 + 8 <= len) {  // two 16-byte reads: no bank conflicts between lanes
+        const uint4 *s4 = reinterpret_cast<const uint4 *>(src + l0);
+        const uint4 p = s4[0], q = s4[1];
+        x[0] = p.x; x[1] = p.y; x[2] = p.z; x[3] = p.w;
+        x[4] = q.x; x[5] = q.y; x[6] = q.z; x[7] = q.w;
+      } else {
+#pragma unroll
+        for (int i = 0; i < 8; i++) x[i] = (l0 + i < len) ? src[l0 + i] : 0u;
+      }
+      encode_out_block(o, g_done / kBlk, x, lane, lds, or_main);
+      g_done = bend;
+    }
+    wave_sync();
+  };
 
   // Emit one unit: lane bits m (bit i = value i, which is pos0 + i, or v[i] when the
   // chunk's values are emitted) in row order across the lanes; at most 512 outputs.
@@ -525,73 +585,119 @@ __device__ __forceinline__ void emit_body(const EmitArgs &a, const unsigned seg,
     while (m) {  // elements outside the fast paths
       const unsigned i = lowest(m);
       m &= m - 1;
-      const unsigned val = value(i);
-      if (gl < n_main_o) or_main |= val;
-      if (gl >= cap32) {
-        raise_err(E_INVALID);
-      } else if (kind == UNCOMPR) {
-        a.out.payload[gl] = val;
-      } else if (kind == RLE) {
-        a.out.rvalues[gl] = val;
-        a.out.rstarts[gl] = gl;
-      } else if (gl >= Nb32) {
-        a.out.rem[gl - Nb32] = val;           // DynBP-family remainder
-      } else if (gl < A32 || gl >= B32) {
-        a.stage_g[gl] = val;                  // block shared with a neighbouring wave
-      } else {
-        ring[(gl - A32) & (kEmitRing - 1)] = val;
-      }
-      gl++;
+      store_one(gl++, value(i));
     }
     g += tot;
-    if (blocky && B32 > A32) {
-      wave_sync();
-      // pack every owned block that is now complete (the last block of the output may be partial)
-      const unsigned have_end = min(g, B32);
-      while (g_done < have_end) {
-        const unsigned bend = (unsigned)blk_end(g_done / kBlk, Nb);
-        if (bend > have_end) break;
-        const unsigned len = bend - g_done;
-        const unsigned *src = ring + ((g_done - A32) & (kEmitRing - 1));
-        unsigned x[8];
-        const unsigned l0 = 8u * lane;
-        if (l0 + 8 <= len) {  // two 16-byte reads: no bank conflicts between lanes
-          const uint4 *s4 = reinterpret_cast<const uint4 *>(src + l0);
-          const uint4 p = s4[0], q = s4[1];
-          x[0] = p.x; x[1] = p.y; x[2] = p.z; x[3] = p.w;
-          x[4] = q.x; x[5] = q.y; x[6] = q.z; x[7] = q.w;
-        } else {
-#pragma unroll
-          for (int i = 0; i < 8; i++) x[i] = (l0 + i < len) ? src[l0 + i] : 0u;
+    pack_ready();
+  };
+
+  // Emit the positions of one row plane per step: a 64-row word wd of the bitmask (rows
+  // base .. base + 63) is spread over the lanes, lane l taking row base + l, and each
+  // selected lane finds its output slot by counting the set bits below it.  No per-lane
+  // loop, so the cost per plane does not depend on how its rows are selected.  nz: the
+  // lanes of m whose word has a set bit, each such lane's word being one plane; tot: the
+  // step's output count.  The checks that place outputs are made once per step where the
+  // whole step lies in one region (owned blocks, or an uncompressed / RLE output).
+  auto emit_planes = [&](unsigned long long m, unsigned long long nz, unsigned row0, unsigned tot) {
+    const unsigned ge = g + tot;
+    if (blocky && cap_ok && g >= A32 && ge <= B32 && ge <= n_main_o) {
+      // owned block elements: selected lanes write the ring, the others their spare word;
+      // a block is packed as soon as it is complete, so at most 575 outputs wait in the ring
+      unsigned k = g - A32;  // ring index of the next output, before wrapping
+      unsigned next_end = (unsigned)blk_end(g_done / kBlk, Nb) - A32;
+      while (nz) {
+        const unsigned i = (unsigned)__ffsll((long long)nz) - 1u;
+        nz &= nz - 1;
+        const unsigned lo = __builtin_amdgcn_readlane((unsigned)m, i);
+        const unsigned hi = __builtin_amdgcn_readlane((unsigned)(m >> 32), i);
+        const unsigned long long wd = ((unsigned long long)hi << 32) | lo;
+        const unsigned base = row0 + 64u * i;
+        ring[lane_bit_select(wd, lanes_below(wd, k) & (kEmitRing - 1), kEmitRing + lane)] = base + lane;
+        or_base |= base;
+        or_words = uni(or_words | wd);
+        k += (unsigned)__popcll(wd);
+        if (k >= next_end) {
+          g = A32 + k;
+          pack_ready();
+          next_end = (unsigned)blk_end(g_done / kBlk, Nb) - A32;
         }
-        encode_out_block(o, g_done / kBlk, x, lane, lds, or_main);
-        g_done = bend;
       }
-      wave_sync();
+      g = ge;
+      return;
+    }
+    if (!blocky && cap_ok) {  // uncompressed or RLE output: the selected lanes store directly
+      while (nz) {
+        const unsigned i = (unsigned)__ffsll((long long)nz) - 1u;
+        nz &= nz - 1;
+        const unsigned lo = __builtin_amdgcn_readlane((unsigned)m, i);
+        const unsigned hi = __builtin_amdgcn_readlane((unsigned)(m >> 32), i);
+        const unsigned long long wd = ((unsigned long long)hi << 32) | lo;
+        const unsigned base = row0 + 64u * i;
+        if (lane_bit_select(wd, 1u, 0u)) {
+          const unsigned gl = lanes_below(wd, g);
+          if (kind == UNCOMPR) {
+            a.out.payload[gl] = base + lane;
+          } else {
+            a.out.rvalues[gl] = base + lane;
+            a.out.rstarts[gl] = gl;
+          }
+        }
+        or_base |= base;
+        or_words = uni(or_words | wd);
+        g += (unsigned)__popcll(wd);
+      }
+      return;
+    }
+    while (nz) {  // anything else: element by element
+      const unsigned i = (unsigned)__ffsll((long long)nz) - 1u;
+      nz &= nz - 1;
+      const unsigned lo = __builtin_amdgcn_readlane((unsigned)m, i);
+      const unsigned hi = __builtin_amdgcn_readlane((unsigned)(m >> 32), i);
+      const unsigned long long wd = ((unsigned long long)hi << 32) | lo;
+      if ((wd >> lane) & 1ull) store_one(lanes_below(wd, g), row0 + 64u * i + lane);
+      g += (unsigned)__popcll(wd);
+      pack_ready();
     }
   };
 
   const unsigned char *bm = a.bitmask + lane;
   const unsigned novals[8] = {0, 0, 0, 0, 0, 0, 0, 0};
   if (!a.emit_values) {
-    // positions: eight chunks at a time while they hold at most one block of outputs,
-    // else chunk by chunk
+    // positions, eight chunks (4096 rows, lane l's word holding rows 64l .. 64l + 63) per
+    // step, loaded three steps ahead (lanes past the wave's chunks read nothing and hold 0).
+    auto load_group = [&](unsigned long long cg) -> unsigned long long {
+      return (cg + (lane >> 3) < cw1) ? bm64[cg * 8 + lane] : 0ull;
+    };
     unsigned long long c = cw0;
-    unsigned long long mnext = (c + 8 <= cw1) ? bm64[c * 8 + lane] : 0ull;
-    for (; c + 8 <= cw1; c += 8) {
-      const unsigned long long m = mnext;
-      mnext = (c + 16 <= cw1) ? bm64[(c + 8) * 8 + lane] : 0ull;
-      const unsigned pc = __popcll(m);
-      const unsigned t_lo = wave_add(lane < 32 ? pc : 0u), t_hi = wave_add(lane < 32 ? 0u : pc);
-      if (t_lo + t_hi == 0) continue;
-      const unsigned pos0 = (unsigned)(c * kBlk) + 64u * lane;
-      if (t_lo + t_hi <= kBlk) {
-        emit_unit(m, pos0, novals, false);
+    unsigned long long q0 = load_group(c), q1 = load_group(c + 8), q2 = load_group(c + 16);
+    for (; c < cw1; c += 8) {
+      const unsigned long long m = q0;
+      q0 = q1;
+      q1 = q2;
+      q2 = load_group(c + 24);
+      const unsigned long long nz = __ballot(m != 0ull);
+      if (nz == 0ull) continue;
+      const unsigned pc = (unsigned)__popcll(m);
+      const unsigned row0 = (unsigned)(c * kBlk);
+      const unsigned pos0 = row0 + 64u * lane;
+      // Costs in cycles of a CU per step, measured on 1e8-row selections: the per-lane
+      // loop about 25 per round (as many rounds as the fullest lane has set bits) plus 100;
+      // a plane about 48, being one serial chain; the paths for denser steps below about
+      // 2000.  Planes pay where selected rows cluster, leaving most 64-row words empty.
+      const unsigned tot = wave_add(pc), planes_cost = 48u * (unsigned)__popcll(nz);
+      if (tot <= kBlk) {
+        if (25u * wave_max(pc) + 100u <= planes_cost) emit_unit(m, pos0, novals, false);
+        else emit_planes(m, nz, row0, tot);
         continue;
       }
-      // denser: the two halves of four chunks (lanes 0..31, 32..63), each alone if it
+      if (planes_cost < 2000u) {
+        emit_planes(m, nz, row0, tot);
+        continue;
+      }
+      // dense: the two halves of four chunks (lanes 0..31, 32..63), each alone if it
       // holds at most a block of outputs, else chunk by chunk with one byte per lane
       // (byte lane & 7 of lane 8k + lane / 8's word)
+      const unsigned t_lo = wave_add(lane < 32 ? pc : 0u), t_hi = tot - t_lo;
       for (unsigned h = 0; h < 2; h++) {
         const unsigned th = h ? t_hi : t_lo;
         if (th == 0) continue;
@@ -608,7 +714,6 @@ __device__ __forceinline__ void emit_body(const EmitArgs &a, const unsigned seg,
         }
       }
     }
-    for (; c < cw1; c++) emit_unit((unsigned)bm[c * 64], (unsigned)(c * kBlk) + 8u * lane, novals, false);
   } else {
     for (unsigned long long c = cw0; c < cw1; c++) {
       unsigned v[8];
@@ -616,7 +721,7 @@ __device__ __forceinline__ void emit_body(const EmitArgs &a, const unsigned seg,
       emit_unit((unsigned)bm[c * 64], (unsigned)(c * kBlk) + 8u * lane, v, true);
     }
   }
-  or_main = wg_or(or_main, redo);
+  or_main = wg_or(or_main | or_base | bit_index_or(or_words), redo);
   if (threadIdx.x == 0) {
     a.partials[2 * seg] = orv;
     a.partials[2 * seg + 1] = or_main;
