@@ -392,21 +392,21 @@ __device__ __forceinline__ void owned_blocks(unsigned long long Ow, unsigned lon
 
 // Compaction phase 2.  Each wave emits a contiguous quarter of its workgroup's chunks on
 // its own: it counts its outputs from the bitmask, learns its output offset through
-// LDS, then streams its chunks, appending outputs of owned blocks to a two-block ring
-// in its LDS and packing each block as soon as it is complete.  No workgroup barrier
+// LDS, then streams its chunks, appending outputs of owned blocks to a four-block ring
+// in its LDS and packing each block as soon as it is complete, in the block's own ring
+// slot (uncompressed and RLE outputs are staged in the ring).  No workgroup barrier
 // inside the loop.
-constexpr unsigned kEmitRing = 2 * kBlk;
+constexpr unsigned kEmitRing = 4 * kBlk;
+constexpr unsigned kEmitUnitMax = kEmitRing - kBlk;   // outputs of one unit: fewer than a block wait in the ring
 constexpr unsigned kEmitRingStride = kEmitRing + 64;  // the ring, then one spare word per lane
 
 __device__ __forceinline__ void emit_body(const EmitArgs &a, const unsigned seg, const unsigned G) {
   __shared__ __attribute__((aligned(16))) unsigned ring_all[kWaves * kEmitRingStride];
-  __shared__ __attribute__((aligned(16))) unsigned lds_all[kWaves * kBlk];
   __shared__ unsigned s_wcnt[kWaves];
   __shared__ unsigned long long red[kWaves];
   __shared__ unsigned redo[kWaves];
-  const InCol in = load_in(a.in);
   const unsigned lane = lane_id(), w = wave_id();
-  const unsigned long long C = (in.n + kBlk - 1) / kBlk;
+  const unsigned long long C = (uni(a.in.hdr->n) + kBlk - 1) / kBlk;  // the phase-1 input's chunks
   unsigned long long cb, ce;
   segment(C, seg, G, cb, ce);
   unsigned long long O, N;
@@ -465,7 +465,6 @@ __device__ __forceinline__ void emit_body(const EmitArgs &a, const unsigned seg,
   const unsigned n_main_o = (unsigned)o.n_main, A32 = (unsigned)A, B32 = (unsigned)B, Nb32 = (unsigned)Nb;
   const unsigned cap32 = (unsigned)min(a.out.n_cap, 0xFFFFFFFFull);
   unsigned *ring = ring_all + w * kEmitRingStride;
-  unsigned *lds = lds_all + w * kBlk;
   unsigned g_done = A32;          // owned outputs below g_done are packed
   unsigned g = (unsigned)Ow;      // next output index of this wave
   // OR of the positions written by the row-plane fast path, kept as the OR of the planes'
@@ -503,7 +502,7 @@ __device__ __forceinline__ void emit_body(const EmitArgs &a, const unsigned seg,
       const unsigned bend = (unsigned)blk_end(g_done / kBlk, Nb);
       if (bend > have_end) break;
       const unsigned len = bend - g_done;
-      const unsigned *src = ring + ((g_done - A32) & (kEmitRing - 1));
+      unsigned *src = ring + ((g_done - A32) & (kEmitRing - 1));
       unsigned x[8];
       const unsigned l0 = 8u * lane;
       if (l0 + 8 <= len) {  // two 16-byte reads: no bank conflicts between lanes
@@ -515,15 +514,17 @@ __device__ __forceinline__ void emit_body(const EmitArgs &a, const unsigned seg,
 #pragma unroll
         for (int i = 0; i < 8; i++) x[i] = (l0 + i < len) ? src[l0 + i] : 0u;
       }
-      encode_out_block(o, g_done / kBlk, x, lane, lds, or_main);
+      wave_sync();  // the block is in registers: its ring slot becomes the packing buffer
+      encode_out_block(o, g_done / kBlk, x, lane, src, or_main);
       g_done = bend;
     }
     wave_sync();
   };
 
   // Emit one unit: lane bits m (bit i = value i, which is pos0 + i, or v[i] when the
-  // chunk's values are emitted) in row order across the lanes; at most 512 outputs.
-  // A chunk's unit has eight bits per lane (unsigned), a group's 64 (unsigned long long).
+  // chunk's values are emitted) in row order across the lanes; at most kEmitUnitMax
+  // outputs.  A chunk's unit has eight bits per lane (unsigned), a group's 64 (unsigned
+  // long long, walked as two 32-bit halves: cheaper bit scans and clears).
   auto emit_unit = [&](auto m, unsigned pos0, const unsigned (&v)[8], bool vals) {
     constexpr bool BYTE = sizeof(m) == 4;
     auto value = [&](unsigned i) { return vals ? select8(v, i) : pos0 + i; };
@@ -546,13 +547,21 @@ __device__ __forceinline__ void emit_body(const EmitArgs &a, const unsigned seg,
         }
         m = 0;
       } else {
-        while (m) {
-          const unsigned i = lowest(m);
-          m &= m - 1;
-          const unsigned val = value(i);
+        unsigned h32 = (unsigned)m;
+        while (h32) {
+          const unsigned val = value((unsigned)__ffs(h32) - 1u);
+          h32 &= h32 - 1u;
           dst_at(k++) = val;
           orl |= val;
         }
+        h32 = (unsigned)(m >> 32);
+        while (h32) {
+          const unsigned val = value((unsigned)__ffs(h32) + 31u);
+          h32 &= h32 - 1u;
+          dst_at(k++) = val;
+          orl |= val;
+        }
+        m = 0;
       }
       return orl;
     };
@@ -569,14 +578,14 @@ __device__ __forceinline__ void emit_body(const EmitArgs &a, const unsigned seg,
       }
     } else if (cap_ok && tot > 0) {
       // uncompressed and RLE outputs: stage the unit's outputs, then coalesced stores
-      auto at = [&](unsigned k) -> unsigned & { return lds[k]; };
+      auto at = [&](unsigned k) -> unsigned & { return ring[k]; };
       or_main |= scatter(at, off);  // n_main = N for these kinds
       wave_sync();
       if (kind == UNCOMPR) {
-        for (unsigned t = lane; t < tot; t += 64) a.out.payload[g + t] = lds[t];
+        for (unsigned t = lane; t < tot; t += 64) a.out.payload[g + t] = ring[t];
       } else {
         for (unsigned t = lane; t < tot; t += 64) {
-          a.out.rvalues[g + t] = lds[t];
+          a.out.rvalues[g + t] = ring[t];
           a.out.rstarts[g + t] = g + t;
         }
       }
@@ -597,10 +606,24 @@ __device__ __forceinline__ void emit_body(const EmitArgs &a, const unsigned seg,
   // loop, so the cost per plane does not depend on how its rows are selected.  nz: the
   // lanes of m whose word has a set bit, each such lane's word being one plane; tot: the
   // step's output count.  The checks that place outputs are made once per step where the
-  // whole step lies in one region (owned blocks, or an uncompressed / RLE output).
+  // whole step lies in one region (owned blocks, or an uncompressed / RLE output), else
+  // per element.
   auto emit_planes = [&](unsigned long long m, unsigned long long nz, unsigned row0, unsigned tot) {
     const unsigned ge = g + tot;
-    if (blocky && cap_ok && g >= A32 && ge <= B32 && ge <= n_main_o) {
+    if (!cap_ok || (blocky && (g < A32 || ge > B32 || ge > n_main_o))) {
+      while (nz) {  // element by element
+        const unsigned i = (unsigned)__ffsll((long long)nz) - 1u;
+        nz &= nz - 1;
+        const unsigned lo = __builtin_amdgcn_readlane((unsigned)m, i);
+        const unsigned hi = __builtin_amdgcn_readlane((unsigned)(m >> 32), i);
+        const unsigned long long wd = ((unsigned long long)hi << 32) | lo;
+        if ((wd >> lane) & 1ull) store_one(lanes_below(wd, g), row0 + 64u * i + lane);
+        g += (unsigned)__popcll(wd);
+        pack_ready();
+      }
+      return;
+    }
+    if (blocky) {
       // owned block elements: selected lanes write the ring, the others their spare word;
       // a block is packed as soon as it is complete, so at most 575 outputs wait in the ring
       unsigned k = g - A32;  // ring index of the next output, before wrapping
@@ -625,38 +648,26 @@ __device__ __forceinline__ void emit_body(const EmitArgs &a, const unsigned seg,
       g = ge;
       return;
     }
-    if (!blocky && cap_ok) {  // uncompressed or RLE output: the selected lanes store directly
-      while (nz) {
-        const unsigned i = (unsigned)__ffsll((long long)nz) - 1u;
-        nz &= nz - 1;
-        const unsigned lo = __builtin_amdgcn_readlane((unsigned)m, i);
-        const unsigned hi = __builtin_amdgcn_readlane((unsigned)(m >> 32), i);
-        const unsigned long long wd = ((unsigned long long)hi << 32) | lo;
-        const unsigned base = row0 + 64u * i;
-        if (lane_bit_select(wd, 1u, 0u)) {
-          const unsigned gl = lanes_below(wd, g);
-          if (kind == UNCOMPR) {
-            a.out.payload[gl] = base + lane;
-          } else {
-            a.out.rvalues[gl] = base + lane;
-            a.out.rstarts[gl] = gl;
-          }
-        }
-        or_base |= base;
-        or_words = uni(or_words | wd);
-        g += (unsigned)__popcll(wd);
-      }
-      return;
-    }
-    while (nz) {  // anything else: element by element
+    // uncompressed or RLE output: the selected lanes store directly
+    while (nz) {
       const unsigned i = (unsigned)__ffsll((long long)nz) - 1u;
       nz &= nz - 1;
       const unsigned lo = __builtin_amdgcn_readlane((unsigned)m, i);
       const unsigned hi = __builtin_amdgcn_readlane((unsigned)(m >> 32), i);
       const unsigned long long wd = ((unsigned long long)hi << 32) | lo;
-      if ((wd >> lane) & 1ull) store_one(lanes_below(wd, g), row0 + 64u * i + lane);
+      const unsigned base = row0 + 64u * i;
+      if (lane_bit_select(wd, 1u, 0u)) {
+        const unsigned gl = lanes_below(wd, g);
+        if (kind == UNCOMPR) {
+          a.out.payload[gl] = base + lane;
+        } else {
+          a.out.rvalues[gl] = base + lane;
+          a.out.rstarts[gl] = gl;
+        }
+      }
+      or_base |= base;
+      or_words = uni(or_words | wd);
       g += (unsigned)__popcll(wd);
-      pack_ready();
     }
   };
 
@@ -682,27 +693,31 @@ __device__ __forceinline__ void emit_body(const EmitArgs &a, const unsigned seg,
       const unsigned pos0 = row0 + 64u * lane;
       // Costs in cycles of a CU per step, measured on 1e8-row selections: the per-lane
       // loop about 25 per round (as many rounds as the fullest lane has set bits) plus 100;
-      // a plane about 48, being one serial chain; the paths for denser steps below about
-      // 2000.  Planes pay where selected rows cluster, leaving most 64-row words empty.
+      // a plane about 48, being one serial chain; chunk by chunk about 250 per chunk.
+      // Planes pay where selected rows cluster, leaving most 64-row words empty.
+      constexpr unsigned kChunkCost = 250;
       const unsigned tot = wave_add(pc), planes_cost = 48u * (unsigned)__popcll(nz);
-      if (tot <= kBlk) {
-        if (25u * wave_max(pc) + 100u <= planes_cost) emit_unit(m, pos0, novals, false);
-        else emit_planes(m, nz, row0, tot);
-        continue;
+      bool whole = false;  // the whole step as one unit of the per-lane loop
+      if (tot <= kEmitUnitMax) {
+        const unsigned loop_cost = 25u * wave_max(pc) + 100u;
+        whole = loop_cost <= planes_cost && loop_cost <= 8u * kChunkCost;
       }
-      if (planes_cost < 2000u) {
+      if (!whole && planes_cost < 8u * kChunkCost) {
         emit_planes(m, nz, row0, tot);
         continue;
       }
-      // dense: the two halves of four chunks (lanes 0..31, 32..63), each alone if it
-      // holds at most a block of outputs, else chunk by chunk with one byte per lane
-      // (byte lane & 7 of lane 8k + lane / 8's word)
-      const unsigned t_lo = wave_add(lane < 32 ? pc : 0u), t_hi = tot - t_lo;
-      for (unsigned h = 0; h < 2; h++) {
+      // else the two halves of four chunks (lanes 0..31, 32..63), each by the per-lane loop
+      // where that is cheaper, else chunk by chunk with one byte per lane (byte lane & 7 of
+      // lane 8k + lane / 8's word); or the whole step as one unit
+      const unsigned t_lo = whole ? tot : wave_add(lane < 32 ? pc : 0u), t_hi = tot - t_lo;
+      for (unsigned h = 0; h < (whole ? 1u : 2u); h++) {
         const unsigned th = h ? t_hi : t_lo;
         if (th == 0) continue;
-        if (th <= kBlk) {
-          emit_unit((lane >> 5) == h ? m : 0ull, pos0, novals, false);
+        // (the fullest of 32 lanes holds about th / 32 + 2.5 sqrt(th / 32) set bits, at
+        // least th / 24 for th <= 768: no reduction where that already costs more)
+        if (whole || (th <= kEmitUnitMax && 25u * (th / 24u) + 100u <= 4u * kChunkCost &&
+                      25u * wave_max((lane >> 5) == h ? pc : 0u) + 100u <= 4u * kChunkCost)) {
+          emit_unit(whole || (lane >> 5) == h ? m : 0ull, pos0, novals, false);
           continue;
         }
         for (unsigned k = 4 * h; k < 4 * h + 4; k++) {
@@ -715,6 +730,7 @@ __device__ __forceinline__ void emit_body(const EmitArgs &a, const unsigned seg,
       }
     }
   } else {
+    const InCol in = load_in(a.in);  // its views only here: fewer scalar registers held above
     for (unsigned long long c = cw0; c < cw1; c++) {
       unsigned v[8];
       decode_chunk(in, c, lane, v);
