@@ -998,11 +998,13 @@ __global__ __launch_bounds__(kWG) void k_bitmap(ColView posv, unsigned long long
   segment(C, blockIdx.x, G, cb, ce);
   bool bad_range = false, bad_order = false;
   // strictly increasing: recorded by the producer, or checked here (a failed check is an error)
-  const bool increasing = uni(posv.hdr->sorted) != 0 || chunk_first != nullptr;
+  const bool recorded = uni(posv.hdr->sorted) != 0;
+  const bool check = chunk_first != nullptr && !recorded;
+  const bool increasing = recorded || check;
   stream_chunks(in, cb, ce, w, lane, ring + w * kRing * kBlk, posv.hdr, [&](unsigned long long c, const unsigned (&v)[8]) {
     const unsigned long long idx0 = c * kBlk + 8ull * lane;
     const unsigned valid = chunk_valid(c, lane, in.n);
-    if (chunk_first) {
+    if (check) {
       const unsigned prev = lane_prev(v[7]);
 #pragma unroll
       for (int i = 0; i < 8; i++) {
@@ -1030,13 +1032,13 @@ __global__ __launch_bounds__(kWG) void k_bitmap(ColView posv, unsigned long long
       const unsigned span = w1 - w0 + 1;
       for (unsigned t = lane; t < span; t += 64) st[t] = 0u;
       wave_sync();
+      // p_last < domain here, and an increasing chunk keeps every position in
+      // [p_first, p_last]: one unsigned compare keeps a disordered one out of the span
+      const unsigned pspan = p_last - p_first;
 #pragma unroll
       for (int i = 0; i < 8; i++) {
         const unsigned p = v[i];
-        if (((valid >> i) & 1u) && p >= p_first && p <= p_last && (unsigned long long)p < domain)
-          atomicOr(&st[(p >> 5) - w0], 1u << (p & 31));
-        else if (((valid >> i) & 1u) && (unsigned long long)p >= domain)
-          bad_range = true;
+        if (((valid >> i) & 1u) && p - p_first <= pspan) atomicOr(&st[(p >> 5) - w0], 1u << (p & 31));
       }
       wave_sync();
       for (unsigned t = lane; t < span; t += 64) {
@@ -1086,9 +1088,10 @@ __global__ void k_bitmap_ends(const unsigned *ends, const unsigned *chunk_first,
                               unsigned *bitmap, ColView posv) {
   const unsigned long long n = posv.hdr->n;
   const unsigned long long C = (n + kBlk - 1) / kBlk;
+  const bool check = chunk_first != nullptr && posv.hdr->sorted == 0;  // as k_bitmap decided
   for (unsigned long long c = (unsigned long long)blockIdx.x * blockDim.x + threadIdx.x; c < C;
        c += (unsigned long long)gridDim.x * blockDim.x) {
-    if (chunk_first && c > 0 && chunk_first[c] <= chunk_last[c - 1]) raise_err(E_NOT_SORTED);
+    if (check && c > 0 && chunk_first[c] <= chunk_last[c - 1]) raise_err(E_NOT_SORTED);
     const uint4 e = reinterpret_cast<const uint4 *>(ends)[c];
     if (e.y) atomicOr(&bitmap[e.x], e.y);
     if (e.w) atomicOr(&bitmap[e.z], e.w);
