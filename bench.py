@@ -213,7 +213,8 @@ class Sweep:
             else:
                 ue = 4 * (pa["n"] + pb["n"] + oi["n"])
                 probe, build = (pa, pb) if pa["n"] <= pb["n"] else (pb, pa)
-                alg = {"k_bitmap": build["footprint"], "k_pred": probe["footprint"], "k_emit": oi["footprint"]}
+                alg = {"k_bitmap": build["footprint"], "k_pred": probe["footprint"],
+                       "k_emit_vals": probe["footprint"] + oi["footprint"]}
             kernels = [r[0] for r in recs]
             alg_k = {}
             for k in set(kernels):
@@ -432,7 +433,8 @@ def plan_account(M, plan, inputs, log=None):
             a, b = inf(s.a), inf(s.b)
             ue_total += 4 * (a["n"] + b["n"] + out["n"])
             probe, build = (a, b) if a["capacity_bytes"] <= b["capacity_bytes"] else (b, a)
-            add("k_bitmap", build["footprint"]); add("k_pred<2>", probe["footprint"]); add("k_emit", out["footprint"])
+            add("k_bitmap", build["footprint"]); add("k_pred<2>", probe["footprint"])
+            add("k_emit_vals", probe["footprint"] + out["footprint"])  # decodes the probe list again
         elif op == M.OP_PROJECT:
             d, p = inf(s.a), inf(s.b)
             sec = sectors_touched(M, col(s.b))

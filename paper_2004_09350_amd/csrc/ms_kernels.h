@@ -94,7 +94,7 @@ struct NarrowArgs {
 };
 // Kernels with a batched variant (morph and project: one kind per output kind 0..4).
 enum BatchKind : unsigned {
-  BK_PRED0, BK_PRED1, BK_PRED2, BK_EMIT, BK_EMIT_FIX, BK_FINISH, BK_SUM, BK_SUM_FINISH, BK_GROUP_SUM,
+  BK_PRED0, BK_PRED1, BK_PRED2, BK_EMIT, BK_EMIT_VALS, BK_EMIT_FIX, BK_FINISH, BK_SUM, BK_SUM_FINISH, BK_GROUP_SUM,
   BK_GROUP_SUM_FINISH, BK_FILL, BK_NARROW, BK_NARROW_COPY, BK_MORPH0, BK_PROJECT0 = BK_MORPH0 + 5,
   BK_PROJECT_RLE0 = BK_PROJECT0 + 5, BK_COUNT = BK_PROJECT_RLE0 + 5
 };

@@ -400,6 +400,8 @@ constexpr unsigned kEmitRing = 4 * kBlk;
 constexpr unsigned kEmitUnitMax = kEmitRing - kBlk;   // outputs of one unit: fewer than a block wait in the ring
 constexpr unsigned kEmitRingStride = kEmitRing + 64;  // the ring, then one spare word per lane
 
+// VALS: the chunk's values are emitted (intersect), else its row positions (select, semi-join).
+template <bool VALS>
 __device__ __forceinline__ void emit_body(const EmitArgs &a, const unsigned seg, const unsigned G) {
   __shared__ __attribute__((aligned(16))) unsigned ring_all[kWaves * kEmitRingStride];
   __shared__ unsigned s_wcnt[kWaves];
@@ -465,6 +467,9 @@ __device__ __forceinline__ void emit_body(const EmitArgs &a, const unsigned seg,
   const unsigned n_main_o = (unsigned)o.n_main, A32 = (unsigned)A, B32 = (unsigned)B, Nb32 = (unsigned)Nb;
   const unsigned cap32 = (unsigned)min(a.out.n_cap, 0xFFFFFFFFull);
   unsigned *ring = ring_all + w * kEmitRingStride;
+  // The value path (units of one chunk: at most 512 outputs) keeps its ring in the lower
+  // half and decodes in the upper half.
+  constexpr unsigned ring_mask = VALS ? kEmitRing / 2 - 1 : kEmitRing - 1;
   unsigned g_done = A32;          // owned outputs below g_done are packed
   unsigned g = (unsigned)Ow;      // next output index of this wave
   // OR of the positions written by the row-plane fast path, kept as the OR of the planes'
@@ -488,7 +493,7 @@ __device__ __forceinline__ void emit_body(const EmitArgs &a, const unsigned seg,
     } else if (gl < A32 || gl >= B32) {
       a.stage_g[gl] = val;                  // block shared with a neighbouring wave
     } else {
-      ring[(gl - A32) & (kEmitRing - 1)] = val;
+      ring[(gl - A32) & ring_mask] = val;
     }
   };
   // Pack every owned block that is complete below output g (the last block of the output
@@ -502,7 +507,7 @@ __device__ __forceinline__ void emit_body(const EmitArgs &a, const unsigned seg,
       const unsigned bend = (unsigned)blk_end(g_done / kBlk, Nb);
       if (bend > have_end) break;
       const unsigned len = bend - g_done;
-      unsigned *src = ring + ((g_done - A32) & (kEmitRing - 1));
+      unsigned *src = ring + ((g_done - A32) & ring_mask);
       unsigned x[8];
       const unsigned l0 = 8u * lane;
       if (l0 + 8 <= len) {  // two 16-byte reads: no bank conflicts between lanes
@@ -573,7 +578,7 @@ __device__ __forceinline__ void emit_body(const EmitArgs &a, const unsigned seg,
     if (blocky) {
       if (cap_ok && gend <= n_main_o && gl >= A32 && gend <= B32) {
         // owned, staged block elements: append to the ring
-        auto at = [&](unsigned k) -> unsigned & { return ring[k & (kEmitRing - 1)]; };
+        auto at = [&](unsigned k) -> unsigned & { return ring[k & ring_mask]; };
         or_main |= scatter(at, gl - A32);
       }
     } else if (cap_ok && tot > 0) {
@@ -673,7 +678,7 @@ __device__ __forceinline__ void emit_body(const EmitArgs &a, const unsigned seg,
 
   const unsigned char *bm = a.bitmask + lane;
   const unsigned novals[8] = {0, 0, 0, 0, 0, 0, 0, 0};
-  if (!a.emit_values) {
+  if constexpr (!VALS) {
     // positions, eight chunks (4096 rows, lane l's word holding rows 64l .. 64l + 63) per
     // step, loaded three steps ahead (lanes past the wave's chunks read nothing and hold 0).
     auto load_group = [&](unsigned long long cg) -> unsigned long long {
@@ -730,11 +735,31 @@ __device__ __forceinline__ void emit_body(const EmitArgs &a, const unsigned seg,
       }
     }
   } else {
+    // values: chunk by chunk, the next chunk's loads (and bitmask byte) issued before this
+    // chunk is finished
     const InCol in = load_in(a.in);  // its views only here: fewer scalar registers held above
-    for (unsigned long long c = cw0; c < cw1; c++) {
-      unsigned v[8];
-      decode_chunk(in, c, lane, v);
-      emit_unit((unsigned)bm[c * 64], (unsigned)(c * kBlk) + 8u * lane, v, true);
+    unsigned *dec = ring + kEmitRing / 2;
+    unsigned long long c = cw0;
+    if (c < cw1) {
+      Raw cur = issue_chunk(in, c, lane);
+      unsigned mb = bm[c * 64];
+      while (true) {
+        const unsigned long long cn = c + 1;
+        const bool more = cn < cw1;
+        Raw nxt;
+        unsigned mbn = 0;
+        if (more) {
+          nxt = issue_chunk(in, cn, lane);
+          mbn = bm[cn * 64];
+        }
+        unsigned v[8];
+        finish_chunk(in, cur, c, lane, dec, v);
+        emit_unit(mb, (unsigned)(c * kBlk) + 8u * lane, v, true);
+        if (!more) break;
+        cur = nxt;
+        mb = mbn;
+        c = cn;
+      }
     }
   }
   or_main = wg_or(or_main | or_base | bit_index_or(or_words), redo);
@@ -744,9 +769,13 @@ __device__ __forceinline__ void emit_body(const EmitArgs &a, const unsigned seg,
   }
 }
 
-__global__ __launch_bounds__(kWG) void k_emit(EmitArgs a) { emit_body(a, blockIdx.x, gridDim.x); }
+__global__ __launch_bounds__(kWG) void k_emit(EmitArgs a) { emit_body<false>(a, blockIdx.x, gridDim.x); }
+__global__ __launch_bounds__(kWG) void k_emit_vals(EmitArgs a) { emit_body<true>(a, blockIdx.x, gridDim.x); }
 __global__ __launch_bounds__(kWG) void k_emit_batch(const EmitArgs *tasks, BatchQueue q) {
-  batch_run(tasks, q, [](const EmitArgs &a, unsigned seg, unsigned G) { emit_body(a, seg, G); });
+  batch_run(tasks, q, [](const EmitArgs &a, unsigned seg, unsigned G) { emit_body<false>(a, seg, G); });
+}
+__global__ __launch_bounds__(kWG) void k_emit_vals_batch(const EmitArgs *tasks, BatchQueue q) {
+  batch_run(tasks, q, [](const EmitArgs &a, unsigned seg, unsigned G) { emit_body<true>(a, seg, G); });
 }
 
 // Compaction phase 3 (block formats): a block that started before a wave's output range
@@ -1290,11 +1319,12 @@ hipError_t launch_emit(const EmitArgs &a, unsigned G, void *s) {
   const unsigned k = a.out.kind;
   const bool fix = k == STATIC_BP || k == DYN_BP || k == DELTA_DYN_BP || k == FOR_DYN_BP;
   if (batch::recording()) {
-    hipError_t e = batch::record_task(BK_EMIT, &a, sizeof(a), G, 0);
+    hipError_t e = batch::record_task(a.emit_values ? BK_EMIT_VALS : BK_EMIT, &a, sizeof(a), G, 0);
     if (e == hipSuccess && fix) e = batch::record_task(BK_EMIT_FIX, &a, sizeof(a), G, 0);
     return e;
   }
-  MS_LAUNCH(k_emit, G, kWG, s, a);
+  if (a.emit_values) MS_LAUNCH(k_emit_vals, G, kWG, s, a);
+  else MS_LAUNCH(k_emit, G, kWG, s, a);
   if (fix) MS_LAUNCH(k_emit_fix, G, kWG, s, a);
   return hipGetLastError();
 }
@@ -1351,6 +1381,7 @@ hipError_t launch_batch(unsigned kind, const void *tasks, const BatchQueue &q, u
     case BK_PRED1:
     case BK_PRED2: return launch_pred_batch(kind - BK_PRED0, static_cast<const PredArgs *>(tasks), q, grid, shm, s);
     case BK_EMIT: MS_LAUNCH(k_emit_batch, grid, kWG, s, static_cast<const EmitArgs *>(tasks), q); break;
+    case BK_EMIT_VALS: MS_LAUNCH(k_emit_vals_batch, grid, kWG, s, static_cast<const EmitArgs *>(tasks), q); break;
     case BK_EMIT_FIX: MS_LAUNCH(k_emit_fix_batch, grid, kWG, s, static_cast<const EmitArgs *>(tasks), q); break;
     case BK_FINISH: MS_LAUNCH(k_finish_batch, grid, kWG, s, static_cast<const FinishArgs *>(tasks), q); break;
     case BK_SUM:
