@@ -57,6 +57,8 @@ def parse():
     ap.add_argument("--no-sweep", action="store_true", help="star: skip the operator/format sweep")
     ap.add_argument("--greedy", action="store_true",
                     help="star: add the greedy runtime search policy (hundreds of full-size plan captures)")
+    ap.add_argument("--star-tune", default=None,
+                    help="star: fixed launch shape 'branches,wg_per_cu,chunks_per_wg,batch' (default: STAR_TUNE)")
     ap.add_argument("--star-autotune", action="store_true",
                     help="star: autotune every policy's plan at full size instead of the fixed launch shape")
     ap.add_argument("--sweep-steps", type=int, default=2)
@@ -563,6 +565,7 @@ def copy_bandwidth(M, torch, log):
 def run_star(args, M, gen, torch, log):
     from paper_2004_09350_amd import datagen, queries, selector
     n = args.rows or 600_000_000
+    star_tune = tuple(int(x) for x in args.star_tune.split(",")) if args.star_tune else STAR_TUNE
     wpath = args.weights or selector.WEIGHTS
     sel = selector.load(wpath)
     wsrc = os.path.relpath(wpath, ROOT)
@@ -632,7 +635,7 @@ def run_star(args, M, gen, torch, log):
                     log(f"  {sname}: {pol} autotune")
                     tune, _ = q.plan.autotune(reps=2, cache=cache)
                 else:
-                    q.plan.set_tune(*STAR_TUNE)
+                    q.plan.set_tune(*star_tune)
                     tune = q.plan.tune()
                 q.plan.launch()
                 torch.cuda.synchronize()
@@ -696,7 +699,7 @@ def run_star(args, M, gen, torch, log):
                runs=results, copy_bandwidth_gbs=copy_bw, source_sha=source_sha(),
                protocol="each timed run preceded by a 2 GiB device write (not timed); HIP events per run",
                launch_shape=("autotuned per plan" if args.star_autotune else
-                             f"fixed {list(STAR_TUNE)} (branches, wg/CU, chunks/wg)"))
+                             f"fixed {list(star_tune)} (branches, wg/CU, chunks/wg, batch)"))
     if not args.no_cpu_baseline:
         res["cpu_baseline"] = cpu_baseline_star(min(n, args.cpu_rows or 40_000_000))
     return res
