@@ -212,10 +212,12 @@ def test_semijoin_and_bitmap(M):
     del rng
 
 
-@pytest.mark.parametrize("D", [2_500, 262_144, 262_145, 1_308_672, 1_308_673, 2_000_000])
+@pytest.mark.parametrize("D", [2_500, 262_144, 262_145, 1_308_672, 1_308_673, 2_000_000, 2_617_344, 3_000_000,
+                               3_926_016, 3_926_017])
 def test_semijoin_small_domains(M, D):
     """Bitmaps built from select outputs (recorded as increasing), domains that fit the
-    probe's LDS or exceed it (probed partly in LDS), and keys in and out of the domain."""
+    probe's LDS or exceed it (probed partly in LDS, the wide kernel's 1 308 672 bits and
+    above), and keys in and out of the domain."""
     dim = datagen.uniform_range(61, D, 0, 100)
     s = O.select(dim, O.LT, 13)
     keys = datagen.uniform_range(62, 2_000_003, 0, D + D // 50)
