@@ -640,6 +640,7 @@ def run_star(args, M, gen, torch, log):
                 q.plan.launch()
                 torch.cuda.synchronize()
                 tg = cold_times(torch, q.plan.launch, args.steps, flush)
+                arena = q.plan.arena_bytes()  # device bytes the graph holds (worst-case output capacities, scratch)
                 o1, o2 = q.results()
                 if not (np.array_equal(o1, ref[0]) and np.array_equal(o2, ref[1])):
                     raise SystemExit(f"star query answers differ under policy {pol}")
@@ -651,7 +652,7 @@ def run_star(args, M, gen, torch, log):
                     graph_ms_mean=round(tgm * 1e3, 3), graph_ms_median=round(float(np.median(tg)) * 1e3, 3),
                     eager_ms_mean=round(float(np.mean(te)) * 1e3, 3),
                     eager_ms_median=round(float(np.median(te)) * 1e3, 3), tune=list(tune),
-                    intermediates_bytes=fp,
+                    intermediates_bytes=fp, arena_bytes=int(arena),
                     base_bytes=(plain_fp if pol == "plain" else base_fp if pol != "greedy" else
                                 sum(c.info()["footprint"] for c in q.plan.inputs)),
                     ue_gbs=round(ue / tgm / 1e9, 1), hbm_frac=round(sum(alg.values()) / tgm / 1e9 / HBM_PEAK_GBS, 4))
