@@ -97,6 +97,34 @@ def test_select_project_morph_multichunk(M, dist):
     M.sync()
 
 
+def test_select_emit_step_forms_multichunk(M):
+    """The emit phase's forms of a 4096-row step, each reached in one column: the per-lane
+    loop over a whole step of 512..1536 outputs (uniform 25 % and 35 %), the two halves or
+    chunk by chunk (uniform 40 %), row planes and halves of different density (a column
+    whose density alternates between 70 % and 15 % every 4096 rows, so that steps straddle
+    the change at every offset), into every output format."""
+    u = datagen.uniform_bits(8500, N, 12)
+    i = np.arange(N, dtype=np.int64)
+    alt = np.where((i // 4096) % 2 == 0, u % 1429, u + 400).astype(np.uint32)  # v < 1000: 70 % / 15 %
+    cols = [M.encode(u, M.fmt(M.STATIC_BP)), M.encode(alt, M.fmt(M.STATIC_BP))]
+    cases = [(0, 1024), (0, 1434), (0, 1638), (1, 1000)]
+    steps, expect = [], []
+    for j, c in cases:
+        for kout in O.KINDS:
+            steps.append(M.step(M.OP_SELECT, a=M.inp(j), cmp=M.LT, c0=c, out=M.fmt(kout)))
+            expect.append((j, c, kout))
+    plan = run_plan(M, steps, cols)
+    vals = (u, alt)
+    want = {(j, c): O.select(vals[j], O.LT, c) for j, c in cases}
+    for k, (j, c, kout) in enumerate(expect):
+        try:
+            assert_column(plan.column(k), want[(j, c)], kout)
+        except AssertionError as e:
+            raise AssertionError(f"select column {j} v<{c} -> {kout}: {e}") from None
+    plan.close()
+    M.sync()
+
+
 @pytest.mark.parametrize("D", [200_000, 3_000_000])
 def test_semijoin_multichunk(M, D):
     """dimension select -> bitmap -> semi-join of keys stored in every format, into
